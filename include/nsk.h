@@ -1,0 +1,236 @@
+/*
+ * nsk.h -- C ABI of the sketch-and-solve null-space library for AMD MI355X (gfx950).
+ *
+ * The library computes the trailing k right singular vectors of a tall-skinny m x N
+ * matrix A (the null space problem, Problem 2.1 of Park & Nakatsukasa, "A Fast
+ * Randomized Algorithm for Computing an Approximate Null Space") by Algorithm 1:
+ * draw a random sketching matrix S (s x m, N < s <= m), form SA reading A once, take the
+ * SVD of the small s x N matrix SA and return V(:, N-k+1:N).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are row-major.  A matrix operand is a list of column blocks (nsk_operand),
+ *   so [A | b] of Section 4 is passed as two blocks without a concatenated copy.
+ * - Device pointers are HIP device memory owned by the caller.  The library allocates
+ *   nothing in the calls below: scratch comes from the caller's workspace, sized by the
+ *   matching *_workspace_bytes query.  Host pointers are marked "host".
+ * - `stream` is a hipStream_t passed as void*.  Device entry points only enqueue work on
+ *   it and return; outputs (including nsk_info) are valid after the stream has drained.
+ * - Every entry point returns an nsk_status; no exceptions cross the ABI.  Argument
+ *   errors are detected on the host before anything is enqueued.  NaN and Inf inputs are
+ *   not checked: they propagate to the outputs.
+ * - The realisation of S is a pure function of (kind, m, s, zeta, seed): S is regenerated
+ *   from Philox4x32-10 counters wherever it is applied and is never stored.
+ */
+#ifndef NSK_H
+#define NSK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nsk_status {
+  NSK_OK = 0,
+  NSK_EINVAL = 1,        /* an argument violates the constraints stated below            */
+  NSK_EWORKSPACE = 2,    /* workspace (or TLS state) smaller than the size query returns */
+  NSK_ENOCONV = 3,       /* Jacobi did not converge in max_sweeps; outputs still written  */
+  NSK_EDEVICE = 4,       /* a HIP runtime call failed (launch or copy)                   */
+  NSK_EUNSUPPORTED = 5   /* valid arguments, but this kind/dtype combination is not built */
+} nsk_status;
+
+/* Sketch kinds (Section 2 of the paper). */
+typedef enum nsk_kind {
+  NSK_SRHT = 0,          /* subsampled randomized Hadamard transform: the SRFT of Section 2
+                            with the Walsh-Hadamard transform as trig transform,
+                            S = sqrt(m_p/s) R (H/sqrt(m_p)) D on A zero-padded to
+                            m_p = 2^ceil(log2 m) rows; entries +-1/sqrt(s)                  */
+  NSK_SPARSE_SIGN = 1,   /* zeta distinct nonzeros +-1/sqrt(zeta) per column of S
+                            (the CountSketch family mentioned in Section 2)                 */
+  NSK_GAUSSIAN = 2       /* S = G_hat/sqrt(s), G i.i.d. N(0,1) (Section 2) rounded to the
+                            operand format of A (bf16 or e4m3) and applied on MFMA          */
+} nsk_kind;
+
+typedef enum nsk_dtype {
+  NSK_F64 = 0, NSK_F32 = 1, NSK_BF16 = 2, NSK_F8E4M3 = 3
+} nsk_dtype;
+
+#define NSK_FLAG_RESIDUAL 1   /* nsk_trailing_rsv also writes |A V_k|_F to info->residual */
+
+/* Method parameters. Zero fields take the documented defaults. */
+typedef struct nsk_desc {
+  int32_t kind;        /* nsk_kind                                                         */
+  int32_t zeta;        /* NSK_SPARSE_SIGN: nonzeros per column of S, 1 <= zeta <= min(s,32);
+                          0 selects 8                                                       */
+  int64_t s;           /* sketch size; N < s <= m (Algorithm 1 requires s > n; s <= m)      */
+  uint64_t seed;       /* Philox key of the realisation                                     */
+  int32_t acc;         /* NSK_SRHT / NSK_SPARSE_SIGN arithmetic: NSK_F64 (default, FP32 or
+                          FP64 loads with FP64 accumulation) or NSK_F32 (plain FP32)        */
+  int32_t max_sweeps;  /* Jacobi sweep cap, 0 selects 30                                     */
+  int32_t row_groups;  /* number of row partitions of the sketch (partial sums); 0 = tuned */
+  int32_t flags;       /* NSK_FLAG_*                                                         */
+} nsk_desc;
+
+/* One column block of a row-major matrix operand. */
+typedef struct nsk_operand {
+  const void* ptr;        /* device pointer to element (0,0) of the block                   */
+  int32_t dtype;          /* nsk_dtype of the elements                                       */
+  int32_t reserved;       /* must be 0                                                       */
+  int64_t cols;           /* number of columns, >= 1                                         */
+  int64_t ld;             /* row stride in elements, >= cols                                 */
+  const int8_t* col_exp;  /* NSK_F8E4M3 only, nullable: device array of per-column binary
+                             exponents e_c; the logical entry is stored * 2^e_c             */
+} nsk_operand;
+
+/* Diagnostics written by the device (pass a device pointer, or NULL). */
+typedef struct nsk_info {
+  int32_t sweeps;      /* Jacobi sweeps performed                                            */
+  int32_t converged;   /* 1 if every column pair met |x_p.x_q| <= N u |x_p||x_q|            */
+  double off;          /* largest relative column cosine seen in the last sweep              */
+  double residual;     /* |A V_k|_F (FP64 accumulation) when NSK_FLAG_RESIDUAL was set       */
+  double sigma_max;    /* largest singular value of SA                                       */
+} nsk_info;
+
+const char* nsk_status_str(int status);
+int nsk_version(void);
+
+/*
+ * Workspace bytes for nsk_sketch / nsk_trailing_rsv / nsk_residual / nsk_tls_solve on an
+ * m x N operand with sketch size d->s and k trailing vectors. Returns 0 on invalid input.
+ */
+size_t nsk_workspace_bytes(int64_t m, int64_t N, int64_t k, const nsk_desc* d);
+
+/*
+ * Line 2 of Algorithm 1: SA = S A.
+ * blocks/nblocks (host array, 1..4 blocks): the m x N operand, N = sum of block columns.
+ *   SRHT and sparse sign take NSK_F32 or NSK_F64 blocks; Gaussian takes NSK_BF16 or
+ *   NSK_F8E4M3 blocks (all blocks of one dtype).
+ * SA (device): s x N row-major FP64 output with row stride ldsa >= N.
+ * Errors: NSK_EINVAL if m < N, s <= N, s > m, a block has cols < 1 or ld < cols, nblocks
+ *   outside 1..4, zeta outside 1..min(s,32); NSK_EUNSUPPORTED for other dtype/kind pairs;
+ *   NSK_EWORKSPACE if ws_bytes < nsk_workspace_bytes(m, N, 1, d).
+ */
+int nsk_sketch(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_desc* d,
+               double* SA, int64_t ldsa, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Algorithm 1: trailing k right singular vectors of A through the sketch.
+ * SA is reduced by Householder QR (FP64) to R (N x N); R is diagonalised by one-sided
+ * Jacobi (FP64) with cyclic round-robin pair order and tolerance N*u; singular values
+ * are sorted non-increasing (Section 3 ordering) and W = V(:, N-k+1:N) is returned.
+ * Vk (device): N x k row-major FP64; column j belongs to sigma_{N-k+1+j}; each column is
+ *   sign-normalised so that its entry of largest magnitude (lowest index on ties) > 0.
+ * sigma_k (device): k FP64 values sigma_{N-k+1..N}, non-increasing.
+ * info (device, nullable): nsk_info.  With NSK_FLAG_RESIDUAL, info->residual = |A Vk|_F.
+ * Errors: as nsk_sketch, plus NSK_EINVAL if k < 1 or k > N or N > 1024; NSK_ENOCONV is
+ *   reported through info->converged (the call itself cannot wait for the device).
+ */
+int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int64_t k,
+                     const nsk_desc* d, double* Vk, double* sigma_k, nsk_info* info,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Residual |A Vk|_F of Problem 2.1 with FP64 accumulation (one more read of A).
+ * Vk (device): N x k row-major FP64.  out (device): one FP64 value.
+ * NSK_EUNSUPPORTED if N * k > 16384 (V_k is staged in LDS); the same limit applies to
+ * NSK_FLAG_RESIDUAL in nsk_trailing_rsv.
+ */
+int nsk_residual(const nsk_operand* blocks, int32_t nblocks, int64_t m, const double* Vk,
+                 int64_t k, double* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Batched Algorithm 1: `count` independent problems in one persistent launch.  Each
+ * workgroup takes sketch tiles from a longest-first queue; the workgroup that completes
+ * an instance's last tile reduces its partial sketches and runs its QR + Jacobi.
+ * probs (host array): per-instance operand (single block), sizes, sketch size, seed, k
+ *   and device output pointers.  base: kind (NSK_SRHT or NSK_SPARSE_SIGN), zeta, acc,
+ *   max_sweeps; its s and seed are ignored.  Tile sizes come from the autotuner.
+ */
+typedef struct nsk_problem {
+  const void* A;        /* device, row-major m x n, NSK_F32 or NSK_F64                     */
+  int32_t dtype;
+  int32_t reserved;
+  int64_t m, n, ld;
+  int64_t k;            /* 1 <= k <= n                                                     */
+  int64_t s;            /* n < s <= m                                                      */
+  uint64_t seed;
+  double* Vk;           /* device n x k                                                    */
+  double* sigma_k;      /* device k                                                        */
+  nsk_info* info;       /* device, nullable                                                */
+} nsk_problem;
+
+size_t nsk_batched_workspace_bytes(const nsk_problem* probs, int32_t count,
+                                   const nsk_desc* base);
+int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_desc* base,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Autotuner of the batched launch: the tile height ("rows per tile", in 1024-row transform
+ * blocks) is chosen per n-bucket (32 columns wide) by timing the candidates 2..64 on up to
+ * `per_bucket` of the caller's instances with HIP events (host-blocking; overwrites those
+ * instances' outputs; skips candidates whose workspace exceeds ws_bytes).  Results are kept
+ * per process and, when the environment variable NSK_TUNE_CACHE names a file, persisted
+ * there as text and reloaded by later processes.  nsk_tune_lookup returns the value in use
+ * for an n (tuned, cached, or the default ~ n/16); nsk_tune_set overrides one entry;
+ * nsk_tune_clear empties the table.
+ */
+int nsk_autotune_batched(const nsk_problem* probs, int32_t count, const nsk_desc* base, void* ws,
+                         size_t ws_bytes, void* stream, int32_t per_bucket);
+int nsk_tune_lookup(int n, int dtype, int acc);
+int nsk_tune_set(int n, int dtype, int acc, int rows_per_tile);
+int nsk_tune_clear(void);
+
+/*
+ * Total least squares with one right-hand side (Section 4, Golub-Van Loan): the trailing
+ * right singular vector v of the sketched [A | b] (N = n + 1 columns) gives
+ * x = -v(1:n) / v(N).  `state` (device, nsk_tls_state_bytes(n, s) bytes) receives what
+ * the backward pass needs: SA, the full V and sigma of SA, v and x.
+ * x (device): n FP64.
+ */
+size_t nsk_tls_state_bytes(int64_t n, int64_t s);
+int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_desc* d,
+                  double* x, void* state, size_t state_bytes, nsk_info* info, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/*
+ * Gradient of a loss L(x) with respect to [A | b] through the sketched TLS solution.
+ * d, m, n: the same descriptor and sizes as the nsk_tls_solve call that filled `state`.
+ * gx (device, n FP64): dL/dx.  With g_bar = dL/dv = -(1/v_N)[gx; gx.x],
+ * w = sum_{j<N} v_j (v_j.g_bar) / (sigma_N^2 - sigma_j^2) (first-order perturbation of
+ * the trailing right singular vector of SA), p = S^T (SA v), q = S^T (SA w) with S
+ * regenerated from the seed, the gradient is the rank-2 matrix p w^T + q v^T:
+ * dA (device, m x n, row stride ldda >= n) = its first n columns, db (device, m) the last.
+ * out_dtype: NSK_F32 or NSK_F64 for dA and db.  Built for NSK_SPARSE_SIGN and NSK_SRHT;
+ * NSK_GAUSSIAN returns NSK_EUNSUPPORTED.  A degenerate gap (sigma_N = sigma_j) gives
+ * non-finite output: the TLS solution is then not differentiable.
+ */
+int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state, const double* gx,
+                     void* dA, int64_t ldda, void* db, int32_t out_dtype, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/*
+ * Draw hooks: the random objects behind S, bit-exact between host and device.
+ * Philox4x32-10 block with counter (lo32(idx), hi32(idx), sub, stream) and key
+ * (lo32(seed), hi32(seed)); streams: 1 signs, 2 SRHT rows, 3 sparse rows, 4 sparse
+ * signs, 5 Gaussian entries.
+ */
+int nsk_philox(uint64_t seed, uint64_t idx, uint32_t sub, uint32_t stream,
+               uint32_t out[4]);                                        /* host           */
+int nsk_draw_signs(uint64_t seed, int64_t m, int8_t* d);                 /* host, +-1      */
+int nsk_draw_srht_rows(uint64_t seed, int64_t m, int64_t s, int64_t* rows);  /* host, sorted */
+int nsk_draw_sparse(uint64_t seed, int64_t m, int64_t s, int32_t zeta, int32_t* rows,
+                    int8_t* signs);                                      /* host, m x zeta */
+int nsk_draw_signs_device(uint64_t seed, int64_t m, int8_t* d, void* stream);
+int nsk_draw_sparse_device(uint64_t seed, int64_t m, int64_t s, int32_t zeta, int32_t* rows,
+                           int8_t* signs, void* stream);
+/* G (device): s x (j1 - j0) row-major FP32, entries G_hat[i, j0 + c] rounded to dtype
+ * (NSK_BF16 or NSK_F8E4M3; NSK_F32 leaves the FP32 Box-Muller value unrounded). */
+int nsk_draw_gaussian_device(uint64_t seed, int64_t s, int64_t j0, int64_t j1, int32_t dtype,
+                             float* G, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSK_H */

@@ -1,0 +1,398 @@
+"""Sketch-and-solve null space on MI355X: Python binding of ``libnsk.so``.
+
+Argument marshalling only: every computation runs in the HIP library behind the C ABI
+declared in ``include/nsk.h`` (same names without the ``nsk_`` prefix).  PyTorch supplies
+device memory (tensors and workspaces from its caching allocator) and the current HIP
+stream.  There is no CPU fallback: if the library is not built, :func:`load` raises.
+
+Main entry points
+-----------------
+* :func:`sketch`                  -- ``SA = S A`` (line 2 of Algorithm 1).
+* :func:`trailing_rsv`            -- Algorithm 1: trailing k right singular vectors.
+* :func:`residual`                -- ``|A V_k|_F`` with FP64 accumulation.
+* :func:`trailing_rsv_batched`    -- many instances in one persistent launch.
+* :func:`tls_solve`, :class:`TLSSketch` -- sketched total least squares and its gradient.
+* draw hooks (:func:`philox`, :func:`draw_signs`, ...) for bit-exact checks.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnsk.so")
+
+SRHT, SPARSE_SIGN, GAUSSIAN = 0, 1, 2
+F64, F32, BF16, F8E4M3 = 0, 1, 2, 3
+FLAG_RESIDUAL = 1
+KINDS = {"srht": SRHT, "sparse": SPARSE_SIGN, "gauss": GAUSSIAN}
+STATUS = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "Jacobi did not converge",
+          4: "HIP runtime error", 5: "unsupported kind/dtype combination"}
+
+_TORCH_DT = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16,
+             torch.float8_e4m3fn: F8E4M3}
+
+
+class NskError(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("zeta", ctypes.c_int32), ("s", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("acc", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("row_groups", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Operand(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("cols", ctypes.c_int64), ("ld", ctypes.c_int64), ("col_exp", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32), ("off", ctypes.c_double),
+                ("residual", ctypes.c_double), ("sigma_max", ctypes.c_double)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("s", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("Vk", ctypes.c_void_p), ("sigma_k", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
+INFO_BYTES = ctypes.sizeof(Info)
+_lib = None
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "nsk_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "nsk_version": (ctypes.c_int, []),
+    "nsk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(Desc)]),
+    "nsk_sketch": (ctypes.c_int, [ctypes.POINTER(Operand), ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(Desc),
+                                  _P, ctypes.c_int64, _P, ctypes.c_size_t, _P]),
+    "nsk_trailing_rsv": (ctypes.c_int, [ctypes.POINTER(Operand), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.POINTER(Desc), _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "nsk_residual": (ctypes.c_int, [ctypes.POINTER(Operand), ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
+                                    _P, _P, ctypes.c_size_t, _P]),
+    "nsk_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.POINTER(Desc)]),
+    "nsk_trailing_rsv_batched": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.POINTER(Desc), _P,
+                                                ctypes.c_size_t, _P]),
+    "nsk_autotune_batched": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.POINTER(Desc), _P,
+                                            ctypes.c_size_t, _P, ctypes.c_int32]),
+    "nsk_tune_lookup": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "nsk_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "nsk_tune_clear": (ctypes.c_int, []),
+    "nsk_tls_state_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64]),
+    "nsk_tls_solve": (ctypes.c_int, [ctypes.POINTER(Operand), ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(Desc),
+                                     _P, _P, ctypes.c_size_t, _P, _P, ctypes.c_size_t, _P]),
+    "nsk_tls_backward": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.c_int64, ctypes.c_int64, _P, _P, _P,
+                                        ctypes.c_int64, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "nsk_philox": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.POINTER(ctypes.c_uint32)]),
+    "nsk_draw_signs": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, _P]),
+    "nsk_draw_srht_rows": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
+    "nsk_draw_sparse": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P, _P]),
+    "nsk_draw_signs_device": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, _P, _P]),
+    "nsk_draw_sparse_device": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P,
+                                              _P, _P]),
+    "nsk_draw_gaussian_device": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.c_int32, _P, _P]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def load(path: str = LIB_PATH):
+    """Load ``libnsk.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libnsk.so not built at {path}: run `python -m paper_2206_00975_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise NskError(fn, rc)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_desc(kind="srht", s=0, seed=0, zeta=8, acc="f64", max_sweeps=0, row_groups=0, flags=0) -> Desc:
+    kind_id = KINDS[kind] if isinstance(kind, str) else int(kind)
+    acc_id = {"f64": F64, "f32": F32}[acc] if isinstance(acc, str) else int(acc)
+    return Desc(kind_id, int(zeta), int(s), int(seed) & 0xFFFFFFFFFFFFFFFF, acc_id, int(max_sweeps),
+                int(row_groups), int(flags))
+
+
+def _blocks(A):
+    """Column blocks of a row-major operand: a tensor or a list of tensors (same rows/dtype)."""
+    mats = list(A) if isinstance(A, (list, tuple)) else [A]
+    ops = (Operand * len(mats))()
+    m = None
+    keep = []
+    for i, t in enumerate(mats):
+        exp = None
+        if isinstance(t, tuple):          # (fp8 tensor, int8 column exponents)
+            t, exp = t
+        if t.dim() == 1:
+            t = t.unsqueeze(1)
+        if t.stride(1) != 1:
+            raise ValueError("operand blocks must be row-major with unit column stride")
+        if m is None:
+            m = t.shape[0]
+        elif t.shape[0] != m:
+            raise ValueError("column blocks must have the same number of rows")
+        ops[i] = Operand(t.data_ptr(), _TORCH_DT[t.dtype], 0, t.shape[1], t.stride(0),
+                         exp.data_ptr() if exp is not None else None)
+        keep.append((t, exp))
+    return ops, len(mats), m, sum(t.shape[1] for t, _ in keep), keep[0][0].device, keep
+
+
+def workspace_bytes(m, N, k, desc: Desc) -> int:
+    return int(load().nsk_workspace_bytes(m, N, k, ctypes.byref(desc)))
+
+
+def _ws(nbytes, device):
+    if nbytes == 0:
+        raise NskError("workspace_bytes", 1)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def sketch(A, kind="srht", s=None, seed=0, zeta=8, acc="f64", row_groups=0):
+    """``SA = S A`` as an s x N FP64 tensor on A's device."""
+    lib = load()
+    ops, nb, m, N, dev, keep = _blocks(A)
+    d = make_desc(kind, s, seed, zeta, acc, row_groups=row_groups)
+    ws = _ws(lib.nsk_workspace_bytes(m, N, 1, ctypes.byref(d)), dev)
+    SA = torch.empty((s, N), dtype=torch.float64, device=dev)
+    _check("nsk_sketch", lib.nsk_sketch(ops, nb, m, ctypes.byref(d), SA.data_ptr(), N, ws.data_ptr(),
+                                        ws.numel(), _stream(dev)))
+    return SA
+
+
+@dataclass
+class SolveInfo:
+    sweeps: int
+    converged: bool
+    off: float
+    residual: float
+    sigma_max: float
+
+
+def read_info(t: torch.Tensor) -> SolveInfo:
+    raw = bytes(t.cpu().numpy().tobytes())
+    i = Info.from_buffer_copy(raw)
+    return SolveInfo(i.sweeps, bool(i.converged), i.off, i.residual, i.sigma_max)
+
+
+def trailing_rsv(A, k=1, kind="srht", s=None, seed=0, zeta=8, acc="f64", max_sweeps=0, residual=False,
+                 row_groups=0, ws=None, out=None):
+    """Algorithm 1.  Returns ``(Vk, sigma_k, info_tensor)``: Vk is N x k FP64, sigma_k k FP64,
+    info a raw device buffer (decode with :func:`read_info` after synchronising)."""
+    lib = load()
+    ops, nb, m, N, dev, keep = _blocks(A)
+    d = make_desc(kind, s, seed, zeta, acc, max_sweeps, row_groups, FLAG_RESIDUAL if residual else 0)
+    need = lib.nsk_workspace_bytes(m, N, k, ctypes.byref(d))
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    if out is None:
+        Vk = torch.empty((N, k), dtype=torch.float64, device=dev)
+        sig = torch.empty(k, dtype=torch.float64, device=dev)
+        info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    else:
+        Vk, sig, info = out
+    _check("nsk_trailing_rsv", lib.nsk_trailing_rsv(ops, nb, m, k, ctypes.byref(d), Vk.data_ptr(), sig.data_ptr(),
+                                                    info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)))
+    return Vk, sig, info
+
+
+def residual(A, Vk):
+    """``|A Vk|_F`` (FP64 accumulation) as a 0-d FP64 tensor."""
+    lib = load()
+    ops, nb, m, N, dev, keep = _blocks(A)
+    Vk = Vk.to(torch.float64).contiguous()
+    out = torch.empty((), dtype=torch.float64, device=dev)
+    ws = _ws(1024 * 8, dev)
+    _check("nsk_residual", lib.nsk_residual(ops, nb, m, Vk.data_ptr(), Vk.shape[1], out.data_ptr(), ws.data_ptr(),
+                                            ws.numel(), _stream(dev)))
+    return out
+
+
+def _problems(As, ks, ss, seeds):
+    n = len(As)
+    probs = (Problem * n)()
+    outs = []
+    for i, A in enumerate(As):
+        if A.stride(1) != 1:
+            raise ValueError("instances must be row-major")
+        m, N = A.shape
+        Vk = torch.empty((N, ks[i]), dtype=torch.float64, device=A.device)
+        sig = torch.empty(ks[i], dtype=torch.float64, device=A.device)
+        info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+        probs[i] = Problem(A.data_ptr(), _TORCH_DT[A.dtype], 0, m, N, A.stride(0), ks[i], ss[i],
+                           int(seeds[i]) & 0xFFFFFFFFFFFFFFFF, Vk.data_ptr(), sig.data_ptr(), info.data_ptr())
+        outs.append((Vk, sig, info))
+    return probs, outs
+
+
+def trailing_rsv_batched(As, ks, ss, seeds, kind="srht", acc="f64", max_sweeps=0, autotune=False, ws=None):
+    """Batched Algorithm 1 over a list of row-major instances.  Returns a list of
+    ``(Vk, sigma_k, info_tensor)`` per instance."""
+    lib = load()
+    dev = As[0].device
+    probs, outs = _problems(As, ks, ss, seeds)
+    d = make_desc(kind, 0, 0, 8, acc, max_sweeps)
+    need = lib.nsk_batched_workspace_bytes(probs, len(As), ctypes.byref(d))
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    if autotune:
+        big = int(need * 4)
+        ws = _ws(big, dev)
+        _check("nsk_autotune_batched", lib.nsk_autotune_batched(probs, len(As), ctypes.byref(d), ws.data_ptr(),
+                                                                ws.numel(), _stream(dev), 8))
+        need = lib.nsk_batched_workspace_bytes(probs, len(As), ctypes.byref(d))
+        if ws.numel() < need:
+            ws = _ws(need, dev)
+    _check("nsk_trailing_rsv_batched", lib.nsk_trailing_rsv_batched(probs, len(As), ctypes.byref(d), ws.data_ptr(),
+                                                                    ws.numel(), _stream(dev)))
+    return outs
+
+
+def batched_workspace_bytes(shapes, ks, ss, kind="srht", acc="f64", dtype=torch.float32):
+    """Workspace bytes of a batch given shapes (no device memory needed)."""
+    lib = load()
+    n = len(shapes)
+    probs = (Problem * n)()
+    for i, (m, N) in enumerate(shapes):
+        probs[i] = Problem(1, _TORCH_DT[dtype], 0, m, N, N, ks[i], ss[i], 0, 1, 1, None)
+    d = make_desc(kind, 0, 0, 8, acc)
+    return int(lib.nsk_batched_workspace_bytes(probs, n, ctypes.byref(d)))
+
+
+def tune_lookup(n, dtype=torch.float32, acc="f64"):
+    return int(load().nsk_tune_lookup(n, _TORCH_DT[dtype], {"f64": F64, "f32": F32}[acc]))
+
+
+def tune_set(n, rows_per_tile, dtype=torch.float32, acc="f64"):
+    _check("nsk_tune_set", load().nsk_tune_set(n, _TORCH_DT[dtype], {"f64": F64, "f32": F32}[acc], rows_per_tile))
+
+
+def tune_clear():
+    load().nsk_tune_clear()
+
+
+# ------------------------------------------------------------------------------- TLS
+def tls_solve(A, b=None, kind="sparse", s=None, seed=0, zeta=8, acc="f64", max_sweeps=0):
+    """Sketched TLS: returns ``(x, state, info)``; ``state`` feeds :func:`tls_backward`."""
+    lib = load()
+    blocks = [A] if b is None else [A, b.reshape(-1, 1) if b.dim() == 1 else b]
+    ops, nb, m, N, dev, keep = _blocks(blocks)
+    n = N - 1
+    d = make_desc(kind, s, seed, zeta, acc, max_sweeps)
+    ws = _ws(lib.nsk_workspace_bytes(m, N, 1, ctypes.byref(d)), dev)
+    state = _ws(lib.nsk_tls_state_bytes(n, s), dev)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    _check("nsk_tls_solve", lib.nsk_tls_solve(ops, nb, m, ctypes.byref(d), x.data_ptr(), state.data_ptr(),
+                                              state.numel(), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                                              _stream(dev)))
+    return x, state, info
+
+
+def tls_backward(state, m, n, gx, kind="sparse", s=None, seed=0, zeta=8, acc="f64", out_dtype=torch.float32):
+    """Gradient of ``L(x)`` w.r.t. ``[A | b]``: returns ``(dA, db)`` (m x n and m)."""
+    lib = load()
+    dev = state.device
+    d = make_desc(kind, s, seed, zeta, acc)
+    ws = _ws(lib.nsk_workspace_bytes(m, n + 1, 1, ctypes.byref(d)), dev)
+    gx = gx.to(torch.float64).contiguous()
+    dA = torch.empty((m, n), dtype=out_dtype, device=dev)
+    db = torch.empty(m, dtype=out_dtype, device=dev)
+    _check("nsk_tls_backward", lib.nsk_tls_backward(ctypes.byref(d), m, n, state.data_ptr(), gx.data_ptr(),
+                                                    dA.data_ptr(), n, db.data_ptr(), _TORCH_DT[out_dtype],
+                                                    ws.data_ptr(), ws.numel(), _stream(dev)))
+    return dA, db
+
+
+class TLSSketch(torch.autograd.Function):
+    """``x = TLSSketch.apply(A, b, s, seed, kind, zeta)``: sketched TLS solution (FP64) whose
+    backward applies S^T regenerated from the seed and the SVD adjoint of the trailing vector."""
+
+    @staticmethod
+    def forward(ctx, A, b, s, seed, kind="sparse", zeta=8):
+        x, state, _ = tls_solve(A, b, kind=kind, s=s, seed=seed, zeta=zeta)
+        ctx.save_for_backward(state)
+        ctx.meta = (A.shape[0], A.shape[1], kind, s, seed, zeta, A.dtype, b.dtype)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (state,) = ctx.saved_tensors
+        m, n, kind, s, seed, zeta, adt, bdt = ctx.meta
+        dA, db = tls_backward(state, m, n, gx, kind=kind, s=s, seed=seed, zeta=zeta, out_dtype=adt)
+        return dA, db.to(bdt), None, None, None, None
+
+
+# ----------------------------------------------------------------------- draw hooks
+def philox(seed, idx, sub, stream):
+    out = (ctypes.c_uint32 * 4)()
+    _check("nsk_philox", load().nsk_philox(seed, idx, sub, stream, out))
+    return list(out)
+
+
+def draw_signs(seed, m):
+    import numpy as np
+    d = np.empty(m, dtype=np.int8)
+    _check("nsk_draw_signs", load().nsk_draw_signs(seed, m, d.ctypes.data))
+    return d
+
+
+def draw_srht_rows(seed, m, s):
+    import numpy as np
+    r = np.empty(s, dtype=np.int64)
+    _check("nsk_draw_srht_rows", load().nsk_draw_srht_rows(seed, m, s, r.ctypes.data))
+    return r
+
+
+def draw_sparse(seed, m, s, zeta):
+    import numpy as np
+    rows = np.empty((m, zeta), dtype=np.int32)
+    sg = np.empty((m, zeta), dtype=np.int8)
+    _check("nsk_draw_sparse", load().nsk_draw_sparse(seed, m, s, zeta, rows.ctypes.data, sg.ctypes.data))
+    return rows, sg
+
+
+def draw_signs_device(seed, m, device="cuda"):
+    d = torch.empty(m, dtype=torch.int8, device=device)
+    _check("nsk_draw_signs_device", load().nsk_draw_signs_device(seed, m, d.data_ptr(), _stream(d.device)))
+    return d
+
+
+def draw_sparse_device(seed, m, s, zeta, device="cuda"):
+    rows = torch.empty((m, zeta), dtype=torch.int32, device=device)
+    sg = torch.empty((m, zeta), dtype=torch.int8, device=device)
+    _check("nsk_draw_sparse_device", load().nsk_draw_sparse_device(seed, m, s, zeta, rows.data_ptr(), sg.data_ptr(),
+                                                                    _stream(rows.device)))
+    return rows, sg
+
+
+def draw_gaussian_device(seed, s, j0, j1, dtype="bf16", device="cuda"):
+    dt = {"bf16": BF16, "e4m3": F8E4M3, "f32": F32}[dtype]
+    G = torch.empty((s, j1 - j0), dtype=torch.float32, device=device)
+    _check("nsk_draw_gaussian_device", load().nsk_draw_gaussian_device(seed, s, j0, j1, dt, G.data_ptr(),
+                                                                        _stream(G.device)))
+    return G

@@ -1,0 +1,553 @@
+// C ABI of the nsk library: argument checks, workspace layout, host-side draws and the
+// launch sequence of Algorithm 1 (sketch -> reduce -> QR + Jacobi -> extraction).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "nsk.h"
+#include "nsk_internal.hpp"
+
+namespace nsk {
+// defined in the .hip translation units
+size_t sparse_lds_bytes(int s, int zeta, int acc);
+size_t gauss_lds_bytes(int s, int N, int dtype);
+int gauss_tiles_per_wave(int s, int N);
+size_t batched_lds_bytes(int s_max, int n_max);
+hipError_t launch_batched(const void* insts, const void* tiles, int ntiles, int* counters, int ncounters,
+                          int dtype, int acc, int grid, size_t lds, hipStream_t st);
+size_t batch_inst_bytes();
+size_t batch_tile_bytes();
+void batch_fill_inst(void* dst, const Operand& op, int64_t m, int N, int s, int k, int groups, int ctiles,
+                     int max_sweeps, uint64_t seed, const int* rows, void* partial, double* sa_cm, double* R,
+                     double* V, double* sigma, int* order, double* Vk, double* sigma_k, nsk_info* info);
+void batch_fill_tile(void* dst, int inst, int ctile, int g);
+int tuned_rows_per_tile(int n, int64_t m, int dtype, int acc);
+}  // namespace nsk
+
+using namespace nsk;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kResParts = 1024;
+constexpr int kMaxN = 1024;
+constexpr int64_t kMaxResidualVec = 16384;  // N * k doubles of V_k held in LDS
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int dflt_zeta(const nsk_desc* d) { return d->zeta ? d->zeta : 8; }
+int dflt_sweeps(const nsk_desc* d) { return d->max_sweeps ? d->max_sweeps : 30; }
+int dflt_acc(const nsk_desc* d) { return d->acc == NSK_F32 ? NSK_F32 : NSK_F64; }
+
+// Row groups (number of partial sketches) for a single-instance sketch.
+int plan_groups(const nsk_desc* d, int64_t m, int64_t N) {
+  if (d->row_groups > 0) return d->row_groups;
+  if (d->kind == NSK_SRHT) {
+    if (next_pow2(m) <= 64) return 1;
+    const int64_t ct = (N + 7) / 8, nb = (m + 1023) / 1024;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, (1024 + ct - 1) / ct));
+  }
+  if (d->kind == NSK_SPARSE_SIGN) {
+    const int64_t ct = (N + 15) / 16, nb = (m + 1023) / 1024;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, (512 + ct - 1) / ct));
+  }
+  const int64_t ks = (m + 31) / 32;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(256, (ks + 7) / 8));
+}
+
+struct Layout {
+  size_t rows, partial, sa, R, V, sigma, order, res, work, total;
+};
+
+Layout layout(int64_t m, int64_t N, const nsk_desc* d) {
+  Layout L{};
+  const int64_t s = d->s;
+  const int groups = plan_groups(d, m, N);
+  size_t off = 0;
+  L.rows = off;    off = align_up(off + (size_t)s * 4);
+  L.partial = off; off = align_up(off + (size_t)groups * s * N * 8);
+  L.sa = off;      off = align_up(off + (size_t)s * N * 8);
+  L.R = off;       off = align_up(off + (size_t)N * N * 8);
+  L.V = off;       off = align_up(off + (size_t)N * N * 8);
+  L.sigma = off;   off = align_up(off + (size_t)N * 8);
+  L.order = off;   off = align_up(off + (size_t)N * 4);
+  L.res = off;     off = align_up(off + (size_t)kResParts * 8);
+  L.work = off;    off = align_up(off + (size_t)(2 * s + 2 * N) * 8);
+  L.total = off;
+  return L;
+}
+
+int check_desc(const nsk_desc* d, int64_t m, int64_t N) {
+  if (!d) return NSK_EINVAL;
+  if (d->kind < NSK_SRHT || d->kind > NSK_GAUSSIAN) return NSK_EINVAL;
+  if (m < N || N < 1 || d->s <= N || d->s > m) return NSK_EINVAL;
+  if (d->kind == NSK_SPARSE_SIGN) {
+    const int z = dflt_zeta(d);
+    if (z < 1 || z > 32 || z > d->s || d->s > 65535) return NSK_EINVAL;
+  }
+  if (d->kind == NSK_SRHT && d->s > 2048) return NSK_EUNSUPPORTED;
+  if (d->kind == NSK_GAUSSIAN && gauss_tiles_per_wave((int)d->s, (int)N) > 48) return NSK_EUNSUPPORTED;
+  if (d->acc != 0 && d->acc != NSK_F64 && d->acc != NSK_F32) return NSK_EINVAL;
+  if (d->max_sweeps < 0 || d->row_groups < 0) return NSK_EINVAL;
+  return NSK_OK;
+}
+
+int build_operand(const nsk_operand* blocks, int nblocks, const nsk_desc* d, Operand& op, int64_t& N) {
+  if (!blocks || nblocks < 1 || nblocks > kMaxBlocks) return NSK_EINVAL;
+  std::memset(&op, 0, sizeof(op));
+  op.nb = nblocks;
+  op.dtype = blocks[0].dtype;
+  N = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    const nsk_operand& o = blocks[b];
+    if (!o.ptr || o.cols < 1 || o.ld < o.cols || o.reserved != 0) return NSK_EINVAL;
+    if (o.dtype != op.dtype) return NSK_EINVAL;
+    op.ptr[b] = o.ptr;
+    op.ld[b] = o.ld;
+    op.exp[b] = o.col_exp;
+    op.col0[b] = (int32_t)N;
+    N += o.cols;
+  }
+  op.col0[nblocks] = (int32_t)N;
+  if (N > kMaxN) return NSK_EINVAL;
+  if (!d) return NSK_EINVAL;
+  const int dt = op.dtype;
+  if (d->kind == NSK_GAUSSIAN) {
+    if (dt != NSK_BF16 && dt != NSK_F8E4M3) return NSK_EUNSUPPORTED;
+  } else if (dt != NSK_F32 && dt != NSK_F64) {
+    return NSK_EUNSUPPORTED;
+  }
+  return NSK_OK;
+}
+
+// Host Floyd sampling of s distinct rows of [0, pool), sorted (same rule as the device
+// hooks document: 64-bit uniform from words 0,1 of block (t, 0, stream 2)).
+void srht_rows_host(uint64_t seed, int64_t pool, int64_t s, std::vector<int64_t>& out) {
+  out.clear();
+  out.reserve((size_t)s);
+  std::vector<int64_t> taken;
+  for (int64_t t = 0; t < s; ++t) {
+    const Words w = philox(seed, (uint64_t)t, 0, kRows);
+    const unsigned __int128 u = (unsigned __int128)((uint64_t)w.w[0] | ((uint64_t)w.w[1] << 32));
+    const int64_t i = pool - s + t;
+    int64_t x = (int64_t)((u * (unsigned __int128)(uint64_t)(i + 1)) >> 64);
+    if (std::find(out.begin(), out.end(), x) != out.end()) x = i;
+    out.push_back(x);
+  }
+  std::sort(out.begin(), out.end());
+}
+
+int upload_rows(uint64_t seed, int64_t m, int64_t s, int* dst, hipStream_t st) {
+  std::vector<int64_t> r;
+  srht_rows_host(seed, next_pow2(m), s, r);
+  std::vector<int> r32(r.begin(), r.end());
+  if (hipMemcpyAsync(dst, r32.data(), r32.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
+    return NSK_EDEVICE;
+  // the host vector dies at return: make sure the copy has consumed it
+  if (hipStreamSynchronize(st) != hipSuccess) return NSK_EDEVICE;
+  return NSK_OK;
+}
+
+SketchPlan make_plan(const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws, const Layout& L) {
+  SketchPlan p{};
+  p.kind = d->kind;
+  p.m = m;
+  p.N = (int)N;
+  p.s = (int)d->s;
+  p.zeta = dflt_zeta(d);
+  p.seed = d->seed;
+  p.acc = dflt_acc(d);
+  p.groups = plan_groups(d, m, N);
+  p.col_tile = 0;
+  p.rows = reinterpret_cast<const int*>(ws + L.rows);
+  p.partial = ws + L.partial;
+  return p;
+}
+
+int dev(hipError_t e) { return e == hipSuccess ? NSK_OK : NSK_EDEVICE; }
+
+// Sketch + reduce; SA written column-major into the workspace and optionally row-major out.
+int run_sketch(const Operand& op, const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws, const Layout& L,
+               double* sa_rm, int64_t ld_rm, hipStream_t st, SketchPlan& p) {
+  p = make_plan(d, m, N, ws, L);
+  if (d->kind == NSK_SRHT) {
+    const int rc = upload_rows(d->seed, m, d->s, reinterpret_cast<int*>(ws + L.rows), st);
+    if (rc) return rc;
+  }
+  int rc = dev(launch_sketch(op, p, st));
+  if (rc) return rc;
+  return dev(launch_reduce(op, p, sa_rm, ld_rm, reinterpret_cast<double*>(ws + L.sa), d->s, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nsk_status_str(int status) {
+  switch (status) {
+    case NSK_OK: return "ok";
+    case NSK_EINVAL: return "invalid argument";
+    case NSK_EWORKSPACE: return "workspace too small";
+    case NSK_ENOCONV: return "Jacobi did not converge";
+    case NSK_EDEVICE: return "HIP runtime error";
+    case NSK_EUNSUPPORTED: return "unsupported kind/dtype combination";
+    default: return "unknown status";
+  }
+}
+
+int nsk_version(void) { return 10000; }
+
+size_t nsk_workspace_bytes(int64_t m, int64_t N, int64_t k, const nsk_desc* d) {
+  if (check_desc(d, m, N) != NSK_OK || k < 1 || k > N || N > kMaxN) return 0;
+  return layout(m, N, d).total;
+}
+
+int nsk_sketch(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_desc* d, double* SA, int64_t ldsa,
+               void* ws, size_t ws_bytes, void* stream) {
+  Operand op;
+  int64_t N;
+  int rc = build_operand(blocks, nblocks, d, op, N);
+  if (rc) return rc;
+  if ((rc = check_desc(d, m, N))) return rc;
+  if (!SA || ldsa < N || !ws) return NSK_EINVAL;
+  const Layout L = layout(m, N, d);
+  if (ws_bytes < L.total) return NSK_EWORKSPACE;
+  SketchPlan p;
+  return run_sketch(op, d, m, N, static_cast<unsigned char*>(ws), L, SA, ldsa, (hipStream_t)stream, p);
+}
+
+int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int64_t k, const nsk_desc* d,
+                     double* Vk, double* sigma_k, nsk_info* info, void* ws, size_t ws_bytes, void* stream) {
+  Operand op;
+  int64_t N;
+  int rc = build_operand(blocks, nblocks, d, op, N);
+  if (rc) return rc;
+  if ((rc = check_desc(d, m, N))) return rc;
+  if (k < 1 || k > N || !Vk || !sigma_k || !ws) return NSK_EINVAL;
+  const Layout L = layout(m, N, d);
+  if (ws_bytes < L.total) return NSK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  SketchPlan p;
+  if ((rc = run_sketch(op, d, m, N, w, L, nullptr, 0, st, p))) return rc;
+  SvdPlan sp{};
+  sp.s = (int)d->s;
+  sp.N = (int)N;
+  sp.k = (int)k;
+  sp.max_sweeps = dflt_sweeps(d);
+  sp.sa = reinterpret_cast<double*>(w + L.sa);
+  sp.R = reinterpret_cast<double*>(w + L.R);
+  sp.V = reinterpret_cast<double*>(w + L.V);
+  sp.sigma = reinterpret_cast<double*>(w + L.sigma);
+  sp.order = reinterpret_cast<int*>(w + L.order);
+  sp.Vk = Vk;
+  sp.sigma_k = sigma_k;
+  sp.info = info;
+  if ((rc = dev(launch_svd(sp, st)))) return rc;
+  if ((d->flags & NSK_FLAG_RESIDUAL) && info) {
+    if (N * k > kMaxResidualVec) return NSK_EUNSUPPORTED;
+    const int64_t parts = std::min<int64_t>(kResParts, std::max<int64_t>(1, m / 256));
+    rc = dev(launch_residual(op, m, Vk, (int)k, reinterpret_cast<double*>(w + L.res), (int)parts, nullptr, info, st));
+  }
+  return rc;
+}
+
+int nsk_residual(const nsk_operand* blocks, int32_t nblocks, int64_t m, const double* Vk, int64_t k, double* out,
+                 void* ws, size_t ws_bytes, void* stream) {
+  nsk_desc d{};
+  d.kind = NSK_SRHT;
+  Operand op;
+  int64_t N;
+  // residual accepts FP32 / FP64 operands: validate with a SRHT-shaped descriptor
+  int rc = build_operand(blocks, nblocks, &d, op, N);
+  if (rc) return rc;
+  if (m < 1 || k < 1 || k > N || !Vk || !out || !ws) return NSK_EINVAL;
+  if (N * k > kMaxResidualVec) return NSK_EUNSUPPORTED;
+  if (ws_bytes < (size_t)kResParts * 8) return NSK_EWORKSPACE;
+  const int64_t parts = std::min<int64_t>(kResParts, std::max<int64_t>(1, m / 256));
+  return dev(launch_residual(op, m, Vk, (int)k, static_cast<double*>(ws), (int)parts, out, nullptr,
+                             (hipStream_t)stream));
+}
+
+// TLS state layout: SA row-major (s x N), V (N x N col-major), sigma (N), order (N ints), x (n), v (N).
+static void tls_state_layout(int64_t n, int64_t s, size_t* o) {
+  const int64_t N = n + 1;
+  size_t off = 0;
+  o[0] = off; off = align_up(off + (size_t)s * N * 8);
+  o[1] = off; off = align_up(off + (size_t)N * N * 8);
+  o[2] = off; off = align_up(off + (size_t)N * 8);
+  o[3] = off; off = align_up(off + (size_t)N * 4);
+  o[4] = off; off = align_up(off + (size_t)n * 8);
+  o[5] = off; off = align_up(off + (size_t)N * 8);
+  o[6] = off;
+}
+
+size_t nsk_tls_state_bytes(int64_t n, int64_t s) {
+  if (n < 1 || s <= n + 1) return 0;
+  size_t o[7];
+  tls_state_layout(n, s, o);
+  return o[6];
+}
+
+int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_desc* d, double* x, void* state,
+                  size_t state_bytes, nsk_info* info, void* ws, size_t ws_bytes, void* stream) {
+  Operand op;
+  int64_t N;
+  int rc = build_operand(blocks, nblocks, d, op, N);
+  if (rc) return rc;
+  if ((rc = check_desc(d, m, N))) return rc;
+  if (N < 2 || !x || !state || !ws) return NSK_EINVAL;
+  const int64_t n = N - 1;
+  if (state_bytes < nsk_tls_state_bytes(n, d->s)) return NSK_EWORKSPACE;
+  const Layout L = layout(m, N, d);
+  if (ws_bytes < L.total) return NSK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  unsigned char* S = static_cast<unsigned char*>(state);
+  size_t o[7];
+  tls_state_layout(n, d->s, o);
+  SketchPlan p;
+  if ((rc = run_sketch(op, d, m, N, w, L, reinterpret_cast<double*>(S + o[0]), N, st, p))) return rc;
+  SvdPlan sp{};
+  sp.s = (int)d->s;
+  sp.N = (int)N;
+  sp.k = 1;
+  sp.max_sweeps = dflt_sweeps(d);
+  sp.sa = reinterpret_cast<double*>(w + L.sa);
+  sp.R = reinterpret_cast<double*>(w + L.R);
+  sp.V = reinterpret_cast<double*>(S + o[1]);
+  sp.sigma = reinterpret_cast<double*>(S + o[2]);
+  sp.order = reinterpret_cast<int*>(S + o[3]);
+  sp.Vk = nullptr;
+  sp.sigma_k = nullptr;
+  sp.info = info;
+  if ((rc = dev(launch_svd(sp, st)))) return rc;
+  if ((rc = dev(launch_tls_extract((int)N, sp.V, sp.sigma, sp.order, reinterpret_cast<double*>(S + o[4]),
+                                   reinterpret_cast<double*>(S + o[5]), st))))
+    return rc;
+  return dev(hipMemcpyAsync(x, S + o[4], (size_t)n * 8, hipMemcpyDeviceToDevice, st));
+}
+
+int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state, const double* gx, void* dA,
+                     int64_t ldda, void* db, int32_t out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  const int64_t N = n + 1;
+  int rc = check_desc(d, m, N);
+  if (rc) return rc;
+  if (d->kind == NSK_GAUSSIAN) return NSK_EUNSUPPORTED;
+  if (!state || !gx || !dA || !db || !ws || ldda < n) return NSK_EINVAL;
+  if (out_dtype != NSK_F32 && out_dtype != NSK_F64) return NSK_EINVAL;
+  const Layout L = layout(m, N, d);
+  if (ws_bytes < L.total) return NSK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  const unsigned char* S = static_cast<const unsigned char*>(state);
+  size_t o[7];
+  tls_state_layout(n, d->s, o);
+  SketchPlan p = make_plan(d, m, N, w, L);
+  if (d->kind == NSK_SRHT && (rc = upload_rows(d->seed, m, d->s, reinterpret_cast<int*>(w + L.rows), st))) return rc;
+  return dev(launch_tls_backward(p, m, reinterpret_cast<const double*>(S + o[0]),
+                                 reinterpret_cast<const double*>(S + o[1]), reinterpret_cast<const double*>(S + o[2]),
+                                 reinterpret_cast<const int*>(S + o[3]), reinterpret_cast<const double*>(S + o[4]),
+                                 gx, reinterpret_cast<double*>(w + L.work), dA, ldda, db, out_dtype, st));
+}
+
+// ------------------------------------------------------------------------------ batched
+struct BatchLayout {
+  size_t insts, tiles, counters, rows, per_inst, total;
+  std::vector<size_t> inst_off;
+  std::vector<int> groups;
+  int ntiles;
+};
+
+static int batch_plan(const nsk_problem* probs, int32_t count, const nsk_desc* base, BatchLayout& B) {
+  if (!probs || count < 1 || !base) return NSK_EINVAL;
+  if (base->kind != NSK_SRHT) return NSK_EUNSUPPORTED;
+  B.inst_off.assign(count, 0);
+  B.groups.assign(count, 0);
+  B.ntiles = 0;
+  size_t rows_total = 0;
+  for (int i = 0; i < count; ++i) {
+    const nsk_problem& q = probs[i];
+    if (q.n < 1 || q.n > 256 || q.m < q.n || q.s <= q.n || q.s > q.m || q.s > 1024 || q.k < 1 || q.k > q.n ||
+        q.ld < q.n || !q.A || !q.Vk || !q.sigma_k)
+      return NSK_EINVAL;
+    if (q.dtype != NSK_F32 && q.dtype != NSK_F64) return NSK_EUNSUPPORTED;
+    const int rpt = tuned_rows_per_tile((int)q.n, q.m, q.dtype, dflt_acc(base));
+    const int64_t nb = (q.m + 1023) / 1024;
+    const int g = (int)std::max<int64_t>(1, (nb + rpt - 1) / rpt);
+    B.groups[i] = g;
+    B.ntiles += g * (int)((q.n + 7) / 8);
+    rows_total += align_up((size_t)q.s * 4);
+  }
+  size_t off = 0;
+  B.insts = off;    off = align_up(off + (size_t)count * batch_inst_bytes());
+  B.tiles = off;    off = align_up(off + (size_t)B.ntiles * batch_tile_bytes());
+  B.counters = off; off = align_up(off + (size_t)(count + 1) * 4);
+  B.rows = off;     off = align_up(off + rows_total);
+  B.per_inst = off;
+  for (int i = 0; i < count; ++i) {
+    const nsk_problem& q = probs[i];
+    B.inst_off[i] = off;
+    const size_t s = (size_t)q.s, n = (size_t)q.n;
+    off = align_up(off + (size_t)B.groups[i] * s * n * 8);  // partial
+    off = align_up(off + s * n * 8);                        // sa
+    off = align_up(off + n * n * 8);                        // R
+    off = align_up(off + n * n * 8);                        // V
+    off = align_up(off + n * 8);                            // sigma
+    off = align_up(off + n * 4);                            // order
+  }
+  B.total = off;
+  return NSK_OK;
+}
+
+size_t nsk_batched_workspace_bytes(const nsk_problem* probs, int32_t count, const nsk_desc* base) {
+  BatchLayout B;
+  if (batch_plan(probs, count, base, B) != NSK_OK) return 0;
+  return B.total;
+}
+
+int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_desc* base, void* ws,
+                             size_t ws_bytes, void* stream) {
+  BatchLayout B;
+  int rc = batch_plan(probs, count, base, B);
+  if (rc) return rc;
+  if (!ws) return NSK_EINVAL;
+  if (ws_bytes < B.total) return NSK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  // instances in decreasing SVD cost (n^3), their tiles in that order
+  std::vector<int> ord(count);
+  for (int i = 0; i < count; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (probs[a].n != probs[b].n) return probs[a].n > probs[b].n;
+    return probs[a].m > probs[b].m;
+  });
+  std::vector<unsigned char> hinst((size_t)count * batch_inst_bytes());
+  std::vector<unsigned char> htile((size_t)B.ntiles * batch_tile_bytes());
+  std::vector<int> hrows;
+  std::vector<size_t> rows_off(count);
+  size_t roff = 0;
+  int s_max = 0, n_max = 0;
+  const int acc = dflt_acc(base);
+  for (int i = 0; i < count; ++i) {
+    const nsk_problem& q = probs[i];
+    rows_off[i] = roff;
+    std::vector<int64_t> r;
+    srht_rows_host(q.seed, next_pow2(q.m), q.s, r);
+    hrows.resize(roff / 4 + align_up((size_t)q.s * 4) / 4, 0);
+    for (size_t t = 0; t < r.size(); ++t) hrows[roff / 4 + t] = (int)r[t];
+    roff += align_up((size_t)q.s * 4);
+    s_max = std::max<int>(s_max, (int)q.s);
+    n_max = std::max<int>(n_max, (int)q.n);
+    Operand op;
+    std::memset(&op, 0, sizeof(op));
+    op.nb = 1;
+    op.dtype = q.dtype;
+    op.ptr[0] = q.A;
+    op.ld[0] = q.ld;
+    op.col0[0] = 0;
+    op.col0[1] = (int)q.n;
+    unsigned char* base_i = w + B.inst_off[i];
+    const size_t s = (size_t)q.s, n = (size_t)q.n;
+    size_t o = 0;
+    void* partial = base_i + o; o = align_up(o + (size_t)B.groups[i] * s * n * 8);
+    double* sa = reinterpret_cast<double*>(base_i + o); o = align_up(o + s * n * 8);
+    double* R = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * n * 8);
+    double* V = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * n * 8);
+    double* sig = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * 8);
+    int* order = reinterpret_cast<int*>(base_i + o);
+    batch_fill_inst(hinst.data() + (size_t)i * batch_inst_bytes(), op, q.m, (int)q.n, (int)q.s, (int)q.k,
+                    B.groups[i], (int)((q.n + 7) / 8), dflt_sweeps(base), q.seed,
+                    reinterpret_cast<const int*>(w + B.rows + rows_off[i]), partial, sa, R, V, sig, order, q.Vk,
+                    q.sigma_k, q.info);
+  }
+  int t = 0;
+  for (int oi = 0; oi < count; ++oi) {
+    const int i = ord[oi];
+    const int ct = (int)((probs[i].n + 7) / 8);
+    for (int g = 0; g < B.groups[i]; ++g)
+      for (int c = 0; c < ct; ++c) batch_fill_tile(htile.data() + (size_t)(t++) * batch_tile_bytes(), i, c, g);
+  }
+  int dtype = probs[0].dtype;
+  for (int i = 1; i < count; ++i)
+    if (probs[i].dtype != dtype) return NSK_EINVAL;
+  if (hipMemcpyAsync(w + B.insts, hinst.data(), hinst.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(w + B.tiles, htile.data(), htile.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(w + B.rows, hrows.data(), hrows.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+    return NSK_EDEVICE;
+  int devid = 0, cus = 256;
+  if (hipGetDevice(&devid) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, devid) == hipSuccess) cus = prop.multiProcessorCount;
+  }
+  const size_t lds = batched_lds_bytes(s_max, n_max);
+  const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+  const int grid = std::min(B.ntiles, cus * per_cu);
+  rc = dev(launch_batched(w + B.insts, w + B.tiles, B.ntiles, reinterpret_cast<int*>(w + B.counters), count + 1,
+                          dtype, acc, grid, lds, st));
+  if (rc) return rc;
+  // host staging vectors die at return
+  return dev(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------------------------ draws
+int nsk_philox(uint64_t seed, uint64_t idx, uint32_t sub, uint32_t stream, uint32_t out[4]) {
+  if (!out) return NSK_EINVAL;
+  const Words w = philox(seed, idx, sub, stream);
+  for (int i = 0; i < 4; ++i) out[i] = w.w[i];
+  return NSK_OK;
+}
+
+int nsk_draw_signs(uint64_t seed, int64_t m, int8_t* d) {
+  if (m < 1 || !d) return NSK_EINVAL;
+  for (int64_t j = 0; j < m; ++j) {
+    const uint32_t w = word(philox(seed, (uint64_t)(j >> 7), 0, kSigns), (uint32_t)((j >> 5) & 3));
+    d[j] = ((w >> (j & 31)) & 1u) ? -1 : 1;
+  }
+  return NSK_OK;
+}
+
+int nsk_draw_srht_rows(uint64_t seed, int64_t m, int64_t s, int64_t* rows) {
+  if (m < 1 || s < 1 || s > next_pow2(m) || !rows) return NSK_EINVAL;
+  std::vector<int64_t> r;
+  srht_rows_host(seed, next_pow2(m), s, r);
+  std::copy(r.begin(), r.end(), rows);
+  return NSK_OK;
+}
+
+int nsk_draw_sparse(uint64_t seed, int64_t m, int64_t s, int32_t zeta, int32_t* rows, int8_t* signs) {
+  if (m < 1 || zeta < 1 || zeta > 32 || zeta > s || s > 65535 || !rows || !signs) return NSK_EINVAL;
+  for (int64_t j = 0; j < m; ++j) {
+    int rw[32];
+    uint32_t nb;
+    sparse_column<32>(seed, (uint64_t)j, (int)s, zeta, rw, nb);
+    for (int t = 0; t < zeta; ++t) {
+      rows[j * zeta + t] = rw[t];
+      signs[j * zeta + t] = ((nb >> t) & 1u) ? -1 : 1;
+    }
+  }
+  return NSK_OK;
+}
+
+int nsk_draw_signs_device(uint64_t seed, int64_t m, int8_t* d, void* stream) {
+  if (m < 1 || !d) return NSK_EINVAL;
+  return dev(launch_draw_signs(seed, m, d, (hipStream_t)stream));
+}
+
+int nsk_draw_sparse_device(uint64_t seed, int64_t m, int64_t s, int32_t zeta, int32_t* rows, int8_t* signs,
+                           void* stream) {
+  if (m < 1 || zeta < 1 || zeta > 32 || zeta > s || s > 65535 || !rows || !signs) return NSK_EINVAL;
+  return dev(launch_draw_sparse(seed, m, (int)s, zeta, rows, signs, (hipStream_t)stream));
+}
+
+int nsk_draw_gaussian_device(uint64_t seed, int64_t s, int64_t j0, int64_t j1, int32_t dtype, float* G,
+                             void* stream) {
+  if (s < 1 || j0 < 0 || j1 <= j0 || !G) return NSK_EINVAL;
+  if (dtype != NSK_F32 && dtype != NSK_BF16 && dtype != NSK_F8E4M3) return NSK_EINVAL;
+  return dev(launch_draw_gauss(seed, (int)s, j0, j1, dtype, G, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+// Internal declarations of the nsk library: counter-based draws, operand descriptors,
+// kernel launchers.  Device and host code both include this header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nsk.h"
+
+namespace nsk {
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 multiplies whose halves
+// are xor-mixed with the other counter words and the key; the key advances by the two Weyl
+// increments between rounds.  Counter (lo32(idx), hi32(idx), sub, stream), key = seed.
+// ---------------------------------------------------------------------------------------
+enum : uint32_t { kSigns = 1, kRows = 2, kSparseRows = 3, kSparseSigns = 4, kGauss = 5 };
+
+struct Words { uint32_t w[4]; };
+
+__host__ __device__ inline Words philox(uint64_t seed, uint64_t idx, uint32_t sub, uint32_t stream) {
+  uint32_t x0 = (uint32_t)idx, x1 = (uint32_t)(idx >> 32), x2 = sub, x3 = stream;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p = (uint64_t)0xD2511F53u * x0;
+    const uint64_t q = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t y0 = (uint32_t)(q >> 32) ^ x1 ^ k0;
+    const uint32_t y2 = (uint32_t)(p >> 32) ^ x3 ^ k1;
+    x1 = (uint32_t)q;
+    x3 = (uint32_t)p;
+    x0 = y0;
+    x2 = y2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  Words o;
+  o.w[0] = x0; o.w[1] = x1; o.w[2] = x2; o.w[3] = x3;
+  return o;
+}
+
+// Word i (0..3) of a block, selected without a dynamically indexed array.
+__host__ __device__ inline uint32_t word(const Words& w, uint32_t i) {
+  return i == 0 ? w.w[0] : i == 1 ? w.w[1] : i == 2 ? w.w[2] : w.w[3];
+}
+
+// Sparse-sign column j of S: zeta distinct rows in [0, s) by Floyd sampling (draw t uses
+// word t&3 of block (j, t>>2, stream 3): x = floor(u (i+1) / 2^32), i = s - zeta + t, and
+// i replaces x when x was taken), signs from bit t of word j&3 of block (j>>2, 0, stream 4).
+template <int ZMAX>
+__host__ __device__ inline void sparse_column(uint64_t seed, uint64_t j, int s, int zeta,
+                                              int (&rows)[ZMAX], uint32_t& negbits) {
+  Words w = philox(seed, j, 0, kSparseRows);
+#pragma unroll
+  for (int t = 0; t < ZMAX; ++t) {
+    if (t < zeta) {
+      if (t > 0 && (t & 3) == 0) w = philox(seed, j, (uint32_t)(t >> 2), kSparseRows);
+      const uint32_t i = (uint32_t)(s - zeta + t);
+      int x = (int)(((uint64_t)w.w[t & 3] * (uint64_t)(i + 1u)) >> 32);
+      bool dup = false;
+#pragma unroll
+      for (int u = 0; u < t; ++u) dup |= (rows[u] == x);
+      rows[t] = dup ? (int)i : x;
+    }
+  }
+  negbits = word(philox(seed, j >> 2, 0, kSparseSigns), (uint32_t)(j & 3));
+}
+
+__host__ __device__ inline int64_t next_pow2(int64_t m) {
+  int64_t p = 1;
+  while (p < m) p <<= 1;
+  return p;
+}
+
+// ---------------------------------------------------------------------------------------
+// Operand: up to four row-major column blocks of one element type.
+// ---------------------------------------------------------------------------------------
+constexpr int kMaxBlocks = 4;
+struct Operand {
+  const void* ptr[kMaxBlocks];
+  int64_t ld[kMaxBlocks];
+  const int8_t* exp[kMaxBlocks];
+  int32_t col0[kMaxBlocks + 1];  // first column of each block; col0[nb] = N
+  int32_t nb;
+  int32_t dtype;
+};
+
+// Block holding column `col`, selected with constant indices only (a dynamically indexed
+// kernel-argument array would be copied to scratch memory).
+__device__ inline int column_block(const Operand& op, int col) {
+  int b = 0;
+  if (op.nb > 1 && col >= op.col0[1]) b = 1;
+  if (op.nb > 2 && col >= op.col0[2]) b = 2;
+  if (op.nb > 3 && col >= op.col0[3]) b = 3;
+  return b;
+}
+
+// Element (row, col) pointer parts for a column: base pointer and row stride.
+template <typename T>
+__device__ inline void column_ref(const Operand& op, int col, const T*& base, int64_t& ld) {
+  const int b = column_block(op, col);
+  const void* p = op.ptr[0];
+  int64_t l = op.ld[0];
+  int c0 = 0;
+  if (b == 1) { p = op.ptr[1]; l = op.ld[1]; c0 = op.col0[1]; }
+  if (b == 2) { p = op.ptr[2]; l = op.ld[2]; c0 = op.col0[2]; }
+  if (b == 3) { p = op.ptr[3]; l = op.ld[3]; c0 = op.col0[3]; }
+  base = static_cast<const T*>(p) + (col - c0);
+  ld = l;
+}
+
+__device__ inline int column_exp(const Operand& op, int col) {
+  const int b = column_block(op, col);
+  const int8_t* e = op.exp[0];
+  int c0 = 0;
+  if (b == 1) { e = op.exp[1]; c0 = op.col0[1]; }
+  if (b == 2) { e = op.exp[2]; c0 = op.col0[2]; }
+  if (b == 3) { e = op.exp[3]; c0 = op.col0[3]; }
+  return e ? (int)e[col - c0] : 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Launch plans and launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------------------
+struct SketchPlan {
+  int kind;           // nsk_kind
+  int64_t m;
+  int N;
+  int s;
+  int zeta;
+  uint64_t seed;
+  int acc;            // NSK_F64 or NSK_F32
+  int groups;         // row groups = number of partial sketches
+  int col_tile;       // columns per workgroup
+  const int* rows;    // SRHT: sorted sampled rows (device)
+  void* partial;      // groups x s x N (acc type)
+};
+
+hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st);
+// SA (FP64, s x N) = scale * sum_g partial_g; row-major (ld_rm) and/or column-major (ld_cm)
+hipError_t launch_reduce(const Operand& op, const SketchPlan& p, double* sa_rm, int64_t ld_rm,
+                         double* sa_cm, int64_t ld_cm, hipStream_t st);
+
+struct SvdPlan {
+  int s, N, k;
+  int max_sweeps;
+  double* sa;        // s x N column-major (ld = s), overwritten by the QR
+  double* R;         // N x N column-major work
+  double* V;         // N x N column-major work
+  double* sigma;     // N work: singular values in sorted order
+  int* order;        // N work: column index of each sorted singular value
+  double* Vk;        // N x k row-major out (nullable)
+  double* sigma_k;   // k out (nullable)
+  nsk_info* info;    // nullable
+};
+hipError_t launch_svd(const SvdPlan& p, hipStream_t st);
+
+hipError_t launch_residual(const Operand& op, int64_t m, const double* Vk, int k, double* partial,
+                           int parts, double* out, nsk_info* info, hipStream_t st);
+
+struct TlsState;  // layout in post.hip
+hipError_t launch_tls_extract(int N, const double* V, const double* sigma, const int* order,
+                              double* x, double* vN, hipStream_t st);
+hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const double* sa_cm, const double* V,
+                               const double* sigma, const int* order, const double* x,
+                               const double* gx, double* work, void* dA, int64_t ldda, void* db,
+                               int out_dtype, hipStream_t st);
+
+hipError_t launch_draw_signs(uint64_t seed, int64_t m, int8_t* d, hipStream_t st);
+hipError_t launch_draw_sparse(uint64_t seed, int64_t m, int s, int zeta, int32_t* rows,
+                              int8_t* signs, hipStream_t st);
+hipError_t launch_draw_gauss(uint64_t seed, int s, int64_t j0, int64_t j1, int dtype, float* G,
+                             hipStream_t st);
+
+}  // namespace nsk

@@ -1,0 +1,433 @@
+// Line 2 of Algorithm 1: the sketch SA = S A, reading A from HBM once.
+//
+// Every kernel writes per-row-group partial sketches (groups x s x N); launch_reduce sums
+// them in a fixed order (deterministic, no floating-point atomics to HBM) and applies the
+// operator's scale.
+//
+// SRHT (Section 2, with the Walsh-Hadamard matrix as trig transform).  With T = 1024 and
+// row index j = j1*T + j2, the Sylvester Hadamard entry (-1)^popcount(r & j) factors as
+// (-1)^popcount(i1 & j1) (-1)^popcount(i2 & j2) for a sampled row r = i1*T + i2.  A row block
+// j1 is signed by D, transformed by H_T along its rows (in-register butterflies, one LDS
+// transpose, in-register butterflies), and each sampled row r then takes the signed row
+// i2 of the transformed block: SA[r,:] += (-1)^popcount(i1 & j1) (H_T D_j1 A_j1)[i2,:].
+// A is read once; the sampled outer stage costs s/T adds per element of A.
+//
+// Sparse sign: each row j of A is added with signs to the zeta rows of SA that column j
+// of S selects; the workgroup's s x ct accumulator lives in LDS and takes ds_add_f64.
+//
+// Gaussian: SA = G_hat A on MFMA (bf16 or fp8 operands, FP32 accumulation); G_hat is
+// regenerated from Philox + Box-Muller per K-step and never read from memory.
+#include <hip/hip_runtime.h>
+
+#include "nsk_internal.hpp"
+#include "sketch_device.hpp"
+
+namespace nsk {
+
+// Raise the dynamic-LDS cap of a kernel to the 160 KB a gfx950 CU provides.
+static void set_lds_limit(const void* fn) {
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+// ============================================================================ sparse sign
+constexpr int kSpCols = 16;
+constexpr int kSpThreads = 1024;
+
+template <typename TIn, typename TAcc, int ZMAX>
+__global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t m, int N, int s,
+                                                            int zeta, uint64_t seed, int groups,
+                                                            TAcc* __restrict__ partial) {
+  extern __shared__ unsigned char smem_raw[];
+  TAcc* acc = reinterpret_cast<TAcc*>(smem_raw);                       // s x kSpCols
+  uint16_t* hrow = reinterpret_cast<uint16_t*>(acc + (size_t)s * kSpCols);  // kSpThreads x ZMAX
+  uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + kSpThreads * ZMAX + 16);
+
+  const int t = threadIdx.x;
+  const int col = t & (kSpCols - 1);
+  const int rs = t >> 4;  // 0..63
+  const int c = blockIdx.x * kSpCols + col;
+  const bool live = c < N;
+  const int g = blockIdx.y;
+
+  const TIn* base = nullptr;
+  int64_t ld = 0;
+  if (live) column_ref<TIn>(op, c, base, ld);
+
+  for (int i = t; i < s * kSpCols; i += kSpThreads) acc[i] = 0;
+
+  const int64_t rows_per_group = ((m + groups - 1) / groups + kSpThreads - 1) / kSpThreads * kSpThreads;
+  const int64_t gr0 = (int64_t)g * rows_per_group;
+  const int64_t gr1 = gr0 + rows_per_group < m ? gr0 + rows_per_group : m;
+
+  for (int64_t r0 = gr0; r0 < gr1; r0 += kSpThreads) {
+    __syncthreads();
+    {  // hashes of rows r0 + t
+      const int64_t j = r0 + t;
+      if (j < gr1) {
+        int rw[ZMAX];
+        uint32_t nb;
+        sparse_column<ZMAX>(seed, (uint64_t)j, s, zeta, rw, nb);
+#pragma unroll
+        for (int q = 0; q < ZMAX; ++q)
+          if (q < zeta) hrow[t * ZMAX + q] = (uint16_t)rw[q];
+        hneg[t] = nb;
+      }
+    }
+    __syncthreads();
+    const int nrow = (int)((gr1 - r0) < kSpThreads ? (gr1 - r0) : kSpThreads);
+    for (int q = rs; q < nrow; q += kSpThreads / kSpCols) {
+      if (!live) break;
+      const TAcc a = (TAcc)to_f64(base[(r0 + q) * ld]);
+      const uint32_t nb = hneg[q];
+#pragma unroll
+      for (int z = 0; z < ZMAX; ++z) {
+        if (z < zeta) {
+          const int h = hrow[q * ZMAX + z];
+          atomicAdd(&acc[h * kSpCols + col], ((nb >> z) & 1u) ? -a : a);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  TAcc* out = partial + (size_t)g * s * N;
+  for (int i = t; i < s * kSpCols; i += kSpThreads) {
+    const int row = i / kSpCols, cc = blockIdx.x * kSpCols + (i % kSpCols);
+    if (cc < N) out[(size_t)row * N + cc] = acc[i];
+  }
+}
+
+// ============================================================================== Gaussian
+// v_mfma_f32_16x16x32_{bf16,fp8_fp8}: lane l supplies A[l%16][8(l/16)+0..7] and
+// B[8(l/16)+0..7][l%16]; the accumulator lane l holds C[4(l/16)+0..3][l%16].
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+constexpr int kGK = 32;        // K (rows of A) per MFMA step
+constexpr int kGThreads = 256;
+constexpr int kGMaxTiles = 48; // (s/16)*(N/16) output tiles per wave, at most
+
+template <bool FP8, int TPW>
+__global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m, int N, int s,
+                                                          uint64_t seed, int groups, int ksteps_per_group,
+                                                          float* __restrict__ partial) {
+  using E = typename std::conditional<FP8, uint8_t, __bf16>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const int sp = (s + 15) & ~15;
+  const int np = (N + 15) & ~15;
+  E* gs = reinterpret_cast<E*>(smem_raw);            // sp x kGK (row i, k contiguous)
+  E* as = gs + (size_t)sp * kGK;                     // np x kGK (column j, k contiguous)
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int mt_n = sp / 16, nt_n = np / 16, tiles = mt_n * nt_n;
+  floatx4 accv[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) accv[q] = floatx4{0, 0, 0, 0};
+
+  const int64_t ksteps = (m + kGK - 1) / kGK;
+  const int64_t k_begin = (int64_t)blockIdx.x * ksteps_per_group;
+  const int64_t k_end = k_begin + ksteps_per_group < ksteps ? k_begin + ksteps_per_group : ksteps;
+  for (int64_t ks = k_begin; ks < k_end; ++ks) {
+    const int64_t j0 = ks * kGK;
+    __syncthreads();
+    // G_hat[i, j0 + kk]: Philox block (j, i>>2) gives rows 4q..4q+3 of column j
+    for (int w = t; w < (sp / 4) * kGK; w += kGThreads) {
+      const int kk = w % kGK, q = w / kGK;
+      const int64_t j = j0 + kk;
+      float g[4] = {0, 0, 0, 0};
+      if (j < m) {
+        const Words r = philox(seed, (uint64_t)j, (uint32_t)q, kGauss);
+        box_muller(r.w[0], r.w[1], g[0], g[1]);
+        box_muller(r.w[2], r.w[3], g[2], g[3]);
+      }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int i = 4 * q + h;
+        E e;
+        if constexpr (FP8) {
+          e = (i < s) ? (E)e4m3_bits(e4m3_round(g[h])) : (E)0;
+        } else {
+          e = (i < s) ? (E)bf16_round(g[h]) : (E)0.0f;
+        }
+        gs[(size_t)i * kGK + kk] = e;
+      }
+    }
+    // A[j0 + kk, col] -> as[col][kk]
+    for (int w = t; w < np * kGK; w += kGThreads) {
+      const int cc = w % np, kk = w / np;
+      const int64_t j = j0 + kk;
+      E e;
+      if constexpr (FP8) e = 0; else e = (E)0.0f;
+      if (cc < N && j < m) {
+        const E* b;
+        int64_t ld;
+        column_ref<E>(op, cc, b, ld);
+        e = b[j * ld];
+      }
+      as[(size_t)cc * kGK + kk] = e;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int tile = wave + 4 * q;
+      if (tile < tiles) {
+        const int mt = tile / nt_n, nt = tile % nt_n;
+        const int ka = 8 * (lane >> 4);
+        const E* pa = gs + (size_t)(mt * 16 + (lane & 15)) * kGK + ka;
+        const E* pb = as + (size_t)(nt * 16 + (lane & 15)) * kGK + ka;
+        if constexpr (FP8) {
+          const long av = *reinterpret_cast<const long*>(pa);
+          const long bv = *reinterpret_cast<const long*>(pb);
+          accv[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, accv[q], 0, 0, 0);
+        } else {
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(pa);
+          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(pb);
+          accv[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, accv[q], 0, 0, 0);
+        }
+      }
+    }
+  }
+  float* out = partial + (size_t)blockIdx.x * s * N;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int tile = wave + 4 * q;
+    if (tile < tiles) {
+      const int mt = tile / nt_n, nt = tile % nt_n;
+      const int cc = nt * 16 + (lane & 15);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int i = mt * 16 + 4 * (lane >> 4) + h;
+        if (i < s && cc < N) out[(size_t)i * N + cc] = accv[q][h];
+      }
+    }
+  }
+}
+
+// ============================================================================ small SRHT
+// Explicit-formula SRHT for tiny m (m_p <= 64): SA[i, c] = sum_j d_j (-1)^pc(r_i & j) A[j, c].
+template <typename TIn>
+__global__ void srht_small_kernel(Operand op, int64_t m, int N, int s, uint64_t seed,
+                                  const int* __restrict__ rows, double* __restrict__ partial) {
+  const int i = blockIdx.x;
+  const int r = rows[i];
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    const TIn* b;
+    int64_t ld;
+    column_ref<TIn>(op, c, b, ld);
+    double acc = 0;
+    for (int64_t j = 0; j < m; ++j) {
+      const uint32_t bits = word(philox(seed, (uint64_t)(j >> 7), 0, kSigns), (uint32_t)((j >> 5) & 3));
+      const bool neg = ((bits >> (j & 31)) & 1u) ^ (__popcll((uint64_t)(r & j)) & 1);
+      const double a = to_f64(b[j * ld]);
+      acc += neg ? -a : a;
+    }
+    partial[(size_t)i * N + c] = acc;
+  }
+}
+
+// ============================================================================== launches
+template <typename TIn, typename TAcc>
+static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
+  dim3 grid((p.N + kSrhtCols - 1) / kSrhtCols, p.groups);
+  TAcc* part = static_cast<TAcc*>(p.partial);
+  const size_t lds = srht_smem_bytes(p.s);
+#define NSK_SRHT_CASE(U)                                                                        \
+  {                                                                                             \
+    set_lds_limit((const void*)srht_kernel<TIn, TAcc, U>);                                      \
+    srht_kernel<TIn, TAcc, U><<<grid, kSrhtThreads, lds, st>>>(op, p.m, p.N, p.s, p.seed, p.rows, \
+                                                               p.groups, part);                 \
+  }
+  if (p.s <= 256) NSK_SRHT_CASE(8)
+  else if (p.s <= 512) NSK_SRHT_CASE(16)
+  else if (p.s <= 1024) NSK_SRHT_CASE(32)
+  else NSK_SRHT_CASE(64)
+#undef NSK_SRHT_CASE
+  return hipGetLastError();
+}
+
+template <typename TIn, typename TAcc>
+static hipError_t sparse_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
+  dim3 grid((p.N + kSpCols - 1) / kSpCols, p.groups);
+  const int zmax = p.zeta <= 8 ? 8 : 32;
+  const size_t lds = (size_t)p.s * kSpCols * sizeof(TAcc) + (size_t)kSpThreads * zmax * 2 + 64 +
+                     kSpThreads * 4;
+  TAcc* part = static_cast<TAcc*>(p.partial);
+  if (zmax == 8) {
+    set_lds_limit((const void*)sparse_kernel<TIn, TAcc, 8>);
+    sparse_kernel<TIn, TAcc, 8><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.zeta, p.seed, p.groups, part);
+  } else {
+    set_lds_limit((const void*)sparse_kernel<TIn, TAcc, 32>);
+    sparse_kernel<TIn, TAcc, 32><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.zeta, p.seed, p.groups, part);
+  }
+  return hipGetLastError();
+}
+
+size_t sparse_lds_bytes(int s, int zeta, int acc) {
+  const int zmax = zeta <= 8 ? 8 : 32;
+  return (size_t)s * kSpCols * (acc == NSK_F64 ? 8 : 4) + (size_t)kSpThreads * zmax * 2 + 64 + kSpThreads * 4;
+}
+
+size_t gauss_lds_bytes(int s, int N, int dtype) {
+  const int sp = (s + 15) & ~15, np = (N + 15) & ~15;
+  return (size_t)(sp + np) * kGK * (dtype == NSK_F8E4M3 ? 1 : 2);
+}
+
+int gauss_tiles_per_wave(int s, int N) {
+  const int sp = (s + 15) / 16, np = (N + 15) / 16;
+  return (sp * np + 3) / 4;
+}
+
+static hipError_t gauss_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
+  const int64_t ksteps = (p.m + kGK - 1) / kGK;
+  const int per = (int)((ksteps + p.groups - 1) / p.groups);
+  const size_t lds = gauss_lds_bytes(p.s, p.N, op.dtype);
+  const int tpw = gauss_tiles_per_wave(p.s, p.N);
+  float* part = static_cast<float*>(p.partial);
+  const bool f8 = op.dtype == NSK_F8E4M3;
+#define NSK_GAUSS_CASE(TPWV)                                                                          \
+  if (tpw <= TPWV) {                                                                                  \
+    if (f8)                                                                                           \
+      gauss_kernel<true, TPWV><<<p.groups, kGThreads, lds, st>>>(op, p.m, p.N, p.s, p.seed, p.groups, per, part); \
+    else                                                                                              \
+      gauss_kernel<false, TPWV><<<p.groups, kGThreads, lds, st>>>(op, p.m, p.N, p.s, p.seed, p.groups, per, part); \
+    return hipGetLastError();                                                                         \
+  }
+  NSK_GAUSS_CASE(8)
+  NSK_GAUSS_CASE(16)
+  NSK_GAUSS_CASE(32)
+  NSK_GAUSS_CASE(kGMaxTiles)
+#undef NSK_GAUSS_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st) {
+  if (p.kind == NSK_SRHT) {
+    if (next_pow2(p.m) <= 64) {
+      if (op.dtype == NSK_F64)
+        srht_small_kernel<double><<<p.s, 64, 0, st>>>(op, p.m, p.N, p.s, p.seed, p.rows, (double*)p.partial);
+      else
+        srht_small_kernel<float><<<p.s, 64, 0, st>>>(op, p.m, p.N, p.s, p.seed, p.rows, (double*)p.partial);
+      return hipGetLastError();
+    }
+    if (op.dtype == NSK_F64)
+      return p.acc == NSK_F64 ? srht_dispatch<double, double>(op, p, st) : srht_dispatch<double, float>(op, p, st);
+    return p.acc == NSK_F64 ? srht_dispatch<float, double>(op, p, st) : srht_dispatch<float, float>(op, p, st);
+  }
+  if (p.kind == NSK_SPARSE_SIGN) {
+    if (op.dtype == NSK_F64)
+      return p.acc == NSK_F64 ? sparse_dispatch<double, double>(op, p, st) : sparse_dispatch<double, float>(op, p, st);
+    return p.acc == NSK_F64 ? sparse_dispatch<float, double>(op, p, st) : sparse_dispatch<float, float>(op, p, st);
+  }
+  return gauss_dispatch(op, p, st);
+}
+
+// ================================================================================ reduce
+template <typename TP>
+__global__ void reduce_kernel(Operand op, const TP* __restrict__ partial, int groups, int s, int N,
+                              double scale, int kind, double* __restrict__ sa_rm, int64_t ld_rm,
+                              double* __restrict__ sa_cm, int64_t ld_cm) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)s * N) return;
+  const int i = (int)(idx / N), c = (int)(idx % N);
+  double acc = 0;
+  for (int g = 0; g < groups; ++g) acc += (double)partial[(size_t)g * s * N + idx];
+  double sc = scale;
+  if (kind == NSK_GAUSSIAN && op.dtype == NSK_F8E4M3) sc = ldexp(sc, column_exp(op, c));
+  acc *= sc;
+  if (sa_rm) sa_rm[(size_t)i * ld_rm + c] = acc;
+  if (sa_cm) sa_cm[(size_t)c * ld_cm + i] = acc;
+}
+
+hipError_t launch_reduce(const Operand& op, const SketchPlan& p, double* sa_rm, int64_t ld_rm,
+                         double* sa_cm, int64_t ld_cm, hipStream_t st) {
+  double scale;
+  int groups = p.groups;
+  bool f64part = true;
+  if (p.kind == NSK_SRHT) {
+    scale = 1.0 / sqrt((double)p.s);
+    if (next_pow2(p.m) <= 64) groups = 1;
+    else f64part = p.acc == NSK_F64;
+  } else if (p.kind == NSK_SPARSE_SIGN) {
+    scale = 1.0 / sqrt((double)p.zeta);
+    f64part = p.acc == NSK_F64;
+  } else {
+    scale = 1.0 / sqrt((double)p.s);
+    f64part = false;
+  }
+  const int64_t total = (int64_t)p.s * p.N;
+  const int threads = 256;
+  const unsigned blocks = (unsigned)((total + threads - 1) / threads);
+  if (f64part)
+    reduce_kernel<double><<<blocks, threads, 0, st>>>(op, (const double*)p.partial, groups, p.s, p.N, scale,
+                                                      p.kind, sa_rm, ld_rm, sa_cm, ld_cm);
+  else
+    reduce_kernel<float><<<blocks, threads, 0, st>>>(op, (const float*)p.partial, groups, p.s, p.N, scale,
+                                                     p.kind, sa_rm, ld_rm, sa_cm, ld_cm);
+  return hipGetLastError();
+}
+
+// =============================================================================== draws
+__global__ void draw_signs_kernel(uint64_t seed, int64_t m, int8_t* d) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const uint32_t w = word(philox(seed, (uint64_t)(j >> 7), 0, kSigns), (uint32_t)((j >> 5) & 3));
+  d[j] = ((w >> (j & 31)) & 1u) ? -1 : 1;
+}
+
+template <int ZMAX>
+__global__ void draw_sparse_kernel(uint64_t seed, int64_t m, int s, int zeta, int32_t* rows, int8_t* signs) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  int rw[ZMAX];
+  uint32_t nb;
+  sparse_column<ZMAX>(seed, (uint64_t)j, s, zeta, rw, nb);
+#pragma unroll
+  for (int q = 0; q < ZMAX; ++q)
+    if (q < zeta) {
+      rows[j * zeta + q] = rw[q];
+      signs[j * zeta + q] = ((nb >> q) & 1u) ? -1 : 1;
+    }
+}
+
+__global__ void draw_gauss_kernel(uint64_t seed, int s, int64_t j0, int64_t j1, int dtype, float* G) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ncol = j1 - j0;
+  const int q = (int)(w / ncol);
+  const int64_t cc = w % ncol;
+  if (4 * q >= s) return;
+  const Words r = philox(seed, (uint64_t)(j0 + cc), (uint32_t)q, kGauss);
+  float g[4];
+  box_muller(r.w[0], r.w[1], g[0], g[1]);
+  box_muller(r.w[2], r.w[3], g[2], g[3]);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int i = 4 * q + h;
+    if (i < s) {
+      float v = g[h];
+      if (dtype == NSK_BF16) v = bf16_round(v);
+      else if (dtype == NSK_F8E4M3) v = e4m3_round(v);
+      G[(size_t)i * ncol + cc] = v;
+    }
+  }
+}
+
+hipError_t launch_draw_signs(uint64_t seed, int64_t m, int8_t* d, hipStream_t st) {
+  draw_signs_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(seed, m, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_draw_sparse(uint64_t seed, int64_t m, int s, int zeta, int32_t* rows, int8_t* signs,
+                              hipStream_t st) {
+  if (zeta <= 8)
+    draw_sparse_kernel<8><<<(unsigned)((m + 255) / 256), 256, 0, st>>>(seed, m, s, zeta, rows, signs);
+  else
+    draw_sparse_kernel<32><<<(unsigned)((m + 255) / 256), 256, 0, st>>>(seed, m, s, zeta, rows, signs);
+  return hipGetLastError();
+}
+
+hipError_t launch_draw_gauss(uint64_t seed, int s, int64_t j0, int64_t j1, int dtype, float* G, hipStream_t st) {
+  const int64_t total = (int64_t)((s + 3) / 4) * (j1 - j0);
+  draw_gauss_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(seed, s, j0, j1, dtype, G);
+  return hipGetLastError();
+}
+
+}  // namespace nsk

@@ -1,0 +1,273 @@
+"""Parity of the HIP path with the FP64 oracle, element by element, on seeded inputs.
+
+Tolerances: sketches with FP64 accumulation agree with the oracle's FP64 product to
+rounding (1e-12 relative); plain-FP32 and narrow-operand sketches to the FP32 bound (1e-4
+relative, the spec FP32 tolerance).  Trailing vectors agree to
+max(1e-10, sqrt(N) u kappa_gap) with kappa_gap = sigma_1 / (sigma_{N-k} - sigma_{N-k+1})
+of the oracle's SA (the conditioning floor of the vector), and residual
+ratios to 1e-10 (FP64 arithmetic) or 1e-4 (FP32 arithmetic).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import draws, method, metrics, operators
+from oracle.precision import round_bf16, round_e4m3
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+DEV = "cuda:0"
+
+
+def t(x, dtype=None):
+    return torch.tensor(np.ascontiguousarray(x), device=DEV, dtype=dtype)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def vec_tol(sigma, k, u=U):
+    N = sigma.size
+    kappa = sigma[0] / max(sigma[N - k - 1] - sigma[N - k], 1e-300)
+    return max(1e-10, math.sqrt(N) * u * kappa)
+
+
+# ---------------------------------------------------------------------------- draws
+def test_device_signs_and_sparse_bit_exact(lib):
+    d = lib.draw_signs_device(3, 100_003).cpu().numpy()
+    assert np.array_equal(d, draws.signs(3, 100_003))
+    for s, zeta in ((804, 8), (40, 3), (64, 32)):
+        rows, sg = lib.draw_sparse_device(4, 20_001, s, zeta)
+        r2, s2 = draws.sparse(4, 20_001, s, zeta)
+        assert np.array_equal(rows.cpu().numpy(), r2) and np.array_equal(sg.cpu().numpy(), s2)
+
+
+def test_device_gaussian_matches_oracle_box_muller(lib):
+    s, j0, j1 = 203, 17, 2017
+    g = lib.draw_gaussian_device(5, s, j0, j1, "f32").cpu().numpy().astype(np.float64)
+    ref = draws.gaussian_block(5, s, j0, j1)
+    assert np.max(np.abs(g - ref) / (1 + np.abs(ref))) < 2e-5
+    for fmt, rnd in (("bf16", round_bf16), ("e4m3", round_e4m3)):
+        gq = lib.draw_gaussian_device(5, s, j0, j1, fmt).cpu().numpy().astype(np.float64)
+        rq = rnd(ref)
+        mism = gq != rq
+        assert mism.mean() < 2e-3, (fmt, mism.mean())
+        # every mismatch is one rounding step of an FP32-vs-FP64 boundary case
+        assert np.all(np.abs(gq[mism] - rq[mism]) <= np.abs(rq[mism]) * 2.0 ** -2 + 2.0 ** -9)
+
+
+# ---------------------------------------------------------------------------- sketches
+SRHT_CASES = [
+    ("plain_fp64", 2000, 50, 200, np.float64),
+    ("ragged_fp32", 5003, 37, 150, np.float32),
+    ("tiny_m", 40, 9, 16, np.float64),            # m_p = 64: explicit-formula kernel
+    ("short_m", 100, 13, 40, np.float32),         # m_p = 128 < transform block
+    ("multi_block", 70_000, 21, 300, np.float32),
+    ("wide", 9000, 129, 1100, np.float64),        # s > 1024
+]
+
+
+@pytest.mark.parametrize("name,m,n,s,dt", SRHT_CASES)
+def test_srht_sketch_parity(lib, name, m, n, s, dt):
+    a = np.random.default_rng(hash(name) % 2 ** 32).standard_normal((m, n)).astype(dt)
+    SA = lib.sketch(t(a), "srht", s, 31).cpu().numpy()
+    ref = operators.sketch(a.astype(np.float64), "srht", s, 31)
+    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    SA32 = lib.sketch(t(a), "srht", s, 31, acc="f32").cpu().numpy()
+    assert rel(SA32, ref) < 1e-4
+
+
+@pytest.mark.parametrize("m,n,s,zeta,dt", [(5003, 37, 150, 8, np.float32), (20_000, 201, 804, 8, np.float32),
+                                           (3000, 30, 90, 3, np.float64), (4100, 17, 64, 16, np.float32)])
+def test_sparse_sketch_parity(lib, m, n, s, zeta, dt):
+    a = np.random.default_rng(m + n).standard_normal((m, n)).astype(dt)
+    SA = lib.sketch(t(a), "sparse", s, 77, zeta=zeta).cpu().numpy()
+    ref = operators.sketch(a.astype(np.float64), "sparse", s, 77, zeta=zeta)
+    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    SA32 = lib.sketch(t(a), "sparse", s, 77, zeta=zeta, acc="f32").cpu().numpy()
+    assert rel(SA32, ref) < 1e-4
+
+
+def test_sketch_column_blocks_equal_concatenation(lib):
+    M, _ = W.tls_matrix(m=9000, n=40)
+    Mt = t(M)
+    whole = lib.sketch(Mt, "sparse", 164, 3).cpu().numpy()
+    split = lib.sketch([Mt[:, :40].contiguous(), Mt[:, 40:].contiguous()], "sparse", 164, 3).cpu().numpy()
+    assert np.array_equal(whole, split)
+    strided = lib.sketch([Mt[:, :40], Mt[:, 40:]], "srht", 164, 3).cpu().numpy()
+    ref = operators.sketch(M.astype(np.float64), "srht", 164, 3)
+    assert rel(strided, ref) < 1e-12
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "e4m3"])
+def test_gaussian_sketch_parity(lib, fmt):
+    m, n, s = 6000, 45, 96
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((m, n)) * np.exp(rng.uniform(-2, 2, n))[None, :]
+    if fmt == "bf16":
+        at = t(a, torch.float64).to(torch.bfloat16)
+        stored = at.to(torch.float64).cpu().numpy()
+        SA = lib.sketch(at, "gauss", s, 12).cpu().numpy()
+    else:
+        e = np.floor(np.log2(448.0 / np.abs(a).max(axis=0))).astype(np.int8)
+        q = t(a * 2.0 ** e[None, :], torch.float64).to(torch.float8_e4m3fn)
+        stored = q.to(torch.float64).cpu().numpy() * 2.0 ** (-e[None, :].astype(np.float64))
+        SA = lib.sketch([(q, t(-e))], "gauss", s, 12).cpu().numpy()
+    ref = operators.sketch(stored, "gauss", s, 12, gauss_dtype=fmt)
+    assert rel(SA, ref) < 1e-4, rel(SA, ref)
+
+
+# ---------------------------------------------------------------------------- solves
+def test_plain_workload_trailing_vector(lib):
+    a, _, v = W.plain_matrix()
+    Vk, sk, info = lib.trailing_rsv(t(a), 1, kind="srht", s=200, seed=1, residual=True)
+    torch.cuda.synchronize()
+    vk_ref, sk_ref, sa, sig, V, sweeps = method.trailing_rsv(a, 1, "srht", 200, 1, return_all=True)
+    Vk = Vk.cpu().numpy()
+    assert metrics.sin_theta(vk_ref, Vk) <= vec_tol(sig, 1)
+    assert abs(float(sk[0]) - sk_ref[0]) <= 1e-14 * sig[0]
+    inf = lib.read_info(info)
+    assert inf.converged and inf.sweeps <= 30
+    assert abs(inf.sigma_max - sig[0]) <= 1e-13 * sig[0]
+    assert abs(inf.residual - np.linalg.norm(a @ Vk)) <= 1e-15 * np.linalg.norm(a)
+    # sign normalisation as the oracle: largest-magnitude entry positive
+    assert Vk[np.argmax(np.abs(Vk[:, 0])), 0] > 0
+
+
+@pytest.mark.parametrize("kind,dt,acc", [("sparse", np.float32, "f64"), ("srht", np.float32, "f64"),
+                                         ("sparse", np.float32, "f32"), ("srht", np.float64, "f64")])
+def test_tls_trailing_vector_and_residual_ratio(lib, kind, dt, acc):
+    M, _ = W.tls_matrix(m=30_000, n=60, dtype=dt)
+    s = 4 * 61
+    Vk, sk, info = lib.trailing_rsv(t(M), 1, kind=kind, s=s, seed=8, acc=acc)
+    torch.cuda.synchronize()
+    M64 = M.astype(np.float64)
+    vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(M64, 1, kind, s, 8, return_all=True)
+    u = U if acc == "f64" else 2.0 ** -24
+    err = metrics.sin_theta(vk_ref, Vk.cpu().numpy())
+    assert err <= max(vec_tol(sig, 1, u), 1e-10 if acc == "f64" else 1e-4), err
+    w_opt, _, _ = metrics.trailing_exact(M64, 1)
+    r_gpu = metrics.residual_ratio(M64, Vk.cpu().numpy(), w_opt)
+    r_ref = metrics.residual_ratio(M64, vk_ref, w_opt)
+    assert abs(r_gpu - r_ref) <= (1e-10 if acc == "f64" else 1e-4)
+
+
+def test_planted_near_null_subspace_k4(lib):
+    a, vp = W.planted_matrix(20_000, 64, seed=(4, 1))
+    Vk, sk, _ = lib.trailing_rsv(t(a), 4, kind="srht", s=256, seed=3)
+    torch.cuda.synchronize()
+    vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a.astype(np.float64), 4, "srht", 256, 3, return_all=True)
+    assert metrics.sin_theta(vk_ref, Vk.cpu().numpy()) <= vec_tol(sig, 4)
+    assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-9, atol=1e-13 * sig[0])
+
+
+@pytest.mark.parametrize("m,n,k,s,kind", [(64, 16, 16, 64, "srht"), (300, 1, 1, 8, "sparse"),
+                                          (1000, 8, 3, 1000, "srht"), (513, 5, 2, 10, "sparse")])
+def test_edge_shapes(lib, m, n, k, s, kind):
+    a = np.random.default_rng(m).standard_normal((m, n))
+    Vk, sk, _ = lib.trailing_rsv(t(a), k, kind=kind, s=s, seed=2)
+    torch.cuda.synchronize()
+    vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a, k, kind, s, 2, return_all=True)
+    if k < n:
+        assert metrics.sin_theta(vk_ref, Vk.cpu().numpy()) <= vec_tol(sig, k)
+    else:
+        assert np.abs(Vk.cpu().numpy().T @ Vk.cpu().numpy() - np.eye(n)).max() < 1e-13
+    assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-10, atol=1e-14 * sig[0])
+
+
+def test_nonconvergence_flag_and_nan_propagation(lib):
+    M, _ = W.tls_matrix(m=5000, n=40, dtype=np.float64)
+    _, _, info = lib.trailing_rsv(t(M), 1, kind="sparse", s=164, seed=1, max_sweeps=1)
+    torch.cuda.synchronize()
+    inf = lib.read_info(info)
+    assert inf.sweeps == 1 and not inf.converged
+    M[17, 3] = np.nan
+    Vk, sk, _ = lib.trailing_rsv(t(M), 1, kind="sparse", s=164, seed=1)
+    torch.cuda.synchronize()
+    assert not np.isfinite(sk.cpu().numpy()).all() or not np.isfinite(Vk.cpu().numpy()).all()
+
+
+def test_deterministic_bitwise(lib):
+    M, _ = W.tls_matrix(m=40_000, n=100)
+    Mt = t(M)
+    a = lib.trailing_rsv(Mt, 1, kind="sparse", s=404, seed=5)
+    b = lib.trailing_rsv(Mt, 1, kind="sparse", s=404, seed=5)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    c = lib.sketch(Mt, "srht", 404, 5)
+    d = lib.sketch(Mt, "srht", 404, 5)
+    assert torch.equal(c, d)
+
+
+def test_residual_entry_point(lib):
+    a = np.random.default_rng(3).standard_normal((50_001, 33)).astype(np.float32)
+    v = np.linalg.qr(np.random.default_rng(4).standard_normal((33, 3)))[0]
+    r = float(lib.residual(t(a), t(v)))
+    ref = np.linalg.norm(a.astype(np.float64) @ v)
+    assert abs(r - ref) <= 1e-13 * ref
+
+
+# ---------------------------------------------------------------------------- TLS + grad
+def test_tls_solution_and_gradient(lib):
+    m, n, s = 3000, 30, 124
+    M, _ = W.tls_matrix(m=m, n=n, seed=21, dtype=np.float64)
+    xt = W.tls_target(n)
+    x, state, _ = lib.tls_solve(t(M[:, :n]), t(M[:, n]), kind="sparse", s=s, seed=6)
+    grad, x_ref, _ = method.tls_grad(M, xt, "sparse", s, 6)
+    torch.cuda.synchronize()
+    assert rel(x.cpu().numpy(), x_ref) < 1e-10
+    gx = 2.0 * (x - t(xt))
+    dA, db = lib.tls_backward(state, m, n, gx, kind="sparse", s=s, seed=6, out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    g_gpu = np.hstack([dA.cpu().numpy(), db.cpu().numpy()[:, None]])
+    assert rel(g_gpu, grad) < 1e-10, rel(g_gpu, grad)
+
+
+def test_tls_gradient_srht_kind(lib):
+    m, n, s = 2000, 12, 52
+    M, _ = W.tls_matrix(m=m, n=n, seed=22, dtype=np.float64)
+    xt = W.tls_target(n, seed=9)
+    x, state, _ = lib.tls_solve(t(M[:, :n]), t(M[:, n]), kind="srht", s=s, seed=7)
+    grad, x_ref, _ = method.tls_grad(M, xt, "srht", s, 7)
+    gx = 2.0 * (x - t(xt))
+    dA, db = lib.tls_backward(state, m, n, gx, kind="srht", s=s, seed=7, out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    g_gpu = np.hstack([dA.cpu().numpy(), db.cpu().numpy()[:, None]])
+    assert rel(x.cpu().numpy(), x_ref) < 1e-10
+    assert rel(g_gpu, grad) < 1e-10
+
+
+def test_autograd_function(lib):
+    m, n, s = 4000, 20, 84
+    M, _ = W.tls_matrix(m=m, n=n, seed=23, dtype=np.float64)
+    xt = W.tls_target(n, seed=4)
+    A = t(M[:, :n]).requires_grad_(True)
+    b = t(M[:, n]).requires_grad_(True)
+    x = lib.TLSSketch.apply(A, b, s, 10, "sparse", 8)
+    loss = ((x - t(xt)) ** 2).sum()
+    loss.backward()
+    grad, _, lref = method.tls_grad(M, xt, "sparse", s, 10)
+    assert abs(float(loss) - lref) <= 1e-10 * lref
+    g = np.hstack([A.grad.cpu().numpy(), b.grad.cpu().numpy()[:, None]])
+    assert rel(g, grad) < 1e-10
+
+
+# ---------------------------------------------------------------------------- batched
+def test_batched_matches_single_instances(lib):
+    shapes = [(5000, 16), (12_345, 40), (30_000, 100), (8192, 9), (20_001, 64), (7000, 33)]
+    As = [W.planted_matrix(m, n, seed=(4, 100 + i))[0] for i, (m, n) in enumerate(shapes)]
+    ks = [4 if n > 8 else 2 for _, n in shapes]
+    ss = [4 * n for _, n in shapes]
+    seeds = [1000 + i for i in range(len(shapes))]
+    outs = lib.trailing_rsv_batched([t(a) for a in As], ks, ss, seeds)
+    torch.cuda.synchronize()
+    for a, (Vk, sk, info), k, s, seed in zip(As, outs, ks, ss, seeds):
+        vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a.astype(np.float64), k, "srht", s, seed,
+                                                             return_all=True)
+        assert metrics.sin_theta(vk_ref, Vk.cpu().numpy()) <= vec_tol(sig, k)
+        assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-9, atol=1e-13 * sig[0])
+        assert lib.read_info(info).converged

@@ -1,0 +1,117 @@
+"""Host-side checks of the HIP library (no GPU): it loads, exports every declared symbol,
+its host draw hooks equal the oracle's independent implementation bit for bit, and its
+argument validation rejects what the header says it rejects."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2206_00975_amd as nsk
+from oracle import draws
+from oracle.philox import block
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(nsk.LIB_PATH):
+        pytest.fail("libnsk.so is not built (run __graft_entry__.build())")
+    return nsk.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "nsk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nsk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(nsk.EXPORTS)
+
+
+def test_version_and_status_strings(lib):
+    assert lib.nsk_version() >= 10000
+    for code in range(6):
+        assert lib.nsk_status_str(code).decode()
+
+
+@pytest.mark.parametrize("seed,idx,sub,stream", [(0, 0, 0, 0), (7, 123456789, 3, 2), (2 ** 64 - 1, 2 ** 40 + 5, 9, 5)])
+def test_host_philox_equals_oracle(lib, seed, idx, sub, stream):
+    got = nsk.philox(seed, idx, sub, stream)
+    ref = [int(x) for x in block(seed, idx, sub, stream)]
+    assert got == ref
+
+
+@pytest.mark.parametrize("m", [1, 127, 128, 1000, 65537])
+def test_host_signs_bit_exact(lib, m):
+    assert np.array_equal(nsk.draw_signs(11, m), draws.signs(11, m))
+
+
+@pytest.mark.parametrize("m,s", [(2000, 200), (100_000, 804), (1 << 17, 1024), (16, 16), (3, 2)])
+def test_host_srht_rows_bit_exact(lib, m, s):
+    assert np.array_equal(nsk.draw_srht_rows(5, m, s), draws.srht_rows(5, draws.next_pow2(m), s))
+
+
+@pytest.mark.parametrize("m,s,zeta", [(5000, 804, 8), (3000, 40, 3), (777, 64, 32), (100, 8, 8)])
+def test_host_sparse_bit_exact(lib, m, s, zeta):
+    rows, sg = nsk.draw_sparse(9, m, s, zeta)
+    r2, s2 = draws.sparse(9, m, s, zeta)
+    assert np.array_equal(rows, r2) and np.array_equal(sg, s2)
+
+
+def test_workspace_query_validates(lib):
+    d = nsk.make_desc("srht", s=200, seed=1)
+    assert lib.nsk_workspace_bytes(2000, 50, 1, ctypes.byref(d)) > 0
+    bad = [
+        (2000, 50, 0, nsk.make_desc("srht", s=200)),      # k < 1
+        (2000, 50, 51, nsk.make_desc("srht", s=200)),     # k > N
+        (2000, 50, 1, nsk.make_desc("srht", s=50)),       # s <= N
+        (100, 50, 1, nsk.make_desc("srht", s=200)),       # s > m
+        (40, 50, 1, nsk.make_desc("srht", s=45)),         # m < N
+        (5000, 50, 1, nsk.make_desc("sparse", s=200, zeta=33)),
+        (5000, 50, 1, nsk.make_desc("sparse", s=200, zeta=0, acc=7)),
+        (5000, 2000, 1, nsk.make_desc("srht", s=4000)),   # N > 1024 / s > 2048
+    ]
+    for m, n, k, desc in bad:
+        assert lib.nsk_workspace_bytes(m, n, k, ctypes.byref(desc)) == 0
+
+
+def test_entry_points_reject_bad_arguments_before_device_work(lib):
+    fake = ctypes.c_void_p(0x1000)
+    op = (nsk.Operand * 1)(nsk.Operand(0x1000, nsk.F32, 0, 50, 50, None))
+    d = nsk.make_desc("srht", s=200, seed=1)
+    rc = lib.nsk_trailing_rsv(op, 1, 2000, 0, ctypes.byref(d), fake, fake, None, fake, 1 << 30, None)
+    assert rc == 1
+    rc = lib.nsk_trailing_rsv(op, 1, 2000, 1, ctypes.byref(d), fake, fake, None, fake, 16, None)
+    assert rc == 2                                                   # workspace too small
+    op_ld = (nsk.Operand * 1)(nsk.Operand(0x1000, nsk.F32, 0, 50, 49, None))
+    assert lib.nsk_sketch(op_ld, 1, 2000, ctypes.byref(d), fake, 50, fake, 1 << 30, None) == 1
+    op_bf = (nsk.Operand * 1)(nsk.Operand(0x1000, nsk.BF16, 0, 50, 50, None))
+    assert lib.nsk_sketch(op_bf, 1, 2000, ctypes.byref(d), fake, 50, fake, 1 << 30, None) == 5
+    g = nsk.make_desc("gauss", s=200, seed=1)
+    assert lib.nsk_sketch(op, 1, 2000, ctypes.byref(g), fake, 50, fake, 1 << 30, None) == 5
+    ops5 = (nsk.Operand * 5)(*[nsk.Operand(0x1000, nsk.F32, 0, 10, 10, None)] * 5)
+    assert lib.nsk_sketch(ops5, 5, 2000, ctypes.byref(d), fake, 50, fake, 1 << 30, None) == 1
+    mixed = (nsk.Operand * 2)(nsk.Operand(0x1000, nsk.F32, 0, 10, 10, None), nsk.Operand(0x1000, nsk.F64, 0, 1, 1, None))
+    assert lib.nsk_sketch(mixed, 2, 2000, ctypes.byref(d), fake, 11, fake, 1 << 30, None) == 1
+    assert lib.nsk_tls_backward(ctypes.byref(g), 2000, 10, fake, fake, fake, 10, fake, nsk.F32, fake, 1 << 30,
+                                None) == 5
+
+
+def test_batched_plan_and_tuner_table(lib):
+    shapes = [(5000, 16), (20000, 64), (100_000, 256)]
+    ks, ss = [4] * 3, [4 * n for _, n in shapes]
+    assert nsk.batched_workspace_bytes(shapes, ks, ss) > 0
+    assert nsk.batched_workspace_bytes([(5000, 300)], [4], [1200]) == 0       # n > 256
+    nsk.tune_clear()
+    assert nsk.tune_lookup(256) == 16 and nsk.tune_lookup(16) == 4
+    nsk.tune_set(256, 32)
+    assert nsk.tune_lookup(250) == 32
+    nsk.tune_clear()
