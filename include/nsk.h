@@ -185,11 +185,13 @@ int nsk_tune_clear(void);
 /*
  * Total least squares with one right-hand side (Section 4, Golub-Van Loan): the trailing
  * right singular vector v of the sketched [A | b] (N = n + 1 columns) gives
- * x = -v(1:n) / v(N).  `state` (device, nsk_tls_state_bytes(n, s) bytes) receives what
- * the backward pass needs: SA, the full V and sigma of SA, v and x.
- * x (device): n FP64.
+ * x = -v(1:n) / v(N).  `state` (device, nsk_tls_state_bytes(n, s, d->max_sweeps) bytes)
+ * receives what the backward pass needs: SA, the singular values, v, x and the Jacobi
+ * rotation log (V is rebuilt from it only where the backward needs it).  Built for
+ * N = n + 1 <= 320 and s <= 4096 (NSK_EUNSUPPORTED otherwise).
+ * x (device): n FP64.  With NSK_FLAG_RESIDUAL, info->residual = |[A | b] v|_F.
  */
-size_t nsk_tls_state_bytes(int64_t n, int64_t s);
+size_t nsk_tls_state_bytes(int64_t n, int64_t s, int32_t max_sweeps);
 int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_desc* d,
                   double* x, void* state, size_t state_bytes, nsk_info* info, void* ws,
                   size_t ws_bytes, void* stream);
@@ -209,6 +211,19 @@ int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const n
 int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state, const double* gx,
                      void* dA, int64_t ldda, void* db, int32_t out_dtype, void* ws, size_t ws_bytes,
                      void* stream);
+
+/*
+ * Stage profiler (tracing aid).  nsk_profile_enable(max_calls) creates
+ * NSK_PROF_STAGES+1 HIP events for each of up to max_calls subsequent calls of
+ * nsk_trailing_rsv / nsk_tls_solve / nsk_sketch and records them on the call's stream at
+ * the stage boundaries (0 host draws and uploads, 1 sketch kernel, 2 partial reduce,
+ * 3 QR + Jacobi, 4 post-processing: residual or TLS extraction).  nsk_profile_read waits
+ * for the recorded events and returns the summed milliseconds per stage and the number of
+ * profiled calls; nsk_profile_enable(0) stops recording and frees the events.
+ */
+#define NSK_PROF_STAGES 5
+int nsk_profile_enable(int32_t max_calls);
+int nsk_profile_read(double* ms /* NSK_PROF_STAGES */, int32_t* calls);
 
 /*
  * Draw hooks: the random objects behind S, bit-exact between host and device.

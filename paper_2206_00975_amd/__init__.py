@@ -87,11 +87,13 @@ _SIGS = {
     "nsk_tune_lookup": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "nsk_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "nsk_tune_clear": (ctypes.c_int, []),
-    "nsk_tls_state_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64]),
+    "nsk_tls_state_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]),
     "nsk_tls_solve": (ctypes.c_int, [ctypes.POINTER(Operand), ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(Desc),
                                      _P, _P, ctypes.c_size_t, _P, _P, ctypes.c_size_t, _P]),
     "nsk_tls_backward": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.c_int64, ctypes.c_int64, _P, _P, _P,
                                         ctypes.c_int64, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "nsk_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "nsk_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "nsk_philox": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                   ctypes.POINTER(ctypes.c_uint32)]),
     "nsk_draw_signs": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, _P]),
@@ -296,15 +298,19 @@ def tune_clear():
 
 
 # ------------------------------------------------------------------------------- TLS
-def tls_solve(A, b=None, kind="sparse", s=None, seed=0, zeta=8, acc="f64", max_sweeps=0):
+def tls_solve(A, b=None, kind="sparse", s=None, seed=0, zeta=8, acc="f64", max_sweeps=0, residual=False,
+              ws=None, state=None):
     """Sketched TLS: returns ``(x, state, info)``; ``state`` feeds :func:`tls_backward`."""
     lib = load()
     blocks = [A] if b is None else [A, b.reshape(-1, 1) if b.dim() == 1 else b]
     ops, nb, m, N, dev, keep = _blocks(blocks)
     n = N - 1
-    d = make_desc(kind, s, seed, zeta, acc, max_sweeps)
-    ws = _ws(lib.nsk_workspace_bytes(m, N, 1, ctypes.byref(d)), dev)
-    state = _ws(lib.nsk_tls_state_bytes(n, s), dev)
+    d = make_desc(kind, s, seed, zeta, acc, max_sweeps, flags=FLAG_RESIDUAL if residual else 0)
+    need = lib.nsk_workspace_bytes(m, N, 1, ctypes.byref(d))
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    if state is None:
+        state = _ws(lib.nsk_tls_state_bytes(n, s, max_sweeps), dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
     _check("nsk_tls_solve", lib.nsk_tls_solve(ops, nb, m, ctypes.byref(d), x.data_ptr(), state.data_ptr(),
@@ -345,6 +351,22 @@ class TLSSketch(torch.autograd.Function):
         m, n, kind, s, seed, zeta, adt, bdt = ctx.meta
         dA, db = tls_backward(state, m, n, gx, kind=kind, s=s, seed=seed, zeta=zeta, out_dtype=adt)
         return dA, db.to(bdt), None, None, None, None
+
+
+# ------------------------------------------------------------------------ profiler
+PROF_STAGES = ("draws", "sketch", "reduce", "svd", "post")
+
+
+def profile_enable(max_calls):
+    _check("nsk_profile_enable", load().nsk_profile_enable(max_calls))
+
+
+def profile_read():
+    """Summed milliseconds per stage over the profiled calls and the call count."""
+    ms = (ctypes.c_double * len(PROF_STAGES))()
+    calls = ctypes.c_int32()
+    _check("nsk_profile_read", load().nsk_profile_read(ms, ctypes.byref(calls)))
+    return dict(zip(PROF_STAGES, list(ms))), calls.value
 
 
 # ----------------------------------------------------------------------- draw hooks

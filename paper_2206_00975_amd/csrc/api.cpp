@@ -22,7 +22,8 @@ size_t batch_inst_bytes();
 size_t batch_tile_bytes();
 void batch_fill_inst(void* dst, const Operand& op, int64_t m, int N, int s, int k, int groups, int ctiles,
                      int max_sweeps, uint64_t seed, const int* rows, void* partial, double* sa_cm, double* R,
-                     double* V, double* sigma, int* order, double* Vk, double* sigma_k, nsk_info* info);
+                     double2* log, double* sigma, int* order, double* colnorm, void* jres, double* Vk,
+                     double* sigma_k, nsk_info* info);
 void batch_fill_tile(void* dst, int inst, int ctile, int g);
 int tuned_rows_per_tile(int n, int64_t m, int dtype, int acc);
 }  // namespace nsk
@@ -59,25 +60,46 @@ int plan_groups(const nsk_desc* d, int64_t m, int64_t N) {
 }
 
 struct Layout {
-  size_t rows, partial, sa, R, V, sigma, order, res, work, total;
+  size_t rows, partial, sa, R, V, log, sigma, order, colnorm, jres, res, work, total;
 };
 
 Layout layout(int64_t m, int64_t N, const nsk_desc* d) {
   Layout L{};
   const int64_t s = d->s;
   const int groups = plan_groups(d, m, N);
+  const bool fast = svd_fast_path((int)s, (int)N);
   size_t off = 0;
   L.rows = off;    off = align_up(off + (size_t)s * 4);
   L.partial = off; off = align_up(off + (size_t)groups * s * N * 8);
   L.sa = off;      off = align_up(off + (size_t)s * N * 8);
-  L.R = off;       off = align_up(off + (size_t)N * N * 8);
-  L.V = off;       off = align_up(off + (size_t)N * N * 8);
+  L.R = off;       off = align_up(off + svd_work_R_bytes((int)s, (int)N));
+  L.V = off;       off = align_up(off + (fast ? 0 : (size_t)N * N * 8));
+  L.log = off;     off = align_up(off + svd_work_log_bytes((int)s, (int)N, dflt_sweeps(d)));
   L.sigma = off;   off = align_up(off + (size_t)N * 8);
   L.order = off;   off = align_up(off + (size_t)N * 4);
+  L.colnorm = off; off = align_up(off + (size_t)N * 8);
+  L.jres = off;    off = align_up(off + 64);
   L.res = off;     off = align_up(off + (size_t)kResParts * 8);
   L.work = off;    off = align_up(off + (size_t)(2 * s + 2 * N) * 8);
   L.total = off;
   return L;
+}
+
+SvdPlan svd_plan(const nsk_desc* d, int64_t N, unsigned char* w, const Layout& L) {
+  SvdPlan sp{};
+  sp.s = (int)d->s;
+  sp.N = (int)N;
+  sp.k = 1;
+  sp.max_sweeps = dflt_sweeps(d);
+  sp.sa = reinterpret_cast<double*>(w + L.sa);
+  sp.R = reinterpret_cast<double*>(w + L.R);
+  sp.V = reinterpret_cast<double*>(w + L.V);
+  sp.log = reinterpret_cast<double2*>(w + L.log);
+  sp.sigma = reinterpret_cast<double*>(w + L.sigma);
+  sp.order = reinterpret_cast<int*>(w + L.order);
+  sp.colnorm = reinterpret_cast<double*>(w + L.colnorm);
+  sp.jres = reinterpret_cast<JacobiResult*>(w + L.jres);
+  return sp;
 }
 
 int check_desc(const nsk_desc* d, int64_t m, int64_t N) {
@@ -169,17 +191,43 @@ SketchPlan make_plan(const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws,
 
 int dev(hipError_t e) { return e == hipSuccess ? NSK_OK : NSK_EDEVICE; }
 
+// ------------------------------------------------------------------ stage profiler
+struct Profiler {
+  std::vector<hipEvent_t> ev;  // (NSK_PROF_STAGES + 1) per call
+  int max_calls = 0;
+  int calls = 0;
+  int cur = -1;                // call being recorded, -1 if none
+};
+Profiler g_prof;
+
+void prof_begin(hipStream_t st) {
+  g_prof.cur = -1;
+  if (g_prof.max_calls == 0 || g_prof.calls >= g_prof.max_calls) return;
+  g_prof.cur = g_prof.calls++;
+  (void)hipEventRecord(g_prof.ev[(size_t)g_prof.cur * (NSK_PROF_STAGES + 1)], st);
+}
+
+void prof_mark(int stage, hipStream_t st) {  // end of stage `stage`
+  if (g_prof.cur < 0) return;
+  (void)hipEventRecord(g_prof.ev[(size_t)g_prof.cur * (NSK_PROF_STAGES + 1) + stage + 1], st);
+}
+
 // Sketch + reduce; SA written column-major into the workspace and optionally row-major out.
 int run_sketch(const Operand& op, const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws, const Layout& L,
                double* sa_rm, int64_t ld_rm, hipStream_t st, SketchPlan& p) {
   p = make_plan(d, m, N, ws, L);
+  prof_begin(st);
   if (d->kind == NSK_SRHT) {
     const int rc = upload_rows(d->seed, m, d->s, reinterpret_cast<int*>(ws + L.rows), st);
     if (rc) return rc;
   }
+  prof_mark(0, st);
   int rc = dev(launch_sketch(op, p, st));
   if (rc) return rc;
-  return dev(launch_reduce(op, p, sa_rm, ld_rm, reinterpret_cast<double*>(ws + L.sa), d->s, st));
+  prof_mark(1, st);
+  rc = dev(launch_reduce(op, p, sa_rm, ld_rm, reinterpret_cast<double*>(ws + L.sa), d->s, st));
+  prof_mark(2, st);
+  return rc;
 }
 
 }  // namespace
@@ -216,7 +264,10 @@ int nsk_sketch(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_
   const Layout L = layout(m, N, d);
   if (ws_bytes < L.total) return NSK_EWORKSPACE;
   SketchPlan p;
-  return run_sketch(op, d, m, N, static_cast<unsigned char*>(ws), L, SA, ldsa, (hipStream_t)stream, p);
+  rc = run_sketch(op, d, m, N, static_cast<unsigned char*>(ws), L, SA, ldsa, (hipStream_t)stream, p);
+  prof_mark(3, (hipStream_t)stream);
+  prof_mark(4, (hipStream_t)stream);
+  return rc;
 }
 
 int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int64_t k, const nsk_desc* d,
@@ -233,25 +284,19 @@ int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int6
   unsigned char* w = static_cast<unsigned char*>(ws);
   SketchPlan p;
   if ((rc = run_sketch(op, d, m, N, w, L, nullptr, 0, st, p))) return rc;
-  SvdPlan sp{};
-  sp.s = (int)d->s;
-  sp.N = (int)N;
+  SvdPlan sp = svd_plan(d, N, w, L);
   sp.k = (int)k;
-  sp.max_sweeps = dflt_sweeps(d);
-  sp.sa = reinterpret_cast<double*>(w + L.sa);
-  sp.R = reinterpret_cast<double*>(w + L.R);
-  sp.V = reinterpret_cast<double*>(w + L.V);
-  sp.sigma = reinterpret_cast<double*>(w + L.sigma);
-  sp.order = reinterpret_cast<int*>(w + L.order);
   sp.Vk = Vk;
   sp.sigma_k = sigma_k;
   sp.info = info;
   if ((rc = dev(launch_svd(sp, st)))) return rc;
+  prof_mark(3, st);
   if ((d->flags & NSK_FLAG_RESIDUAL) && info) {
     if (N * k > kMaxResidualVec) return NSK_EUNSUPPORTED;
     const int64_t parts = std::min<int64_t>(kResParts, std::max<int64_t>(1, m / 256));
     rc = dev(launch_residual(op, m, Vk, (int)k, reinterpret_cast<double*>(w + L.res), (int)parts, nullptr, info, st));
   }
+  prof_mark(4, st);
   return rc;
 }
 
@@ -272,24 +317,27 @@ int nsk_residual(const nsk_operand* blocks, int32_t nblocks, int64_t m, const do
                              (hipStream_t)stream));
 }
 
-// TLS state layout: SA row-major (s x N), V (N x N col-major), sigma (N), order (N ints), x (n), v (N).
-static void tls_state_layout(int64_t n, int64_t s, size_t* o) {
+// TLS state layout (N = n + 1 <= 320): SA row-major (s x N), per-column singular values,
+// order, sorted singular values, trailing vector v, x, Jacobi result, rotation log.
+static void tls_state_layout(int64_t n, int64_t s, int max_sweeps, size_t* o) {
   const int64_t N = n + 1;
   size_t off = 0;
   o[0] = off; off = align_up(off + (size_t)s * N * 8);
-  o[1] = off; off = align_up(off + (size_t)N * N * 8);
-  o[2] = off; off = align_up(off + (size_t)N * 8);
-  o[3] = off; off = align_up(off + (size_t)N * 4);
-  o[4] = off; off = align_up(off + (size_t)n * 8);
-  o[5] = off; off = align_up(off + (size_t)N * 8);
-  o[6] = off;
+  o[1] = off; off = align_up(off + (size_t)N * 8);
+  o[2] = off; off = align_up(off + (size_t)N * 4);
+  o[3] = off; off = align_up(off + (size_t)N * 8);
+  o[4] = off; off = align_up(off + (size_t)N * 8);
+  o[5] = off; off = align_up(off + (size_t)n * 8);
+  o[6] = off; off = align_up(off + 64);
+  o[7] = off; off = align_up(off + svd_work_log_bytes((int)s, (int)N, max_sweeps));
+  o[8] = off;
 }
 
-size_t nsk_tls_state_bytes(int64_t n, int64_t s) {
-  if (n < 1 || s <= n + 1) return 0;
-  size_t o[7];
-  tls_state_layout(n, s, o);
-  return o[6];
+size_t nsk_tls_state_bytes(int64_t n, int64_t s, int32_t max_sweeps) {
+  if (n < 1 || s <= n + 1 || !svd_fast_path((int)s, (int)(n + 1)) || max_sweeps < 0) return 0;
+  size_t o[9];
+  tls_state_layout(n, s, max_sweeps ? max_sweeps : 30, o);
+  return o[8];
 }
 
 int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_desc* d, double* x, void* state,
@@ -300,35 +348,39 @@ int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const n
   if (rc) return rc;
   if ((rc = check_desc(d, m, N))) return rc;
   if (N < 2 || !x || !state || !ws) return NSK_EINVAL;
+  if (!svd_fast_path((int)d->s, (int)N)) return NSK_EUNSUPPORTED;
   const int64_t n = N - 1;
-  if (state_bytes < nsk_tls_state_bytes(n, d->s)) return NSK_EWORKSPACE;
+  if (state_bytes < nsk_tls_state_bytes(n, d->s, d->max_sweeps)) return NSK_EWORKSPACE;
   const Layout L = layout(m, N, d);
   if (ws_bytes < L.total) return NSK_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   unsigned char* w = static_cast<unsigned char*>(ws);
   unsigned char* S = static_cast<unsigned char*>(state);
-  size_t o[7];
-  tls_state_layout(n, d->s, o);
+  size_t o[9];
+  tls_state_layout(n, d->s, dflt_sweeps(d), o);
   SketchPlan p;
   if ((rc = run_sketch(op, d, m, N, w, L, reinterpret_cast<double*>(S + o[0]), N, st, p))) return rc;
-  SvdPlan sp{};
-  sp.s = (int)d->s;
-  sp.N = (int)N;
+  SvdPlan sp = svd_plan(d, N, w, L);
   sp.k = 1;
-  sp.max_sweeps = dflt_sweeps(d);
-  sp.sa = reinterpret_cast<double*>(w + L.sa);
-  sp.R = reinterpret_cast<double*>(w + L.R);
-  sp.V = reinterpret_cast<double*>(S + o[1]);
-  sp.sigma = reinterpret_cast<double*>(S + o[2]);
-  sp.order = reinterpret_cast<int*>(S + o[3]);
-  sp.Vk = nullptr;
+  sp.colnorm = reinterpret_cast<double*>(S + o[1]);
+  sp.order = reinterpret_cast<int*>(S + o[2]);
+  sp.sigma = reinterpret_cast<double*>(S + o[3]);
+  sp.Vk = reinterpret_cast<double*>(S + o[4]);
+  sp.jres = reinterpret_cast<JacobiResult*>(S + o[6]);
+  sp.log = reinterpret_cast<double2*>(S + o[7]);
   sp.sigma_k = nullptr;
   sp.info = info;
   if ((rc = dev(launch_svd(sp, st)))) return rc;
-  if ((rc = dev(launch_tls_extract((int)N, sp.V, sp.sigma, sp.order, reinterpret_cast<double*>(S + o[4]),
-                                   reinterpret_cast<double*>(S + o[5]), st))))
-    return rc;
-  return dev(hipMemcpyAsync(x, S + o[4], (size_t)n * 8, hipMemcpyDeviceToDevice, st));
+  prof_mark(3, st);
+  double* xs = reinterpret_cast<double*>(S + o[5]);
+  if ((rc = dev(launch_tls_extract((int)N, sp.Vk, xs, st)))) return rc;
+  if ((rc = dev(hipMemcpyAsync(x, xs, (size_t)n * 8, hipMemcpyDeviceToDevice, st)))) return rc;
+  if ((d->flags & NSK_FLAG_RESIDUAL) && info) {
+    const int64_t parts = std::min<int64_t>(kResParts, std::max<int64_t>(1, m / 256));
+    rc = dev(launch_residual(op, m, sp.Vk, 1, reinterpret_cast<double*>(w + L.res), (int)parts, nullptr, info, st));
+  }
+  prof_mark(4, st);
+  return rc;
 }
 
 int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state, const double* gx, void* dA,
@@ -336,7 +388,7 @@ int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state,
   const int64_t N = n + 1;
   int rc = check_desc(d, m, N);
   if (rc) return rc;
-  if (d->kind == NSK_GAUSSIAN) return NSK_EUNSUPPORTED;
+  if (d->kind == NSK_GAUSSIAN || !svd_fast_path((int)d->s, (int)N)) return NSK_EUNSUPPORTED;
   if (!state || !gx || !dA || !db || !ws || ldda < n) return NSK_EINVAL;
   if (out_dtype != NSK_F32 && out_dtype != NSK_F64) return NSK_EINVAL;
   const Layout L = layout(m, N, d);
@@ -344,14 +396,19 @@ int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state,
   hipStream_t st = (hipStream_t)stream;
   unsigned char* w = static_cast<unsigned char*>(ws);
   const unsigned char* S = static_cast<const unsigned char*>(state);
-  size_t o[7];
-  tls_state_layout(n, d->s, o);
+  size_t o[9];
+  tls_state_layout(n, d->s, dflt_sweeps(d), o);
   SketchPlan p = make_plan(d, m, N, w, L);
   if (d->kind == NSK_SRHT && (rc = upload_rows(d->seed, m, d->s, reinterpret_cast<int*>(w + L.rows), st))) return rc;
-  return dev(launch_tls_backward(p, m, reinterpret_cast<const double*>(S + o[0]),
-                                 reinterpret_cast<const double*>(S + o[1]), reinterpret_cast<const double*>(S + o[2]),
-                                 reinterpret_cast<const int*>(S + o[3]), reinterpret_cast<const double*>(S + o[4]),
-                                 gx, reinterpret_cast<double*>(w + L.work), dA, ldda, db, out_dtype, st));
+  TlsBack tb;
+  tb.sa_rm = reinterpret_cast<const double*>(S + o[0]);
+  tb.colnorm = reinterpret_cast<const double*>(S + o[1]);
+  tb.order = reinterpret_cast<const int*>(S + o[2]);
+  tb.v = reinterpret_cast<const double*>(S + o[4]);
+  tb.x = reinterpret_cast<const double*>(S + o[5]);
+  tb.jres = reinterpret_cast<const JacobiResult*>(S + o[6]);
+  tb.log = reinterpret_cast<const double2*>(S + o[7]);
+  return dev(launch_tls_backward(p, m, tb, gx, reinterpret_cast<double*>(w + L.work), dA, ldda, db, out_dtype, st));
 }
 
 // ------------------------------------------------------------------------------ batched
@@ -392,12 +449,14 @@ static int batch_plan(const nsk_problem* probs, int32_t count, const nsk_desc* b
     const nsk_problem& q = probs[i];
     B.inst_off[i] = off;
     const size_t s = (size_t)q.s, n = (size_t)q.n;
-    off = align_up(off + (size_t)B.groups[i] * s * n * 8);  // partial
-    off = align_up(off + s * n * 8);                        // sa
-    off = align_up(off + n * n * 8);                        // R
-    off = align_up(off + n * n * 8);                        // V
-    off = align_up(off + n * 8);                            // sigma
-    off = align_up(off + n * 4);                            // order
+    off = align_up(off + (size_t)B.groups[i] * s * n * 8);                      // partial
+    off = align_up(off + s * n * 8);                                            // sa
+    off = align_up(off + svd_work_R_bytes((int)s, (int)n));                     // R
+    off = align_up(off + svd_work_log_bytes((int)s, (int)n, dflt_sweeps(base)));  // log
+    off = align_up(off + n * 8);                                                // sigma
+    off = align_up(off + n * 4);                                                // order
+    off = align_up(off + n * 8);                                                // colnorm
+    off = align_up(off + 64);                                                   // jres
   }
   B.total = off;
   return NSK_OK;
@@ -455,14 +514,16 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
     size_t o = 0;
     void* partial = base_i + o; o = align_up(o + (size_t)B.groups[i] * s * n * 8);
     double* sa = reinterpret_cast<double*>(base_i + o); o = align_up(o + s * n * 8);
-    double* R = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * n * 8);
-    double* V = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * n * 8);
+    double* R = reinterpret_cast<double*>(base_i + o); o = align_up(o + svd_work_R_bytes((int)s, (int)n));
+    double2* lg = reinterpret_cast<double2*>(base_i + o); o = align_up(o + svd_work_log_bytes((int)s, (int)n, dflt_sweeps(base)));
     double* sig = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * 8);
-    int* order = reinterpret_cast<int*>(base_i + o);
+    int* order = reinterpret_cast<int*>(base_i + o); o = align_up(o + n * 4);
+    double* cn = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * 8);
+    void* jr = base_i + o;
     batch_fill_inst(hinst.data() + (size_t)i * batch_inst_bytes(), op, q.m, (int)q.n, (int)q.s, (int)q.k,
                     B.groups[i], (int)((q.n + 7) / 8), dflt_sweeps(base), q.seed,
-                    reinterpret_cast<const int*>(w + B.rows + rows_off[i]), partial, sa, R, V, sig, order, q.Vk,
-                    q.sigma_k, q.info);
+                    reinterpret_cast<const int*>(w + B.rows + rows_off[i]), partial, sa, R, lg, sig, order, cn, jr,
+                    q.Vk, q.sigma_k, q.info);
   }
   int t = 0;
   for (int oi = 0; oi < count; ++oi) {
@@ -491,6 +552,38 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
   if (rc) return rc;
   // host staging vectors die at return
   return dev(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------------------------ profiler
+int nsk_profile_enable(int32_t max_calls) {
+  if (max_calls < 0 || max_calls > 100000) return NSK_EINVAL;
+  for (hipEvent_t e : g_prof.ev) (void)hipEventDestroy(e);
+  g_prof.ev.clear();
+  g_prof.max_calls = 0;
+  g_prof.calls = 0;
+  g_prof.cur = -1;
+  if (max_calls == 0) return NSK_OK;
+  g_prof.ev.resize((size_t)max_calls * (NSK_PROF_STAGES + 1));
+  for (auto& e : g_prof.ev)
+    if (hipEventCreate(&e) != hipSuccess) return NSK_EDEVICE;
+  g_prof.max_calls = max_calls;
+  return NSK_OK;
+}
+
+int nsk_profile_read(double* ms, int32_t* calls) {
+  if (!ms || !calls) return NSK_EINVAL;
+  for (int st = 0; st < NSK_PROF_STAGES; ++st) ms[st] = 0;
+  *calls = g_prof.calls;
+  for (int c = 0; c < g_prof.calls; ++c) {
+    hipEvent_t* e = &g_prof.ev[(size_t)c * (NSK_PROF_STAGES + 1)];
+    if (hipEventSynchronize(e[NSK_PROF_STAGES]) != hipSuccess) return NSK_EDEVICE;
+    for (int st = 0; st < NSK_PROF_STAGES; ++st) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, e[st], e[st + 1]) != hipSuccess) return NSK_EDEVICE;
+      ms[st] += t;
+    }
+  }
+  return NSK_OK;
 }
 
 // ------------------------------------------------------------------------------ draws

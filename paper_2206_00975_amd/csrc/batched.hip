@@ -13,6 +13,7 @@
 #include "nsk_internal.hpp"
 #include "sketch_device.hpp"
 #include "svd_device.hpp"
+#include "svd_pipeline.hpp"
 
 namespace nsk {
 
@@ -24,10 +25,12 @@ struct BatchInst {
   const int* rows;
   void* partial;      // groups x s x N (TAcc)
   double* sa_cm;      // s x N column-major
-  double* R;
-  double* V;
+  double* R;          // fast-path R buffer
+  double2* log;       // rotation log
   double* sigma;
   int* order;
+  double* colnorm;
+  JacobiResult* jres;
   double* Vk;
   double* sigma_k;
   nsk_info* info;
@@ -82,15 +85,29 @@ __global__ __launch_bounds__(kSrhtThreads) void batched_kernel(const BatchInst* 
         I.sa_cm[(size_t)c * I.s + i] = a * scale;
       }
       __syncthreads();
-      svd_instance(I.sa_cm, I.s, I.N, I.k, I.max_sweeps, I.R, I.V, I.sigma, I.order, I.Vk, I.sigma_k, I.info,
-                   smem);
+      SvdWork w;
+      w.sa = I.sa_cm;
+      w.R = I.R;
+      w.log = I.log;
+      w.sigma = I.sigma;
+      w.order = I.order;
+      w.colnorm = I.colnorm;
+      w.jres = I.jres;
+      w.Vk = I.Vk;
+      w.sigma_k = I.sigma_k;
+      w.info = I.info;
+      w.s = I.s;
+      w.N = I.N;
+      w.k = I.k;
+      w.max_sweeps = I.max_sweeps;
+      svd_pipeline(w, smem);
     }
     __syncthreads();
   }
 }
 
 size_t batched_lds_bytes(int s_max, int n_max) {
-  const size_t a = srht_smem_bytes(s_max), b = svd_lds_bytes(s_max, n_max);
+  const size_t a = srht_smem_bytes(s_max), b = svd_fast_lds_bytes(s_max, n_max, kSrhtThreads / 64);
   return a > b ? a : b;
 }
 
@@ -101,8 +118,11 @@ hipError_t launch_batched(const void* insts, const void* tiles, int ntiles, int*
   const BatchTile* T = static_cast<const BatchTile*>(tiles);
 #define NSK_BATCH(TI, TA)                                                                           \
   {                                                                                                 \
-    (void)hipFuncSetAttribute((const void*)batched_kernel<TI, TA>,                                  \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);              \
+    if (lds > 64 * 1024) {                                                                          \
+      const hipError_t e = hipFuncSetAttribute((const void*)batched_kernel<TI, TA>,                 \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      if (e != hipSuccess) return e;                                                                \
+    }                                                                                               \
     batched_kernel<TI, TA><<<grid, kSrhtThreads, lds, st>>>(I, T, ntiles, counters);                \
   }
   if (dtype == NSK_F64) {
@@ -120,7 +140,8 @@ size_t batch_tile_bytes() { return sizeof(BatchTile); }
 // Fill one instance record (host side); layout private to this file.
 void batch_fill_inst(void* dst, const Operand& op, int64_t m, int N, int s, int k, int groups, int ctiles,
                      int max_sweeps, uint64_t seed, const int* rows, void* partial, double* sa_cm, double* R,
-                     double* V, double* sigma, int* order, double* Vk, double* sigma_k, nsk_info* info) {
+                     double2* log, double* sigma, int* order, double* colnorm, void* jres, double* Vk,
+                     double* sigma_k, nsk_info* info) {
   BatchInst b;
   b.op = op;
   b.m = m;
@@ -137,9 +158,11 @@ void batch_fill_inst(void* dst, const Operand& op, int64_t m, int N, int s, int 
   b.partial = partial;
   b.sa_cm = sa_cm;
   b.R = R;
-  b.V = V;
+  b.log = log;
   b.sigma = sigma;
   b.order = order;
+  b.colnorm = colnorm;
+  b.jres = static_cast<JacobiResult*>(jres);
   b.Vk = Vk;
   b.sigma_k = sigma_k;
   b.info = info;

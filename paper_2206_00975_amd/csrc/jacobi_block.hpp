@@ -1,0 +1,440 @@
+// Block one-sided Jacobi on R (N x N) with the column blocks held in registers.
+//
+// The N columns (padded with zero columns to nb * B, nb even) form nb blocks of B columns
+// that stay in place in global memory (column-major, ld = 64 * NR, rows >= N zero).  One
+// sweep is
+//  * an intra phase: every block rotates the pairs of its own columns in circle order (B'
+//    = B rounded up to even positions, position 0 fixed, one register shift per round), and
+//  * an inter phase: every pair of blocks once, in circle order over the blocks; in block
+//    round r the block pairs (circle(i, r), circle(nb - 1 - i, r)) are disjoint and each is
+//    handled by one wave, which loads the two blocks T and U into registers (lane l holds
+//    rows l + 64 j) and rotates (T_i, U_i) for all i in each of B sub-rounds, moving U's
+//    registers up by one slot between sub-rounds so that every T_i meets every U_j.
+// Rotation angles follow the one-sided Jacobi formulas; a pair is skipped when
+// |gamma| <= tol sqrt(alpha beta).  In the inter phase only gamma = x.y is reduced per
+// sub-round (a 16-value transposed reduction leaving pair i's sum in lane i); the squared
+// norms are exact at block load and updated as alpha - t gamma, beta + t gamma.  Every
+// rotation (c, s), skipped ones as (1, 0), goes to a log in schedule order so that columns
+// of V = J_1 J_2 ... are rebuilt later only for the vectors that are needed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "nsk_internal.hpp"
+
+namespace nsk {
+
+// ---------------------------------------------------------------- schedule arithmetic
+__host__ __device__ inline int circle_pos(int pos, int r, int n) {  // n even
+  return pos == 0 ? 0 : 1 + (pos - 1 + r) % (n - 1);
+}
+
+struct JacobiShape {
+  int N;     // columns of R
+  int NR;    // rows per lane (R has 64 * NR padded rows)
+  int B;     // columns per block
+  int nb;    // blocks (even)
+  int bq;    // B rounded up to even (intra-block circle size)
+  int spw;   // steps per sweep: (bq - 1) intra steps + B * (nb - 1) inter steps
+};
+
+__host__ __device__ inline int jacobi_nr(int N) {
+  const int nr = (N + 63) / 64;
+  return nr <= 5 ? nr : nr <= 8 ? 8 : 16;
+}
+
+__host__ __device__ inline int jacobi_block_size(int NR) {
+  return NR == 1 ? 4 : NR == 2 ? 8 : NR == 3 ? 12 : NR == 4 ? 13 : NR == 5 ? 10 : NR <= 8 ? 6 : 3;
+}
+
+__host__ __device__ inline JacobiShape jacobi_shape(int N) {
+  JacobiShape s;
+  s.N = N;
+  s.NR = jacobi_nr(N);
+  s.B = jacobi_block_size(s.NR);
+  s.nb = (N + s.B - 1) / s.B;
+  if (s.nb < 2) s.nb = 2;
+  s.nb += s.nb & 1;
+  s.bq = s.B + (s.B & 1);
+  s.spw = (s.bq - 1) + s.B * (s.nb - 1);
+  return s;
+}
+
+// Log layout of one sweep: intra steps have nb groups (blocks) of 16 slots, inter steps
+// nb/2 groups (block pairs) of 16 slots.
+__host__ __device__ inline size_t jacobi_log_step_offset(const JacobiShape& s, int st) {
+  const size_t intra = (size_t)(s.bq - 1) * s.nb * 16;
+  return st < s.bq - 1 ? (size_t)st * s.nb * 16 : intra + (size_t)(st - (s.bq - 1)) * (s.nb / 2) * 16;
+}
+
+__host__ __device__ inline size_t jacobi_log_entries_per_sweep(const JacobiShape& s) {
+  return jacobi_log_step_offset(s, s.spw);
+}
+
+// ---------------------------------------------------------------- wave primitives
+__device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+
+__device__ inline double bcast_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum each of the first P (<= 16) per-lane values over the wave; afterwards lane l holds the
+// total of value l & 15 (zero for l & 15 >= P).  Two full butterflies over lane bits 5 and 4,
+// then transposed halving steps over lane bits 3..0: a lane keeps the half selected by its
+// bit and adds the other half received from its partner.
+template <int P>
+__device__ inline double reduce16(double (&v)[16], int lane) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) v[i] += shfl_xor_d(v[i], 32);
+#pragma unroll
+  for (int i = 0; i < P; ++i) v[i] += shfl_xor_d(v[i], 16);
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1) {
+    const bool up = (lane & h) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      // before the step with partner distance h only slots < min(P, 2h) can be nonzero
+      const int pc = P < 2 * h ? P : 2 * h;
+      if (i >= pc) continue;
+      const double lo = v[i];
+      const double hi = i + h < pc ? v[i + h] : 0.0;
+      const double keep = up ? hi : lo;
+      const double send = up ? lo : hi;
+      v[i] = keep + shfl_xor_d(send, h);
+    }
+  }
+  return v[0];
+}
+
+struct JacobiCtx {
+  double tol;
+  int rotations;   // per-lane count
+  double offmax;   // per-lane largest relative cosine
+};
+
+__device__ inline void jacobi_params(double a, double b, double g, double tol, double& c, double& s,
+                                     double& t, bool& act) {
+  const double nab = sqrt(a * b);
+  act = fabs(g) > tol * nab;
+  c = 1.0;
+  s = 0.0;
+  t = 0.0;
+  if (act) {
+    const double zeta = (b - a) / (2.0 * g);
+    t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = c * t;
+  }
+}
+
+template <int NR>
+__device__ inline void rot_cols(double (&x)[NR], double (&y)[NR], double c, double s) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double a = x[r], b = y[r];
+    x[r] = c * a - s * b;
+    y[r] = s * a + c * b;
+  }
+}
+
+// ---------------------------------------------------------------- intra phase
+// Block `blk` alone: circle rounds q = 0..BQ-2 rotate the column at position i with the one
+// at position BQ-1-i (i < BQ/2); positions 1..BQ-1 then shift down by one.  A padding
+// position (B odd) holds a zero column and never rotates.
+template <int NR, int B>
+__device__ inline void jacobi_intra_block(double* __restrict__ R, int ld, int blk, double2* lg, int stride,
+                                          JacobiCtx& cx, int lane) {
+  constexpr int BQ = B + (B & 1);
+  constexpr int H = BQ / 2;
+  double X[BQ][NR];
+  double* p = R + (size_t)blk * B * ld + lane;
+#pragma unroll
+  for (int b = 0; b < BQ; ++b)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) X[b][r] = b < B ? p[(size_t)b * ld + 64 * r] : 0.0;
+  for (int q = 0; q < BQ - 1; ++q) {
+    double sab[3];
+#pragma unroll
+    for (int which = 0; which < 3; ++which) {
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = 0;
+#pragma unroll
+      for (int i = 0; i < H; ++i)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double a = X[i][r], b = X[BQ - 1 - i][r];
+          v[i] += which == 0 ? a * a : which == 1 ? b * b : a * b;
+        }
+      sab[which] = reduce16<H>(v, lane);
+    }
+    double c, s, t;
+    bool act;
+    jacobi_params(sab[0], sab[1], sab[2], cx.tol, c, s, t, act);
+    if (lane < H) {
+      const double nab = sqrt(sab[0] * sab[1]);
+      if (nab > 0) cx.offmax = fmax(cx.offmax, fabs(sab[2]) / nab);
+      if (act) cx.rotations++;
+      lg[lane] = make_double2(c, s);
+    }
+#pragma unroll
+    for (int i = 0; i < H; ++i) rot_cols<NR>(X[i], X[BQ - 1 - i], bcast_d(c, i), bcast_d(s, i));
+    // circle shift: position p takes position p+1 (p >= 1), the last takes position 1
+    double tmp[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tmp[r] = X[1][r];
+#pragma unroll
+    for (int b = 1; b < BQ - 1; ++b)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) X[b][r] = X[b + 1][r];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) X[BQ - 1][r] = tmp[r];
+    lg += stride;
+  }
+  // after BQ - 1 shifts every column is back at its starting position
+#pragma unroll
+  for (int b = 0; b < B; ++b)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) p[(size_t)b * ld + 64 * r] = X[b][r];
+}
+
+// ---------------------------------------------------------------- inter phase
+template <int NR, int B>
+__device__ inline void jacobi_inter_pair(double* __restrict__ R, int ld, int I, int J, double2* lg, int stride,
+                                         JacobiCtx& cx, int lane) {
+  double T[B][NR], U[B][NR];
+  double* pt = R + (size_t)I * B * ld + lane;
+  double* pu = R + (size_t)J * B * ld + lane;
+#pragma unroll
+  for (int b = 0; b < B; ++b)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T[b][r] = pt[(size_t)b * ld + 64 * r];
+      U[b][r] = pu[(size_t)b * ld + 64 * r];
+    }
+  // exact squared norms: lane i < B holds |T_i|^2 and |U_i|^2
+  double alpha, beta;
+  {
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[i] += T[i][r] * T[i][r];
+    alpha = reduce16<B>(v, lane);
+  }
+  {
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[i] += U[i][r] * U[i][r];
+    beta = reduce16<B>(v, lane);
+  }
+  const int lb = lane & 15;
+  const int nxt = lb + 1 == B ? 0 : (lb < B ? lb + 1 : lb);
+  for (int j = 0; j < B; ++j) {
+    // slot i of U holds block column (i + j) mod B
+    double z[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) z[i] = 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) z[i] += T[i][r] * U[i][r];
+    const double g = reduce16<B>(z, lane);
+    double c, s, t;
+    bool act;
+    jacobi_params(alpha, beta, g, cx.tol, c, s, t, act);
+    if (lb >= B) {
+      c = 1.0;
+      s = 0.0;
+      t = 0.0;
+      act = false;
+    }
+    if (lane < B) {
+      const double nab = sqrt(alpha * beta);
+      if (nab > 0) cx.offmax = fmax(cx.offmax, fabs(g) / nab);
+      if (act) cx.rotations++;
+      lg[lane] = make_double2(c, s);
+    }
+    if (act) {
+      alpha = fmax(alpha - t * g, 0.0);
+      beta = fmax(beta + t * g, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) rot_cols<NR>(T[i], U[i], bcast_d(c, i), bcast_d(s, i));
+    // U slots move up by one; lane i takes the norm of its new U column from lane i + 1
+    double tmp[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tmp[r] = U[0][r];
+#pragma unroll
+    for (int b = 0; b < B - 1; ++b)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) U[b][r] = U[b + 1][r];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) U[B - 1][r] = tmp[r];
+    beta = __shfl(beta, nxt, 16);
+    lg += stride;
+  }
+  // after B moves the U slots are back in block order
+#pragma unroll
+  for (int b = 0; b < B; ++b)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      pt[(size_t)b * ld + 64 * r] = T[b][r];
+      pu[(size_t)b * ld + 64 * r] = U[b][r];
+    }
+}
+
+// Sweeps until a sweep performs no rotation (or max_sweeps).  All waves of the workgroup
+// take part, with a barrier after the intra phase and after every block round.
+// log: max_sweeps * jacobi_log_entries_per_sweep entries.  Returns sweeps; *conv, *off set.
+template <int NR, int B>
+__device__ inline int jacobi_block_sweeps(double* __restrict__ R, const JacobiShape& js, int max_sweeps,
+                                          double2* __restrict__ log, int* sh_rot, double* sh_off, int* conv,
+                                          double* off_out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ld = 64 * NR;
+  const int nbp = js.nb / 2;
+  const size_t per_sweep = jacobi_log_entries_per_sweep(js);
+  JacobiCtx cx;
+  cx.tol = (double)js.N * 0x1p-53;
+  int sweeps = 0;
+  *conv = 0;
+  double off = 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    if (threadIdx.x == 0) {
+      *sh_rot = 0;
+      *sh_off = 0.0;
+    }
+    __syncthreads();
+    cx.rotations = 0;
+    cx.offmax = 0.0;
+    double2* sweep_log = log + (size_t)sw * per_sweep;
+    for (int b = wave; b < js.nb; b += nw)
+      jacobi_intra_block<NR, B>(R, ld, b, sweep_log + (size_t)b * 16, js.nb * 16, cx, lane);
+    __syncthreads();
+    for (int r = 0; r < js.nb - 1; ++r) {
+      double2* round_log = sweep_log + jacobi_log_step_offset(js, js.bq - 1 + r * B);
+      for (int i = wave; i < nbp; i += nw) {
+        int I = circle_pos(i, r, js.nb), J = circle_pos(js.nb - 1 - i, r, js.nb);
+        if (I > J) { const int t = I; I = J; J = t; }
+        jacobi_inter_pair<NR, B>(R, ld, I, J, round_log + (size_t)i * 16, nbp * 16, cx, lane);
+      }
+      __syncthreads();
+    }
+    int rot = cx.rotations;
+    double om = cx.offmax;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      rot += __shfl_xor(rot, o, 64);
+      om = fmax(om, __shfl_xor(om, o, 64));
+    }
+    if (lane == 0) {
+      atomicAdd(sh_rot, rot);
+      atomicMax(reinterpret_cast<unsigned long long*>(sh_off), (unsigned long long)__double_as_longlong(om));
+    }
+    __syncthreads();
+    sweeps = sw + 1;
+    off = *sh_off;
+    const int total = *sh_rot;
+    __syncthreads();
+    if (total == 0) {
+      *conv = 1;
+      break;
+    }
+  }
+  *off_out = off;
+  return sweeps;
+}
+
+// ------------------------------------------------------------------ log replay
+// Column pair of log slot (group g, slot l) at sweep-local step st; false if the slot holds
+// no rotation or touches a padding column.  Orientation (gp, gq) matches the kernel: x = gp.
+__device__ inline bool step_pair(const JacobiShape& js, int st, int g, int l, int& gp, int& gq) {
+  if (st < js.bq - 1) {
+    if (l >= js.bq / 2) return false;
+    const int a = circle_pos(l, st, js.bq), b = circle_pos(js.bq - 1 - l, st, js.bq);
+    if (a >= js.B || b >= js.B) return false;
+    gp = g * js.B + a;
+    gq = g * js.B + b;
+  } else {
+    if (l >= js.B) return false;
+    const int t = st - (js.bq - 1);
+    const int r = t / js.B, j = t % js.B;
+    int I = circle_pos(g, r, js.nb), J = circle_pos(js.nb - 1 - g, r, js.nb);
+    if (I > J) { const int u = I; I = J; J = u; }
+    gp = I * js.B + l;
+    gq = J * js.B + (l + j) % js.B;
+  }
+  return gp < js.N && gq < js.N;
+}
+
+__device__ inline int step_groups(const JacobiShape& js, int st) { return st < js.bq - 1 ? js.nb : js.nb / 2; }
+
+// One wave applies the logged rotations to the vector x (LDS, nb * B doubles).
+// transpose = false: x <- V x, steps from last to first with [x_p, x_q] <- [c x_p + s x_q,
+// -s x_p + c x_q].  transpose = true: x <- V^T x, steps from first to last with
+// [x_p, x_q] <- [c x_p - s x_q, s x_p + c x_q].  Log entries are prefetched kD steps ahead.
+template <int EPL>
+__device__ inline void jacobi_replay(double* x, const double2* __restrict__ log, const JacobiShape& js, int sweeps,
+                                     bool transpose, int lane) {
+  constexpr int kD = 4;
+  const size_t per_sweep = jacobi_log_entries_per_sweep(js);
+  const int total = sweeps * js.spw;
+  auto step_of = [&](int t) { return transpose ? t : total - 1 - t; };
+  auto load = [&](int t, double2 (&dst)[EPL]) {
+    const int g = step_of(t);
+    const int st = g % js.spw;
+    const int ent = step_groups(js, st) * 16;
+    const double2* base = log + (size_t)(g / js.spw) * per_sweep + jacobi_log_step_offset(js, st);
+#pragma unroll
+    for (int u = 0; u < EPL; ++u) {
+      const int e = lane + 64 * u;
+      dst[u] = e < ent ? base[e] : make_double2(1.0, 0.0);
+    }
+  };
+  double2 buf[kD][EPL];
+#pragma unroll
+  for (int d = 0; d < kD; ++d)
+    if (d < total) load(d, buf[d]);
+  for (int t0 = 0; t0 < total; t0 += kD) {
+#pragma unroll
+    for (int d = 0; d < kD; ++d) {
+      const int t = t0 + d;
+      if (t < total) {
+        const int st = step_of(t) % js.spw;
+        const int ent = step_groups(js, st) * 16;
+#pragma unroll
+        for (int u = 0; u < EPL; ++u) {
+          const int e = lane + 64 * u;
+          int gp, gq;
+          if (e < ent && step_pair(js, st, e >> 4, e & 15, gp, gq)) {
+            const double c = buf[d][u].x, s = buf[d][u].y;
+            const double xp = x[gp], xq = x[gq];
+            if (transpose) {
+              x[gp] = c * xp - s * xq;
+              x[gq] = s * xp + c * xq;
+            } else {
+              x[gp] = c * xp + s * xq;
+              x[gq] = -s * xp + c * xq;
+            }
+          }
+        }
+        if (t + kD < total) load(t + kD, buf[d]);
+      }
+    }
+  }
+}
+
+// entries per lane: intra steps have nb * 16 slots
+__host__ __device__ inline int replay_epl(const JacobiShape& js) { return (js.nb * 16 + 63) / 64; }
+
+}  // namespace nsk

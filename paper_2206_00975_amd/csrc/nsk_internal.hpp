@@ -141,30 +141,44 @@ hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st)
 hipError_t launch_reduce(const Operand& op, const SketchPlan& p, double* sa_rm, int64_t ld_rm,
                          double* sa_cm, int64_t ld_cm, hipStream_t st);
 
+struct JacobiResult;  // svd_pipeline.hpp
 struct SvdPlan {
   int s, N, k;
   int max_sweeps;
-  double* sa;        // s x N column-major (ld = s), overwritten by the QR
-  double* R;         // N x N column-major work
-  double* V;         // N x N column-major work
-  double* sigma;     // N work: singular values in sorted order
-  int* order;        // N work: column index of each sorted singular value
-  double* Vk;        // N x k row-major out (nullable)
-  double* sigma_k;   // k out (nullable)
-  nsk_info* info;    // nullable
+  double* sa;          // s x N column-major (ld = s), overwritten by the QR
+  double* R;           // work: (64 NR) x (nb B) on the fast path, N x N otherwise
+  double* V;           // work: N x N (only without the fast path)
+  double2* log;        // work: rotation log (fast path)
+  double* sigma;       // N: singular values in sorted order
+  int* order;          // N: column index of each sorted singular value
+  double* colnorm;     // N: singular value of each column (fast path; nullable)
+  JacobiResult* jres;  // fast path: sweeps / convergence
+  double* Vk;          // N x k row-major out (nullable)
+  double* sigma_k;     // k out (nullable)
+  nsk_info* info;      // nullable
 };
+bool svd_fast_path(int s, int N);
+size_t svd_work_R_bytes(int s, int N);
+size_t svd_work_log_bytes(int s, int N, int max_sweeps);
 hipError_t launch_svd(const SvdPlan& p, hipStream_t st);
 
 hipError_t launch_residual(const Operand& op, int64_t m, const double* Vk, int k, double* partial,
                            int parts, double* out, nsk_info* info, hipStream_t st);
 
-struct TlsState;  // layout in post.hip
-hipError_t launch_tls_extract(int N, const double* V, const double* sigma, const int* order,
-                              double* x, double* vN, hipStream_t st);
-hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const double* sa_cm, const double* V,
-                               const double* sigma, const int* order, const double* x,
-                               const double* gx, double* work, void* dA, int64_t ldda, void* db,
-                               int out_dtype, hipStream_t st);
+hipError_t launch_tls_extract(int N, const double* v, double* x, hipStream_t st);
+// TLS adjoint + gradient.  st: TLS state arrays (see api.cpp); the trailing vector v,
+// singular values per column and the rotation log give w = V D V^T g_bar by two replays.
+struct TlsBack {
+  const double* sa_rm;     // s x N row-major
+  const double* colnorm;   // N
+  const int* order;        // N
+  const double* v;         // N
+  const double* x;         // n
+  const JacobiResult* jres;
+  const double2* log;
+};
+hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const TlsBack& tb, const double* gx, double* work,
+                               void* dA, int64_t ldda, void* db, int out_dtype, hipStream_t st);
 
 hipError_t launch_draw_signs(uint64_t seed, int64_t m, int8_t* d, hipStream_t st);
 hipError_t launch_draw_sparse(uint64_t seed, int64_t m, int s, int zeta, int32_t* rows,

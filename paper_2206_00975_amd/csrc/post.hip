@@ -5,6 +5,7 @@
 
 #include "nsk_internal.hpp"
 #include "svd_device.hpp"
+#include "svd_pipeline.hpp"
 
 namespace nsk {
 
@@ -73,46 +74,34 @@ hipError_t launch_residual(const Operand& op, int64_t m, const double* Vk, int k
 }
 
 // ========================================================================= TLS forward
-// x = -v(1:n) / v(N) with v the trailing right singular vector (column order[N-1] of V).
-__global__ void tls_extract_kernel(int N, const double* __restrict__ V, const int* __restrict__ order,
-                                   double* __restrict__ x, double* __restrict__ vN) {
-  const int c = order[N - 1];
-  const double* v = V + (size_t)c * N;
+// x = -v(1:n) / v(N) with v the trailing right singular vector of the sketched [A | b].
+__global__ void tls_extract_kernel(int N, const double* __restrict__ v, double* __restrict__ x) {
   const double last = v[N - 1];
-  for (int e = threadIdx.x; e < N; e += blockDim.x) {
-    if (e < N - 1) x[e] = -v[e] / last;
-    if (vN) vN[e] = v[e];
-  }
+  for (int e = threadIdx.x; e < N - 1; e += blockDim.x) x[e] = -v[e] / last;
 }
 
-hipError_t launch_tls_extract(int N, const double* V, const double* sigma, const int* order, double* x,
-                              double* vN, hipStream_t st) {
-  (void)sigma;
-  tls_extract_kernel<<<1, 256, 0, st>>>(N, V, order, x, vN);
+hipError_t launch_tls_extract(int N, const double* v, double* x, hipStream_t st) {
+  tls_extract_kernel<<<1, 256, 0, st>>>(N, v, x);
   return hipGetLastError();
 }
 
 // ======================================================================== TLS backward
-// work layout: y_v (s), y_w (s), v (N), w (N).
-__global__ __launch_bounds__(1024) void tls_adjoint_kernel(int s, int N, const double* __restrict__ sa_rm,
-                                                           const double* __restrict__ V,
-                                                           const double* __restrict__ sigma,
-                                                           const int* __restrict__ order,
-                                                           const double* __restrict__ x,
-                                                           const double* __restrict__ gx,
+// g_bar = dL/dv = -(1/v_N) [g; g.x];  w = V D V^T g_bar with D_c = 1 / (sigma_N^2 - sigma_c^2)
+// for every column c except the trailing one (D = 0 there): the first-order change of the
+// trailing right singular vector of SA.  V^T g_bar and V z are applied by replaying the
+// Jacobi rotation log forward (transposed) and backward.  work = [SA v (s), SA w (s), v, w].
+__global__ __launch_bounds__(1024) void tls_adjoint_kernel(int s, int N, TlsBack tb, const double* __restrict__ gx,
                                                            double* __restrict__ work) {
   extern __shared__ double sm[];
-  double* gbar = sm;           // N
-  double* coef = gbar + N;     // N
-  double* vloc = coef + N;     // N
-  double* wloc = vloc + N;     // N
+  const JacobiShape js = jacobi_shape(N);
+  const int ncols = js.nb * js.B;
+  double* xb = sm;             // ncols
+  double* wl = xb + ncols;     // N: w
   __shared__ double red[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = N - 1;
-  const double* v = V + (size_t)order[N - 1] * N;
-  // g.x
   double gxdot = 0;
-  for (int e = tid; e < n; e += blockDim.x) gxdot += gx[e] * x[e];
+  for (int e = tid; e < n; e += blockDim.x) gxdot += gx[e] * tb.x[e];
   gxdot = wave_sum(gxdot);
   if (lane == 0) red[wave] = gxdot;
   __syncthreads();
@@ -123,41 +112,36 @@ __global__ __launch_bounds__(1024) void tls_adjoint_kernel(int s, int N, const d
   }
   __syncthreads();
   const double gx_x = red[0];
-  const double inv = -1.0 / v[N - 1];
-  for (int e = tid; e < N; e += blockDim.x) {
-    gbar[e] = inv * (e < n ? gx[e] : gx_x);
-    vloc[e] = v[e];
+  const double inv = -1.0 / tb.v[N - 1];
+  for (int e = tid; e < ncols; e += blockDim.x) xb[e] = e < N ? inv * (e < n ? gx[e] : gx_x) : 0.0;
+  __syncthreads();
+  const int sweeps = tb.jres->sweeps;
+  if (wave == 0) replay_dispatch(xb, tb.log, js, sweeps, true, lane);
+  __syncthreads();
+  const int cN = tb.order[N - 1];
+  const double lamN = tb.colnorm[cN] * tb.colnorm[cN];
+  for (int c = tid; c < ncols; c += blockDim.x) {
+    const double sc = tb.colnorm[c < N ? c : 0];
+    xb[c] = (c < N && c != cN) ? xb[c] / (lamN - sc * sc) : 0.0;
   }
   __syncthreads();
-  // coefficients (v_r . g_bar) / (sigma_N^2 - sigma_r^2) over the other singular vectors
-  const double lamN = sigma[N - 1] * sigma[N - 1];
-  for (int r = wave; r < N - 1; r += nw) {
-    const double* vr = V + (size_t)order[r] * N;
-    double d = 0;
-    for (int e = lane; e < N; e += 64) d += vr[e] * gbar[e];
-    d = wave_sum(d);
-    if (lane == 0) coef[r] = d / (lamN - sigma[r] * sigma[r]);
-  }
+  if (wave == 0) replay_dispatch(xb, tb.log, js, sweeps, false, lane);
   __syncthreads();
-  for (int e = tid; e < N; e += blockDim.x) {
-    double t = 0;
-    for (int r = 0; r < N - 1; ++r) t += V[(size_t)order[r] * N + e] * coef[r];
-    wloc[e] = t;
-  }
+  for (int e = tid; e < N; e += blockDim.x) wl[e] = xb[e];
   __syncthreads();
   for (int i = tid; i < s; i += blockDim.x) {
     double a = 0, b = 0;
     for (int c = 0; c < N; ++c) {
-      const double m = sa_rm[(size_t)i * N + c];
-      a += m * vloc[c];
-      b += m * wloc[c];
+      const double m = tb.sa_rm[(size_t)i * N + c];
+      a += m * tb.v[c];
+      b += m * wl[c];
     }
     work[i] = a;
     work[s + i] = b;
   }
   for (int e = tid; e < N; e += blockDim.x) {
-    work[2 * s + e] = vloc[e];
-    work[2 * s + N + e] = wloc[e];
+    work[2 * s + e] = tb.v[e];
+    work[2 * s + N + e] = wl[e];
   }
 }
 
@@ -244,11 +228,12 @@ __global__ __launch_bounds__(256) void tls_grad_srht_kernel(int64_t m, int N, in
   }
 }
 
-hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const double* sa_rm, const double* V,
-                               const double* sigma, const int* order, const double* x, const double* gx,
-                               double* work, void* dA, int64_t ldda, void* db, int out_dtype, hipStream_t st) {
+hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const TlsBack& tb, const double* gx, double* work,
+                               void* dA, int64_t ldda, void* db, int out_dtype, hipStream_t st) {
   const int N = p.N, s = p.s;
-  tls_adjoint_kernel<<<1, 1024, (size_t)4 * N * sizeof(double), st>>>(s, N, sa_rm, V, sigma, order, x, gx, work);
+  const JacobiShape js = jacobi_shape(N);
+  const size_t alds = (size_t)(js.nb * js.B + N) * sizeof(double);
+  tls_adjoint_kernel<<<1, 1024, alds, st>>>(s, N, tb, gx, work);
   const size_t lds = (size_t)(2 * s + 2 * N) * sizeof(double) + (size_t)s * 4;
   const unsigned blocks = (unsigned)((m + 4 * 64 - 1) / (4 * 64)) < 4096u ? (unsigned)((m + 255) / 256) : 4096u;
   if (p.kind == NSK_SPARSE_SIGN) {

@@ -24,9 +24,10 @@
 
 namespace nsk {
 
-// Raise the dynamic-LDS cap of a kernel to the 160 KB a gfx950 CU provides.
-static void set_lds_limit(const void* fn) {
-  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+// Dynamic LDS above the 64 KB default must be requested per kernel (a gfx950 CU has 160 KB).
+static hipError_t set_lds_limit(const void* fn, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 // ============================================================================ sparse sign
@@ -232,7 +233,7 @@ static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStrea
   const size_t lds = srht_smem_bytes(p.s);
 #define NSK_SRHT_CASE(U)                                                                        \
   {                                                                                             \
-    set_lds_limit((const void*)srht_kernel<TIn, TAcc, U>);                                      \
+    if (hipError_t e = set_lds_limit((const void*)srht_kernel<TIn, TAcc, U>, lds)) return e;                                      \
     srht_kernel<TIn, TAcc, U><<<grid, kSrhtThreads, lds, st>>>(op, p.m, p.N, p.s, p.seed, p.rows, \
                                                                p.groups, part);                 \
   }
@@ -252,10 +253,10 @@ static hipError_t sparse_dispatch(const Operand& op, const SketchPlan& p, hipStr
                      kSpThreads * 4;
   TAcc* part = static_cast<TAcc*>(p.partial);
   if (zmax == 8) {
-    set_lds_limit((const void*)sparse_kernel<TIn, TAcc, 8>);
+    if (hipError_t e = set_lds_limit((const void*)sparse_kernel<TIn, TAcc, 8>, lds)) return e;
     sparse_kernel<TIn, TAcc, 8><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.zeta, p.seed, p.groups, part);
   } else {
-    set_lds_limit((const void*)sparse_kernel<TIn, TAcc, 32>);
+    if (hipError_t e = set_lds_limit((const void*)sparse_kernel<TIn, TAcc, 32>, lds)) return e;
     sparse_kernel<TIn, TAcc, 32><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.zeta, p.seed, p.groups, part);
   }
   return hipGetLastError();

@@ -1,0 +1,199 @@
+// SVD of the sketch SA for N <= 320 and s <= 4096: panel Householder QR -> block
+// one-sided Jacobi with a rotation log -> singular values, ordering and the requested
+// right singular vectors rebuilt from the log.  Every stage runs inside one workgroup and
+// synchronises with barriers only (the batched persistent kernel calls it directly); the
+// single-instance path launches the three stages as three kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "jacobi_block.hpp"
+#include "nsk_internal.hpp"
+#include "qr_panel.hpp"
+
+namespace nsk {
+
+constexpr int kFastMaxN = 320;
+constexpr int kFastMaxS = 4096;
+
+struct JacobiResult {
+  int sweeps;
+  int converged;
+  double off;
+};
+
+struct SvdWork {
+  double* sa;          // s x N column-major, overwritten by the QR
+  double* R;           // (64 NR) x (nb B) column-major, ld = 64 NR
+  double2* log;        // max_sweeps * jacobi_log_entries_per_sweep
+  double* sigma;       // N, sorted non-increasing
+  int* order;          // N, column of R holding sigma[i]
+  double* colnorm;     // N, |R_c| for every column c
+  JacobiResult* jres;  // sweeps / convergence of the Jacobi stage
+  double* Vk;          // N x k row-major (nullable)
+  double* sigma_k;     // k (nullable)
+  nsk_info* info;      // nullable
+  int s, N, k, max_sweeps;
+};
+
+__host__ __device__ inline size_t svd_fast_log_bytes(int N, int max_sweeps) {
+  const JacobiShape js = jacobi_shape(N);
+  return (size_t)max_sweeps * jacobi_log_entries_per_sweep(js) * sizeof(double2);
+}
+
+__host__ __device__ inline size_t svd_fast_R_bytes(int N) {
+  const JacobiShape js = jacobi_shape(N);
+  return (size_t)64 * js.NR * js.nb * js.B * sizeof(double);
+}
+
+__host__ __device__ inline int qr_panel_width(int s, int nwaves) {
+  int nb = nwaves < 16 ? nwaves : 16;
+  while (nb > 1 && qr_panel_lds_bytes(s, nb) > 120 * 1024) nb >>= 1;
+  return nb;
+}
+
+__host__ __device__ inline size_t svd_fast_lds_bytes(int s, int N, int nwaves) {
+  const JacobiShape js = jacobi_shape(N);
+  const size_t qr = qr_panel_lds_bytes(s, qr_panel_width(s, nwaves));
+  const size_t fin = (size_t)N * 12 + (size_t)nwaves * js.nb * js.B * 8 + 256;
+  return qr > fin ? qr : fin;
+}
+
+// ---------------------------------------------------------------- stage 1: QR
+template <int NB>
+__device__ inline void svd_stage_qr_nb(const SvdWork& w, int ldr, unsigned char* smem) {
+  if (w.s <= 1024) qr_panel<16, NB>(w.sa, w.s, w.N, w.R, ldr, smem);
+  else if (w.s <= 2048) qr_panel<32, NB>(w.sa, w.s, w.N, w.R, ldr, smem);
+  else qr_panel<64, NB>(w.sa, w.s, w.N, w.R, ldr, smem);
+}
+
+__device__ inline void svd_stage_qr(const SvdWork& w, unsigned char* smem) {
+  const JacobiShape js = jacobi_shape(w.N);
+  const int ldr = 64 * js.NR;
+  const size_t total = (size_t)ldr * js.nb * js.B;
+  for (size_t e = threadIdx.x; e < total; e += blockDim.x) w.R[e] = 0.0;
+  __syncthreads();
+  const int nb = qr_panel_width(w.s, blockDim.x >> 6);
+  switch (nb) {
+    case 16: svd_stage_qr_nb<16>(w, ldr, smem); break;
+    case 8: svd_stage_qr_nb<8>(w, ldr, smem); break;
+    case 4: svd_stage_qr_nb<4>(w, ldr, smem); break;
+    case 2: svd_stage_qr_nb<2>(w, ldr, smem); break;
+    default: svd_stage_qr_nb<1>(w, ldr, smem); break;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- stage 2: Jacobi
+__device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
+  const JacobiShape js = jacobi_shape(w.N);
+  int* sh_rot = reinterpret_cast<int*>(smem);
+  double* sh_off = reinterpret_cast<double*>(smem + 8);
+  int conv = 0;
+  double off = 0;
+  int sweeps = 0;
+  switch (js.NR) {
+    case 1: sweeps = jacobi_block_sweeps<1, 4>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
+    case 2: sweeps = jacobi_block_sweeps<2, 8>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
+    case 3: sweeps = jacobi_block_sweeps<3, 12>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
+    case 4: sweeps = jacobi_block_sweeps<4, 13>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
+    default: sweeps = jacobi_block_sweeps<5, 10>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
+  }
+  if (threadIdx.x == 0) {
+    w.jres->sweeps = sweeps;
+    w.jres->converged = conv;
+    w.jres->off = off;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- stage 3: finish
+__device__ inline void replay_dispatch(double* x, const double2* log, const JacobiShape& js, int sweeps,
+                                       bool transpose, int lane) {
+  const int epl = replay_epl(js);
+  if (epl <= 1) jacobi_replay<1>(x, log, js, sweeps, transpose, lane);
+  else if (epl <= 2) jacobi_replay<2>(x, log, js, sweeps, transpose, lane);
+  else if (epl <= 4) jacobi_replay<4>(x, log, js, sweeps, transpose, lane);
+  else jacobi_replay<8>(x, log, js, sweeps, transpose, lane);
+}
+
+__device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
+  const JacobiShape js = jacobi_shape(w.N);
+  const int N = w.N, k = w.k;
+  const int ldr = 64 * js.NR;
+  const int ncols = js.nb * js.B;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  double* nrm = reinterpret_cast<double*>(smem);
+  int* rk = reinterpret_cast<int*>(nrm + N);
+  double* xs = reinterpret_cast<double*>(smem + (((size_t)N * 12 + 255) & ~(size_t)255));
+  // singular values: column norms of the rotated R
+  for (int c = wave; c < N; c += nw) {
+    double a = 0;
+    for (int e = lane; e < ldr; e += 64) a += w.R[(size_t)c * ldr + e] * w.R[(size_t)c * ldr + e];
+    a = wave_sum64(a);
+    if (lane == 0) {
+      nrm[c] = sqrt(a);
+      if (w.colnorm) w.colnorm[c] = sqrt(a);
+    }
+  }
+  __syncthreads();
+  // rank by (norm descending, index ascending); NaN ranks last so ranks are a permutation
+  for (int c = tid; c < N; c += blockDim.x) {
+    const double xv = nrm[c];
+    const double x = xv != xv ? -1.0 : xv;
+    int r = 0;
+    for (int d = 0; d < N; ++d) {
+      const double yv = nrm[d];
+      const double y = yv != yv ? -1.0 : yv;
+      r += (y > x) || (y == x && d < c);
+    }
+    rk[c] = r;
+    w.order[r] = c;
+    w.sigma[r] = xv;
+  }
+  __syncthreads();
+  const int sweeps = w.jres->sweeps;
+  // trailing vectors: wave q rebuilds V e_{order[N-k+q]} from the log
+  for (int q0 = 0; q0 < k; q0 += nw) {
+    const int q = q0 + wave;
+    double* x = xs + (size_t)wave * ncols;
+    if (q < k) {
+      const int c = w.order[N - k + q];
+      for (int e = lane; e < ncols; e += 64) x[e] = e == c ? 1.0 : 0.0;
+      replay_dispatch(x, w.log, js, sweeps, false, lane);
+      // sign: largest-magnitude entry positive, lowest index on ties
+      double best = -1;
+      int bi = 0;
+      for (int e = lane; e < N; e += 64) {
+        const double a = fabs(x[e]);
+        if (a > best) { best = a; bi = e; }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      const double sgn = x[bi] < 0 ? -1.0 : 1.0;
+      if (w.Vk)
+        for (int e = lane; e < N; e += 64) w.Vk[(size_t)e * k + q] = sgn * x[e];
+      if (w.sigma_k && lane == 0) w.sigma_k[q] = w.sigma[N - k + q];
+    }
+    __syncthreads();
+  }
+  if (w.info && tid == 0) {
+    w.info->sweeps = sweeps;
+    w.info->converged = w.jres->converged;
+    w.info->off = w.jres->off;
+    w.info->sigma_max = w.sigma[0];
+  }
+  __syncthreads();
+}
+
+__device__ inline void svd_pipeline(const SvdWork& w, unsigned char* smem) {
+  svd_stage_qr(w, smem);
+  svd_stage_jacobi(w, smem);
+  svd_stage_finish(w, smem);
+}
+
+}  // namespace nsk
