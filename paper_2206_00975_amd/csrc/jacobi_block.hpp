@@ -12,7 +12,7 @@
 //    registers up by one slot between sub-rounds so that every T_i meets every U_j.
 // Rotation angles follow the one-sided Jacobi formulas; a pair is skipped when
 // |gamma| <= tol sqrt(alpha beta).  In the inter phase only gamma = x.y is reduced per
-// sub-round (a 16-value transposed reduction leaving pair i's sum in lane i); the squared
+// sub-round (one transposed reduction over the wave for all B pairs at once); the squared
 // norms are exact at block load and updated as alpha - t gamma, beta + t gamma.  Every
 // rotation (c, s), skipped ones as (1, 0), goes to a log in schedule order so that columns
 // of V = J_1 J_2 ... are rebuilt later only for the vectors that are needed.
@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "nsk_internal.hpp"
+#include "wave_ops.hpp"
 
 namespace nsk {
 
@@ -43,7 +44,7 @@ __host__ __device__ inline int jacobi_nr(int N) {
   return nr <= 5 ? nr : nr <= 8 ? 8 : 16;
 }
 
-__host__ __device__ inline int jacobi_block_size(int NR) {
+__host__ __device__ constexpr int jacobi_block_size(int NR) {
   return NR == 1 ? 4 : NR == 2 ? 8 : NR == 3 ? 12 : NR == 4 ? 13 : NR == 5 ? 10 : NR <= 8 ? 6 : 3;
 }
 
@@ -72,43 +73,6 @@ __host__ __device__ inline size_t jacobi_log_entries_per_sweep(const JacobiShape
 }
 
 // ---------------------------------------------------------------- wave primitives
-__device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
-
-__device__ inline double bcast_d(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum each of the first P (<= 16) per-lane values over the wave; afterwards lane l holds the
-// total of value l & 15 (zero for l & 15 >= P).  Two full butterflies over lane bits 5 and 4,
-// then transposed halving steps over lane bits 3..0: a lane keeps the half selected by its
-// bit and adds the other half received from its partner.
-template <int P>
-__device__ inline double reduce16(double (&v)[16], int lane) {
-#pragma unroll
-  for (int i = 0; i < P; ++i) v[i] += shfl_xor_d(v[i], 32);
-#pragma unroll
-  for (int i = 0; i < P; ++i) v[i] += shfl_xor_d(v[i], 16);
-#pragma unroll
-  for (int h = 8; h >= 1; h >>= 1) {
-    const bool up = (lane & h) != 0;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      // before the step with partner distance h only slots < min(P, 2h) can be nonzero
-      const int pc = P < 2 * h ? P : 2 * h;
-      if (i >= pc) continue;
-      const double lo = v[i];
-      const double hi = i + h < pc ? v[i + h] : 0.0;
-      const double keep = up ? hi : lo;
-      const double send = up ? lo : hi;
-      v[i] = keep + shfl_xor_d(send, h);
-    }
-  }
-  return v[0];
-}
-
 struct JacobiCtx {
   double tol;
   int rotations;   // per-lane count
@@ -143,45 +107,50 @@ __device__ inline void rot_cols(double (&x)[NR], double (&y)[NR], double c, doub
 // ---------------------------------------------------------------- intra phase
 // Block `blk` alone: circle rounds q = 0..BQ-2 rotate the column at position i with the one
 // at position BQ-1-i (i < BQ/2); positions 1..BQ-1 then shift down by one.  A padding
-// position (B odd) holds a zero column and never rotates.
+// position (B odd) holds a zero column and never rotates.  After each reduction pair i's
+// sums sit in lanes i << SH .. (i << SH) + 2^SH - 1.
 template <int NR, int B>
 __device__ inline void jacobi_intra_block(double* __restrict__ R, int ld, int blk, double2* lg, int stride,
                                           JacobiCtx& cx, int lane) {
   constexpr int BQ = B + (B & 1);
   constexpr int H = BQ / 2;
+  constexpr int SH = 6 - ceil_log2(H);
+  const int pi = lane >> SH;
+  const bool lead = (lane & ((1 << SH) - 1)) == 0 && pi < H;
   double X[BQ][NR];
-  double* p = R + (size_t)blk * B * ld + lane;
+  // wave-uniform column bases keep addressing in scalar registers plus one lane offset
+  double* p = uniform_ptr(R + (size_t)blk * B * ld);
 #pragma unroll
   for (int b = 0; b < BQ; ++b)
 #pragma unroll
-    for (int r = 0; r < NR; ++r) X[b][r] = b < B ? p[(size_t)b * ld + 64 * r] : 0.0;
+    for (int r = 0; r < NR; ++r) X[b][r] = b < B ? p[(size_t)b * ld + lane + 64 * r] : 0.0;
   for (int q = 0; q < BQ - 1; ++q) {
     double sab[3];
 #pragma unroll
     for (int which = 0; which < 3; ++which) {
       double v[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = 0;
-#pragma unroll
-      for (int i = 0; i < H; ++i)
+      for (int i = 0; i < H; ++i) {
+        v[i] = 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const double a = X[i][r], b = X[BQ - 1 - i][r];
           v[i] += which == 0 ? a * a : which == 1 ? b * b : a * b;
         }
-      sab[which] = reduce16<H>(v, lane);
+      }
+      sab[which] = reduce_t<H>(v, lane);
     }
     double c, s, t;
     bool act;
     jacobi_params(sab[0], sab[1], sab[2], cx.tol, c, s, t, act);
-    if (lane < H) {
+    if (lead) {
       const double nab = sqrt(sab[0] * sab[1]);
       if (nab > 0) cx.offmax = fmax(cx.offmax, fabs(sab[2]) / nab);
       if (act) cx.rotations++;
-      lg[lane] = make_double2(c, s);
+      lg[pi] = make_double2(c, s);
     }
 #pragma unroll
-    for (int i = 0; i < H; ++i) rot_cols<NR>(X[i], X[BQ - 1 - i], bcast_d(c, i), bcast_d(s, i));
+    for (int i = 0; i < H; ++i) rot_cols<NR>(X[i], X[BQ - 1 - i], bcast_d(c, i << SH), bcast_d(s, i << SH));
     // circle shift: position p takes position p+1 (p >= 1), the last takes position 1
     double tmp[NR];
 #pragma unroll
@@ -195,82 +164,90 @@ __device__ inline void jacobi_intra_block(double* __restrict__ R, int ld, int bl
     lg += stride;
   }
   // after BQ - 1 shifts every column is back at its starting position
+  p = opaque_uniform(p);
 #pragma unroll
   for (int b = 0; b < B; ++b)
 #pragma unroll
-    for (int r = 0; r < NR; ++r) p[(size_t)b * ld + 64 * r] = X[b][r];
+    for (int r = 0; r < NR; ++r) p[(size_t)b * ld + lane + 64 * r] = X[b][r];
 }
 
 // ---------------------------------------------------------------- inter phase
+// Pair i's scalars (|T_i|^2, |U_i|^2, T_i . U_i, rotation) live in lanes i << SH ..
 template <int NR, int B>
 __device__ inline void jacobi_inter_pair(double* __restrict__ R, int ld, int I, int J, double2* lg, int stride,
                                          JacobiCtx& cx, int lane) {
+  constexpr int SH = 6 - ceil_log2(B);
+  const int pi = lane >> SH;
+  const bool valid = pi < B;
+  const bool lead = (lane & ((1 << SH) - 1)) == 0 && valid;
   double T[B][NR], U[B][NR];
-  double* pt = R + (size_t)I * B * ld + lane;
-  double* pu = R + (size_t)J * B * ld + lane;
+  double* pt = uniform_ptr(R + (size_t)I * B * ld);
+  double* pu = uniform_ptr(R + (size_t)J * B * ld);
 #pragma unroll
   for (int b = 0; b < B; ++b)
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      T[b][r] = pt[(size_t)b * ld + 64 * r];
-      U[b][r] = pu[(size_t)b * ld + 64 * r];
+      T[b][r] = pt[(size_t)b * ld + lane + 64 * r];
+      U[b][r] = pu[(size_t)b * ld + lane + 64 * r];
     }
-  // exact squared norms: lane i < B holds |T_i|^2 and |U_i|^2
+  // exact squared norms at load
   double alpha, beta;
   {
     double v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = 0;
-#pragma unroll
-    for (int i = 0; i < B; ++i)
+    for (int i = 0; i < B; ++i) {
+      v[i] = 0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) v[i] += T[i][r] * T[i][r];
-    alpha = reduce16<B>(v, lane);
+    }
+    alpha = reduce_t<B>(v, lane);
   }
   {
     double v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = 0;
-#pragma unroll
-    for (int i = 0; i < B; ++i)
+    for (int i = 0; i < B; ++i) {
+      v[i] = 0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) v[i] += U[i][r] * U[i][r];
-    beta = reduce16<B>(v, lane);
+    }
+    beta = reduce_t<B>(v, lane);
   }
-  const int lb = lane & 15;
-  const int nxt = lb + 1 == B ? 0 : (lb < B ? lb + 1 : lb);
+  // lane of the pair whose U column moves into this lane's slot next sub-round
+  const int nxt_pair = pi + 1 == B ? 0 : (valid ? pi + 1 : pi);
+  const int nxt_lane = (nxt_pair << SH) | (lane & ((1 << SH) - 1));
   for (int j = 0; j < B; ++j) {
     // slot i of U holds block column (i + j) mod B
     double z[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) z[i] = 0;
-#pragma unroll
-    for (int i = 0; i < B; ++i)
+    for (int i = 0; i < B; ++i) {
+      z[i] = 0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) z[i] += T[i][r] * U[i][r];
-    const double g = reduce16<B>(z, lane);
+    }
+    const double g = reduce_t<B>(z, lane);
     double c, s, t;
     bool act;
     jacobi_params(alpha, beta, g, cx.tol, c, s, t, act);
-    if (lb >= B) {
+    if (!valid) {
       c = 1.0;
       s = 0.0;
       t = 0.0;
       act = false;
     }
-    if (lane < B) {
+    if (lead) {
       const double nab = sqrt(alpha * beta);
       if (nab > 0) cx.offmax = fmax(cx.offmax, fabs(g) / nab);
       if (act) cx.rotations++;
-      lg[lane] = make_double2(c, s);
+      lg[pi] = make_double2(c, s);
     }
     if (act) {
       alpha = fmax(alpha - t * g, 0.0);
       beta = fmax(beta + t * g, 0.0);
     }
 #pragma unroll
-    for (int i = 0; i < B; ++i) rot_cols<NR>(T[i], U[i], bcast_d(c, i), bcast_d(s, i));
-    // U slots move up by one; lane i takes the norm of its new U column from lane i + 1
+    for (int i = 0; i < B; ++i) rot_cols<NR>(T[i], U[i], bcast_d(c, i << SH), bcast_d(s, i << SH));
+    // U slots move up by one; each pair takes the squared norm of its new U column from the
+    // next pair's lanes
     double tmp[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) tmp[r] = U[0][r];
@@ -280,16 +257,18 @@ __device__ inline void jacobi_inter_pair(double* __restrict__ R, int ld, int I, 
       for (int r = 0; r < NR; ++r) U[b][r] = U[b + 1][r];
 #pragma unroll
     for (int r = 0; r < NR; ++r) U[B - 1][r] = tmp[r];
-    beta = __shfl(beta, nxt, 16);
+    beta = __shfl(beta, nxt_lane, 64);
     lg += stride;
   }
   // after B moves the U slots are back in block order
+  pt = opaque_uniform(pt);
+  pu = opaque_uniform(pu);
 #pragma unroll
   for (int b = 0; b < B; ++b)
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      pt[(size_t)b * ld + 64 * r] = T[b][r];
-      pu[(size_t)b * ld + 64 * r] = U[b][r];
+      pt[(size_t)b * ld + lane + 64 * r] = T[b][r];
+      pu[(size_t)b * ld + lane + 64 * r] = U[b][r];
     }
 }
 

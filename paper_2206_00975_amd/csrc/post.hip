@@ -90,7 +90,7 @@ hipError_t launch_tls_extract(int N, const double* v, double* x, hipStream_t st)
 // for every column c except the trailing one (D = 0 there): the first-order change of the
 // trailing right singular vector of SA.  V^T g_bar and V z are applied by replaying the
 // Jacobi rotation log forward (transposed) and backward.  work = [SA v (s), SA w (s), v, w].
-__global__ __launch_bounds__(1024) void tls_adjoint_kernel(int s, int N, TlsBack tb, const double* __restrict__ gx,
+__global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack tb, const double* __restrict__ gx,
                                                            double* __restrict__ work) {
   extern __shared__ double sm[];
   const JacobiShape js = jacobi_shape(N);
@@ -233,7 +233,7 @@ hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const TlsBack& tb
   const int N = p.N, s = p.s;
   const JacobiShape js = jacobi_shape(N);
   const size_t alds = (size_t)(js.nb * js.B + N) * sizeof(double);
-  tls_adjoint_kernel<<<1, 1024, alds, st>>>(s, N, tb, gx, work);
+  tls_adjoint_kernel<<<1, 512, alds, st>>>(s, N, tb, gx, work);
   const size_t lds = (size_t)(2 * s + 2 * N) * sizeof(double) + (size_t)s * 4;
   const unsigned blocks = (unsigned)((m + 4 * 64 - 1) / (4 * 64)) < 4096u ? (unsigned)((m + 255) / 256) : 4096u;
   if (p.kind == NSK_SPARSE_SIGN) {

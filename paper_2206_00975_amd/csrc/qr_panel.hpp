@@ -14,21 +14,9 @@
 #include <hip/hip_runtime.h>
 
 #include "nsk_internal.hpp"
+#include "wave_ops.hpp"
 
 namespace nsk {
-
-__device__ inline double wave_sum64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ inline double lane_value(double x, int src) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // LDS bytes: NB * s doubles of Householder vectors + NB taus.
 __host__ __device__ inline size_t qr_panel_lds_bytes(int s, int NB) { return (size_t)NB * s * 8 + NB * 8 + 64; }

@@ -1,9 +1,11 @@
 // Single-instance SVD launches.
 //
 // N <= 320 and s <= 4096: three kernels, one workgroup each -- panel Householder QR (1024
-// threads), block one-sided Jacobi with the blocks in registers (512 threads: 8 waves with up
-// to 256 VGPRs each), and the finish stage (1024 threads) that ranks the singular values and
-// rebuilds the requested vectors from the rotation log.
+// threads), block one-sided Jacobi with the blocks in registers, and the finish stage (1024
+// threads) that ranks the singular values and rebuilds the requested vectors from the
+// rotation log.  The Jacobi kernel is specialised on the rows per lane NR: NR <= 3 runs 8
+// waves (2 per SIMD, 256 VGPRs each); NR >= 4 holds two blocks of 4 x 13 or 5 x 10 doubles per
+// lane and runs 4 waves (1 per SIMD), whose accumulation registers absorb the overflow.
 // Larger problems use svd_instance (scalar Jacobi on global-memory R with V accumulated).
 #include <hip/hip_runtime.h>
 
@@ -14,7 +16,7 @@
 namespace nsk {
 
 constexpr int kSvdThreads = 1024;
-constexpr int kJacobiThreads = 512;
+__host__ __device__ constexpr int jacobi_threads(int NR) { return NR <= 3 ? 512 : 256; }
 
 static SvdWork to_work(const SvdPlan& p) {
   SvdWork w;
@@ -35,19 +37,27 @@ static SvdWork to_work(const SvdPlan& p) {
   return w;
 }
 
-__global__ __launch_bounds__(kSvdThreads) void svd_qr_kernel(SvdWork w) {
+// QR with 64 rows per lane and the replay with 8 log entries per lane need more than the
+// 128 VGPRs a 1024-thread workgroup leaves each wave; they run 512 threads.
+__host__ __device__ constexpr int qr_threads(int rpl) { return rpl >= 64 ? 512 : 1024; }
+__host__ __device__ constexpr int finish_threads(int epl) { return epl >= 8 ? 512 : 1024; }
+
+template <int RPL>
+__global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_kernel(SvdWork w) {
   extern __shared__ unsigned char smem[];
-  svd_stage_qr(w, smem);
+  svd_stage_qr_rpl<RPL>(w, smem);
 }
 
-__global__ __launch_bounds__(kJacobiThreads) void svd_jacobi_kernel(SvdWork w) {
+template <int NR>
+__global__ __launch_bounds__(jacobi_threads(NR)) void svd_jacobi_kernel(SvdWork w) {
   __shared__ unsigned char smem[64];
-  svd_stage_jacobi(w, smem);
+  svd_stage_jacobi_nr<NR, JacobiB<NR>::value>(w, smem);
 }
 
-__global__ __launch_bounds__(kSvdThreads) void svd_finish_kernel(SvdWork w) {
+template <int EPL>
+__global__ __launch_bounds__(finish_threads(EPL)) void svd_finish_kernel(SvdWork w) {
   extern __shared__ unsigned char smem[];
-  svd_stage_finish(w, smem);
+  svd_stage_finish_epl<EPL>(w, smem);
 }
 
 __global__ __launch_bounds__(kSvdThreads) void svd_kernel(SvdPlan p) {
@@ -73,13 +83,52 @@ size_t svd_work_log_bytes(int s, int N, int max_sweeps) {
 hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
   if (svd_fast_path(p.s, p.N)) {
     const SvdWork w = to_work(p);
-    const size_t l1 = svd_fast_lds_bytes(p.s, p.N, kSvdThreads / 64);
-    hipError_t e = lds_attr((const void*)svd_qr_kernel, l1);
-    if (e == hipSuccess) e = lds_attr((const void*)svd_finish_kernel, l1);
+    hipError_t e = hipSuccess;
+    const int rpl = qr_rpl(p.s), tq = qr_threads(rpl);
+    const size_t lq = svd_fast_lds_bytes(p.s, p.N, tq / 64);
+    switch (rpl) {
+      case 16:
+        e = lds_attr((const void*)svd_qr_kernel<16>, lq);
+        if (e == hipSuccess) svd_qr_kernel<16><<<1, tq, lq, st>>>(w);
+        break;
+      case 32:
+        e = lds_attr((const void*)svd_qr_kernel<32>, lq);
+        if (e == hipSuccess) svd_qr_kernel<32><<<1, tq, lq, st>>>(w);
+        break;
+      default:
+        e = lds_attr((const void*)svd_qr_kernel<64>, lq);
+        if (e == hipSuccess) svd_qr_kernel<64><<<1, tq, lq, st>>>(w);
+        break;
+    }
     if (e != hipSuccess) return e;
-    svd_qr_kernel<<<1, kSvdThreads, l1, st>>>(w);
-    svd_jacobi_kernel<<<1, kJacobiThreads, 0, st>>>(w);
-    svd_finish_kernel<<<1, kSvdThreads, l1, st>>>(w);
+    switch (jacobi_shape(p.N).NR) {
+      case 1: svd_jacobi_kernel<1><<<1, jacobi_threads(1), 0, st>>>(w); break;
+      case 2: svd_jacobi_kernel<2><<<1, jacobi_threads(2), 0, st>>>(w); break;
+      case 3: svd_jacobi_kernel<3><<<1, jacobi_threads(3), 0, st>>>(w); break;
+      case 4: svd_jacobi_kernel<4><<<1, jacobi_threads(4), 0, st>>>(w); break;
+      default: svd_jacobi_kernel<5><<<1, jacobi_threads(5), 0, st>>>(w); break;
+    }
+    const int epl = finish_epl(p.N), tf = finish_threads(epl);
+    const size_t lf = svd_fast_lds_bytes(p.s, p.N, tf / 64);
+    switch (epl) {
+      case 1:
+        e = lds_attr((const void*)svd_finish_kernel<1>, lf);
+        if (e == hipSuccess) svd_finish_kernel<1><<<1, tf, lf, st>>>(w);
+        break;
+      case 2:
+        e = lds_attr((const void*)svd_finish_kernel<2>, lf);
+        if (e == hipSuccess) svd_finish_kernel<2><<<1, tf, lf, st>>>(w);
+        break;
+      case 4:
+        e = lds_attr((const void*)svd_finish_kernel<4>, lf);
+        if (e == hipSuccess) svd_finish_kernel<4><<<1, tf, lf, st>>>(w);
+        break;
+      default:
+        e = lds_attr((const void*)svd_finish_kernel<8>, lf);
+        if (e == hipSuccess) svd_finish_kernel<8><<<1, tf, lf, st>>>(w);
+        break;
+    }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
   }
   const size_t lds = svd_lds_bytes(p.s, p.N);

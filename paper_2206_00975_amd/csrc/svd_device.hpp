@@ -19,14 +19,11 @@
 #include <hip/hip_runtime.h>
 
 #include "nsk_internal.hpp"
+#include "wave_ops.hpp"
 
 namespace nsk {
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ inline double wave_sum(double v) { return wave_sum64(v); }
 
 struct SvdShared {
   double tau;

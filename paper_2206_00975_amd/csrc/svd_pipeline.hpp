@@ -60,45 +60,43 @@ __host__ __device__ inline size_t svd_fast_lds_bytes(int s, int N, int nwaves) {
 }
 
 // ---------------------------------------------------------------- stage 1: QR
-template <int NB>
-__device__ inline void svd_stage_qr_nb(const SvdWork& w, int ldr, unsigned char* smem) {
-  if (w.s <= 1024) qr_panel<16, NB>(w.sa, w.s, w.N, w.R, ldr, smem);
-  else if (w.s <= 2048) qr_panel<32, NB>(w.sa, w.s, w.N, w.R, ldr, smem);
-  else qr_panel<64, NB>(w.sa, w.s, w.N, w.R, ldr, smem);
-}
+// rows per lane of a panel column: s <= 64 RPL
+__host__ __device__ inline int qr_rpl(int s) { return s <= 1024 ? 16 : s <= 2048 ? 32 : 64; }
 
-__device__ inline void svd_stage_qr(const SvdWork& w, unsigned char* smem) {
+template <int RPL>
+__device__ inline void svd_stage_qr_rpl(const SvdWork& w, unsigned char* smem) {
   const JacobiShape js = jacobi_shape(w.N);
   const int ldr = 64 * js.NR;
   const size_t total = (size_t)ldr * js.nb * js.B;
   for (size_t e = threadIdx.x; e < total; e += blockDim.x) w.R[e] = 0.0;
   __syncthreads();
-  const int nb = qr_panel_width(w.s, blockDim.x >> 6);
-  switch (nb) {
-    case 16: svd_stage_qr_nb<16>(w, ldr, smem); break;
-    case 8: svd_stage_qr_nb<8>(w, ldr, smem); break;
-    case 4: svd_stage_qr_nb<4>(w, ldr, smem); break;
-    case 2: svd_stage_qr_nb<2>(w, ldr, smem); break;
-    default: svd_stage_qr_nb<1>(w, ldr, smem); break;
+  switch (qr_panel_width(w.s, blockDim.x >> 6)) {
+    case 16: qr_panel<RPL, 16>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    case 8: qr_panel<RPL, 8>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    case 4: qr_panel<RPL, 4>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    case 2: qr_panel<RPL, 2>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    default: qr_panel<RPL, 1>(w.sa, w.s, w.N, w.R, ldr, smem); break;
   }
   __syncthreads();
 }
 
+__device__ inline void svd_stage_qr(const SvdWork& w, unsigned char* smem) {
+  switch (qr_rpl(w.s)) {
+    case 16: svd_stage_qr_rpl<16>(w, smem); break;
+    case 32: svd_stage_qr_rpl<32>(w, smem); break;
+    default: svd_stage_qr_rpl<64>(w, smem); break;
+  }
+}
+
 // ---------------------------------------------------------------- stage 2: Jacobi
-__device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
+template <int NR, int B>
+__device__ inline void svd_stage_jacobi_nr(const SvdWork& w, unsigned char* smem) {
   const JacobiShape js = jacobi_shape(w.N);
   int* sh_rot = reinterpret_cast<int*>(smem);
   double* sh_off = reinterpret_cast<double*>(smem + 8);
   int conv = 0;
   double off = 0;
-  int sweeps = 0;
-  switch (js.NR) {
-    case 1: sweeps = jacobi_block_sweeps<1, 4>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
-    case 2: sweeps = jacobi_block_sweeps<2, 8>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
-    case 3: sweeps = jacobi_block_sweeps<3, 12>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
-    case 4: sweeps = jacobi_block_sweeps<4, 13>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
-    default: sweeps = jacobi_block_sweeps<5, 10>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off); break;
-  }
+  const int sweeps = jacobi_block_sweeps<NR, B>(w.R, js, w.max_sweeps, w.log, sh_rot, sh_off, &conv, &off);
   if (threadIdx.x == 0) {
     w.jres->sweeps = sweeps;
     w.jres->converged = conv;
@@ -107,7 +105,29 @@ __device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
   __syncthreads();
 }
 
+template <int NR>
+struct JacobiB {
+  static constexpr int value = jacobi_block_size(NR);
+};
+
+__device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
+  switch (jacobi_shape(w.N).NR) {
+    case 1: svd_stage_jacobi_nr<1, JacobiB<1>::value>(w, smem); break;
+    case 2: svd_stage_jacobi_nr<2, JacobiB<2>::value>(w, smem); break;
+    case 3: svd_stage_jacobi_nr<3, JacobiB<3>::value>(w, smem); break;
+    case 4: svd_stage_jacobi_nr<4, JacobiB<4>::value>(w, smem); break;
+    default: svd_stage_jacobi_nr<5, JacobiB<5>::value>(w, smem); break;
+  }
+}
+
 // ---------------------------------------------------------------- stage 3: finish
+// log entries per lane of the widest replay step
+__host__ __device__ inline int finish_epl(int N) {
+  const int e = replay_epl(jacobi_shape(N));
+  return e <= 1 ? 1 : e <= 2 ? 2 : e <= 4 ? 4 : 8;
+}
+
+// x <- V x (transpose = false) or V^T x for one wave; any workgroup size up to 512 threads
 __device__ inline void replay_dispatch(double* x, const double2* log, const JacobiShape& js, int sweeps,
                                        bool transpose, int lane) {
   const int epl = replay_epl(js);
@@ -117,7 +137,8 @@ __device__ inline void replay_dispatch(double* x, const double2* log, const Jaco
   else jacobi_replay<8>(x, log, js, sweeps, transpose, lane);
 }
 
-__device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
+template <int EPL>
+__device__ inline void svd_stage_finish_epl(const SvdWork& w, unsigned char* smem) {
   const JacobiShape js = jacobi_shape(w.N);
   const int N = w.N, k = w.k;
   const int ldr = 64 * js.NR;
@@ -160,7 +181,7 @@ __device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
     if (q < k) {
       const int c = w.order[N - k + q];
       for (int e = lane; e < ncols; e += 64) x[e] = e == c ? 1.0 : 0.0;
-      replay_dispatch(x, w.log, js, sweeps, false, lane);
+      jacobi_replay<EPL>(x, w.log, js, sweeps, false, lane);
       // sign: largest-magnitude entry positive, lowest index on ties
       double best = -1;
       int bi = 0;
@@ -188,6 +209,15 @@ __device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
     w.info->sigma_max = w.sigma[0];
   }
   __syncthreads();
+}
+
+__device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
+  switch (finish_epl(w.N)) {
+    case 1: svd_stage_finish_epl<1>(w, smem); break;
+    case 2: svd_stage_finish_epl<2>(w, smem); break;
+    case 4: svd_stage_finish_epl<4>(w, smem); break;
+    default: svd_stage_finish_epl<8>(w, smem); break;
+  }
 }
 
 __device__ inline void svd_pipeline(const SvdWork& w, unsigned char* smem) {
