@@ -52,8 +52,10 @@ int plan_groups(const nsk_desc* d, int64_t m, int64_t N) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, (1024 + ct - 1) / ct));
   }
   if (d->kind == NSK_SPARSE_SIGN) {
-    const int64_t ct = (N + 15) / 16, nb = (m + 1023) / 1024;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, (512 + ct - 1) / ct));
+    // one workgroup per CU (the accumulator fills most of the LDS): about 256 workgroups
+    const int cols = sparse_cols((int)d->s, dflt_zeta(d), dflt_acc(d));
+    const int64_t ct = (N + cols - 1) / cols, nb = (m + 1023) / 1024;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256 / ct));
   }
   const int64_t ks = (m + 31) / 32;
   return (int)std::max<int64_t>(1, std::min<int64_t>(256, (ks + 7) / 8));
@@ -111,6 +113,8 @@ int check_desc(const nsk_desc* d, int64_t m, int64_t N) {
     if (z < 1 || z > 32 || z > d->s || d->s > 65535) return NSK_EINVAL;
   }
   if (d->kind == NSK_SRHT && d->s > 2048) return NSK_EUNSUPPORTED;
+  if (d->kind == NSK_SPARSE_SIGN && sparse_lds_bytes((int)d->s, dflt_zeta(d), dflt_acc(d)) > 160 * 1024)
+    return NSK_EUNSUPPORTED;
   if (d->kind == NSK_GAUSSIAN && gauss_tiles_per_wave((int)d->s, (int)N) > 48) return NSK_EUNSUPPORTED;
   if (d->acc != 0 && d->acc != NSK_F64 && d->acc != NSK_F32) return NSK_EINVAL;
   if (d->max_sweeps < 0 || d->row_groups < 0) return NSK_EINVAL;

@@ -335,85 +335,222 @@ __device__ inline int jacobi_block_sweeps(double* __restrict__ R, const JacobiSh
 }
 
 // ------------------------------------------------------------------ log replay
-// Column pair of log slot (group g, slot l) at sweep-local step st; false if the slot holds
-// no rotation or touches a padding column.  Orientation (gp, gq) matches the kernel: x = gp.
-__device__ inline bool step_pair(const JacobiShape& js, int st, int g, int l, int& gp, int& gq) {
-  if (st < js.bq - 1) {
-    if (l >= js.bq / 2) return false;
-    const int a = circle_pos(l, st, js.bq), b = circle_pos(js.bq - 1 - l, st, js.bq);
-    if (a >= js.B || b >= js.B) return false;
-    gp = g * js.B + a;
-    gq = g * js.B + b;
-  } else {
-    if (l >= js.B) return false;
-    const int t = st - (js.bq - 1);
-    const int r = t / js.B, j = t % js.B;
-    int I = circle_pos(g, r, js.nb), J = circle_pos(js.nb - 1 - g, r, js.nb);
-    if (I > J) { const int u = I; I = J; J = u; }
-    gp = I * js.B + l;
-    gq = J * js.B + (l + j) % js.B;
-  }
-  return gp < js.N && gq < js.N;
+// One wave applies the logged rotations to a vector x (LDS, nb * B doubles, zero beyond N).
+// x <- V x (fwd = false) takes the steps from last to first with [x_p, x_q] <- [c x_p + s x_q,
+// -s x_p + c x_q]; x <- V^T x (fwd = true) takes them from first to last with [x_p, x_q] <-
+// [c x_p - s x_q, s x_p + c x_q].  Lanes follow the Jacobi kernel's register schedule: in an
+// intra phase lane g holds block g, in block round r lane g holds the blocks of pair g, and
+// positions move between registers exactly as the columns did, so every slot of a step is a
+// compile-time register pair.  Rotations on padding columns were logged as (1, 0).
+//
+// The log streams through LDS (stage, replay_stage_bytes()) in chunks of whole steps of at
+// most kReplayE entries; the next chunk is loaded into registers while the current one is
+// applied.  Entry k of a chunk sits at k + k / 16 so that the lanes of a step, which read
+// entries 16 apart, fall in different banks.
+constexpr int kReplayCH = 24;
+constexpr int kReplayE = kReplayCH * 64;
+
+__host__ __device__ constexpr size_t replay_stage_bytes() {
+  return (size_t)(kReplayE + kReplayE / 16) * sizeof(double2);
 }
 
 __device__ inline int step_groups(const JacobiShape& js, int st) { return st < js.bq - 1 ? js.nb : js.nb / 2; }
 
-// One wave applies the logged rotations to the vector x (LDS, nb * B doubles).
-// transpose = false: x <- V x, steps from last to first with [x_p, x_q] <- [c x_p + s x_q,
-// -s x_p + c x_q].  transpose = true: x <- V^T x, steps from first to last with
-// [x_p, x_q] <- [c x_p - s x_q, s x_p + c x_q].  Log entries are prefetched kD steps ahead.
-template <int EPL>
-__device__ inline void jacobi_replay(double* x, const double2* __restrict__ log, const JacobiShape& js, int sweeps,
-                                     bool transpose, int lane) {
-  constexpr int kD = 4;
-  const size_t per_sweep = jacobi_log_entries_per_sweep(js);
-  const int total = sweeps * js.spw;
-  auto step_of = [&](int t) { return transpose ? t : total - 1 - t; };
-  auto load = [&](int t, double2 (&dst)[EPL]) {
-    const int g = step_of(t);
-    const int st = g % js.spw;
-    const int ent = step_groups(js, st) * 16;
-    const double2* base = log + (size_t)(g / js.spw) * per_sweep + jacobi_log_step_offset(js, st);
-#pragma unroll
-    for (int u = 0; u < EPL; ++u) {
-      const int e = lane + 64 * u;
-      dst[u] = e < ent ? base[e] : make_double2(1.0, 0.0);
+struct StepPos {
+  int sw, st;
+};
+
+__device__ inline size_t step_begin(const JacobiShape& js, size_t per_sweep, StepPos p) {
+  return (size_t)p.sw * per_sweep + jacobi_log_step_offset(js, p.st);
+}
+
+__device__ inline void step_advance(const JacobiShape& js, StepPos& p, bool fwd) {
+  if (fwd) {
+    if (++p.st == js.spw) {
+      p.st = 0;
+      ++p.sw;
     }
-  };
-  double2 buf[kD][EPL];
-#pragma unroll
-  for (int d = 0; d < kD; ++d)
-    if (d < total) load(d, buf[d]);
-  for (int t0 = 0; t0 < total; t0 += kD) {
-#pragma unroll
-    for (int d = 0; d < kD; ++d) {
-      const int t = t0 + d;
-      if (t < total) {
-        const int st = step_of(t) % js.spw;
-        const int ent = step_groups(js, st) * 16;
-#pragma unroll
-        for (int u = 0; u < EPL; ++u) {
-          const int e = lane + 64 * u;
-          int gp, gq;
-          if (e < ent && step_pair(js, st, e >> 4, e & 15, gp, gq)) {
-            const double c = buf[d][u].x, s = buf[d][u].y;
-            const double xp = x[gp], xq = x[gq];
-            if (transpose) {
-              x[gp] = c * xp - s * xq;
-              x[gq] = s * xp + c * xq;
-            } else {
-              x[gp] = c * xp + s * xq;
-              x[gq] = -s * xp + c * xq;
-            }
-          }
-        }
-        if (t + kD < total) load(t + kD, buf[d]);
-      }
-    }
+  } else if (p.st-- == 0) {
+    p.st = js.spw - 1;
+    --p.sw;
   }
 }
 
-// entries per lane: intra steps have nb * 16 slots
-__host__ __device__ inline int replay_epl(const JacobiShape& js) { return (js.nb * 16 + 63) / 64; }
+struct LogStream {
+  const double2* log;
+  double2* stage;
+  const JacobiShape* js;
+  size_t per_sweep;
+  long long steps;      // total steps to replay
+  bool fwd;
+  StepPos plan;         // position of step next_t (processing order)
+  long long next_t;     // first step of the prefetched chunk's successor
+  size_t pre_base;      // first log entry of the prefetched chunk
+  size_t pre_end;
+  long long pre_t1;     // steps [.., pre_t1) are in the prefetched chunk
+  long long cur_t1;     // steps [.., cur_t1) are staged in LDS
+  size_t cur_base;
+  double2 pre[kReplayCH];
+
+  // plan the chunk starting at step next_t and load it into pre[]
+  __device__ void prefetch(int lane) {
+    size_t lo = ~(size_t)0, hi = 0;
+    long long t = next_t;
+    while (t < steps) {
+      const size_t b = step_begin(*js, per_sweep, plan);
+      const size_t e = b + (size_t)step_groups(*js, plan.st) * 16;
+      const size_t nlo = b < lo ? b : lo, nhi = e > hi ? e : hi;
+      if (nhi - nlo > (size_t)kReplayE) break;
+      lo = nlo;
+      hi = nhi;
+      ++t;
+      step_advance(*js, plan, fwd);
+    }
+    pre_base = lo;
+    pre_end = hi;
+    pre_t1 = t;
+    next_t = t;
+#pragma unroll
+    for (int u = 0; u < kReplayCH; ++u) {
+      const size_t e = lo + lane + 64 * u;
+      pre[u] = e < hi ? log[e] : make_double2(1.0, 0.0);
+    }
+  }
+
+  __device__ void init(const double2* lg, double2* stg, const JacobiShape* shape, int sweeps, bool forward,
+                       int lane) {
+    log = lg;
+    stage = stg;
+    js = shape;
+    per_sweep = jacobi_log_entries_per_sweep(*shape);
+    steps = (long long)sweeps * shape->spw;
+    fwd = forward;
+    plan = forward ? StepPos{0, 0} : StepPos{sweeps - 1, shape->spw - 1};
+    next_t = 0;
+    cur_t1 = 0;
+    cur_base = 0;
+    if (steps > 0) prefetch(lane);
+  }
+
+  // make step t (processing order) readable from LDS
+  __device__ void ensure(long long t, int lane) {
+    if (t < cur_t1) return;
+#pragma unroll
+    for (int u = 0; u < kReplayCH; ++u) {
+      const int k = lane + 64 * u;
+      stage[k + (k >> 4)] = pre[u];
+    }
+    __builtin_amdgcn_wave_barrier();
+    cur_t1 = pre_t1;
+    cur_base = pre_base;
+    if (next_t < steps) prefetch(lane);
+  }
+
+  // (c, s) of slot i of group g at step position p (staged)
+  __device__ double2 entry(StepPos p, int g, int i) const {
+    const size_t k0 = step_begin(*js, per_sweep, p) - cur_base;
+    return stage[17 * ((int)(k0 >> 4) + g) + i];
+  }
+};
+
+__device__ inline void rot_pair(double& x, double& y, double2 cs, bool fwd) {
+  const double c = cs.x, s = fwd ? cs.y : -cs.y;
+  const double a = x, b = y;
+  x = c * a - s * b;
+  y = s * a + c * b;
+}
+
+template <int B>
+__device__ inline void jacobi_replay(double* x, const double2* __restrict__ log, const JacobiShape& js, int sweeps,
+                                     bool fwd, int lane, double2* stage) {
+  constexpr int BQ = B + (B & 1);
+  constexpr int H = BQ / 2;
+  LogStream ls;
+  ls.init(log, stage, &js, sweeps, fwd, lane);
+  long long t = 0;
+  const int nb = js.nb, nbp = js.nb / 2;
+  auto intra = [&](int sw) {
+    const bool act = lane < nb;
+    double X[BQ];
+#pragma unroll
+    for (int b = 0; b < BQ; ++b) X[b] = act && b < B ? x[lane * B + b] : 0.0;
+    for (int qi = 0; qi < BQ - 1; ++qi) {
+      const int q = fwd ? qi : BQ - 2 - qi;
+      ls.ensure(t++, lane);
+      if (!fwd) {  // undo the circle shift that followed step q
+        const double last = X[BQ - 1];
+#pragma unroll
+        for (int b = BQ - 1; b > 1; --b) X[b] = X[b - 1];
+        X[1] = last;
+      }
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < H; ++i) rot_pair(X[i], X[BQ - 1 - i], ls.entry(StepPos{sw, q}, lane, i), fwd);
+      }
+      if (fwd) {
+        const double first = X[1];
+#pragma unroll
+        for (int b = 1; b < BQ - 1; ++b) X[b] = X[b + 1];
+        X[BQ - 1] = first;
+      }
+    }
+    if (act)
+#pragma unroll
+      for (int b = 0; b < B; ++b) x[lane * B + b] = X[b];
+  };
+  auto round = [&](int sw, int r) {
+    const bool act = lane < nbp;
+    int I = circle_pos(lane, r, nb), J = circle_pos(nb - 1 - lane, r, nb);
+    if (I > J) {
+      const int u = I;
+      I = J;
+      J = u;
+    }
+    if (!act) I = J = 0;
+    double T[B], U[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      T[b] = act ? x[I * B + b] : 0.0;
+      U[b] = act ? x[J * B + b] : 0.0;
+    }
+    for (int ji = 0; ji < B; ++ji) {
+      const int j = fwd ? ji : B - 1 - ji;
+      ls.ensure(t++, lane);
+      if (!fwd) {  // undo the move of U's slots that followed sub-round j
+        const double last = U[B - 1];
+#pragma unroll
+        for (int b = B - 1; b > 0; --b) U[b] = U[b - 1];
+        U[0] = last;
+      }
+      if (act) {
+        const StepPos p{sw, js.bq - 1 + r * B + j};
+#pragma unroll
+        for (int i = 0; i < B; ++i) rot_pair(T[i], U[i], ls.entry(p, lane, i), fwd);
+      }
+      if (fwd) {
+        const double first = U[0];
+#pragma unroll
+        for (int b = 0; b < B - 1; ++b) U[b] = U[b + 1];
+        U[B - 1] = first;
+      }
+    }
+    if (act)
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        x[I * B + b] = T[b];
+        x[J * B + b] = U[b];
+      }
+  };
+  for (int si = 0; si < sweeps; ++si) {
+    const int sw = fwd ? si : sweeps - 1 - si;
+    if (fwd) {
+      intra(sw);
+      for (int r = 0; r < nb - 1; ++r) round(sw, r);
+    } else {
+      for (int r = nb - 2; r >= 0; --r) round(sw, r);
+      intra(sw);
+    }
+  }
+}
 
 }  // namespace nsk

@@ -10,9 +10,54 @@
 namespace nsk {
 
 // ============================================================================ residual
+// |A V_k|_F^2 = sum over rows r and vectors q of (a_r . v_q)^2.  A wave takes RT rows at a
+// time: lane l loads columns l + 64 i of all RT rows (every load of the tile in flight at
+// once, each row read as contiguous 256-byte segments), accumulates the RT partial dots
+// per vector in FP64, and one transposed reduction leaves row (l >> (6 - log2 RT))'s dot in
+// lane l.  Per-workgroup partial sums are combined in a fixed order by residual_finish, so
+// the result is bitwise reproducible.
 constexpr int kResThreads = 256;
 
-template <typename T>
+// Column group i of this lane for the pass starting at column cb: pointers resolved once;
+// invalid columns read column 0 and are masked after the load.
+template <typename T, int CI>
+__device__ inline void residual_columns(const Operand& op, int N, int cb, int lane, const T* (&base)[CI],
+                                        int64_t (&ld)[CI], bool (&live)[CI]) {
+#pragma unroll
+  for (int i = 0; i < CI; ++i) {
+    const int c = cb + lane + 64 * i;
+    live[i] = c < N;
+    column_ref<T>(op, live[i] ? c : 0, base[i], ld[i]);
+  }
+}
+
+// Adds this lane's contribution of columns cb + lane + 64 i to the RT row dots d[q][r].
+// Every load of the tile is issued before the first use (rows past the end re-read row r0).
+template <typename T, int KQ, int RT, int CI>
+__device__ inline void residual_tile(const T* (&base)[CI], const int64_t (&ld)[CI], const bool (&live)[CI],
+                                     const double* vsh, int cb, int k, int q0, int64_t r0, int nrow, int lane,
+                                     double (&d)[KQ][16]) {
+  T a[CI][RT];
+#pragma unroll
+  for (int i = 0; i < CI; ++i)
+#pragma unroll
+    for (int r = 0; r < RT; ++r) a[i][r] = base[i][(r0 + (r < nrow ? r : 0)) * ld[i]];
+#pragma unroll
+  for (int i = 0; i < CI; ++i) {
+    double v[KQ];
+    const int c = cb + lane + 64 * i;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) v[q] = live[i] && q0 + q < k ? vsh[c * k + q0 + q] : 0.0;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const double x = r < nrow ? (double)a[i][r] : 0.0;
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) d[q][r] += x * v[q];
+    }
+  }
+}
+
+template <typename T, int KQ, int RT, int CI>
 __global__ __launch_bounds__(kResThreads) void residual_kernel(Operand op, int64_t m, int N,
                                                                const double* __restrict__ Vk, int k,
                                                                double* __restrict__ partial) {
@@ -20,29 +65,44 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Operand op, int64
   __shared__ double wsum[kResThreads / 64];
   for (int e = threadIdx.x; e < N * k; e += blockDim.x) vsh[e] = Vk[e];
   __syncthreads();
+  constexpr int SH = 6 - ceil_log2(RT);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
+  const int my_row = lane >> SH;
+  const bool lead = (lane & ((1 << SH) - 1)) == 0;
+  const bool one_pass = N <= 64 * CI;
+  const T* base[CI];
+  int64_t ld[CI];
+  bool live[CI];
+  residual_columns<T, CI>(op, N, 0, lane, base, ld, live);
   double local = 0;
-  for (int64_t row = (int64_t)blockIdx.x * wpb + wave; row < m; row += (int64_t)gridDim.x * wpb) {
-    for (int q0 = 0; q0 < k; q0 += 4) {
-      double d[4] = {0, 0, 0, 0};
-      for (int c = lane; c < N; c += 64) {
-        const T* b;
-        int64_t ld;
-        column_ref<T>(op, c, b, ld);
-        const double a = (double)b[row * ld];
+  for (int64_t r0 = ((int64_t)blockIdx.x * wpb + wave) * RT; r0 < m; r0 += (int64_t)gridDim.x * wpb * RT) {
+    const int nrow = m - r0 < RT ? (int)(m - r0) : RT;
+    for (int q0 = 0; q0 < k; q0 += KQ) {
+      double d[KQ][16];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (q0 + q < k) d[q] += a * vsh[c * k + q0 + q];
+      for (int q = 0; q < KQ; ++q)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) d[q][r] = 0;
+      if (one_pass) {
+        residual_tile<T, KQ, RT, CI>(base, ld, live, vsh, 0, k, q0, r0, nrow, lane, d);
+      } else {
+        for (int cb = 0; cb < N; cb += 64 * CI) {
+          const T* pb[CI];
+          int64_t pl[CI];
+          bool pv[CI];
+          residual_columns<T, CI>(op, N, cb, lane, pb, pl, pv);
+          residual_tile<T, KQ, RT, CI>(pb, pl, pv, vsh, cb, k, q0, r0, nrow, lane, d);
+        }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (q0 + q < k) {
-          const double t = wave_sum(d[q]);
-          local += t * t;
-        }
+      for (int q = 0; q < KQ; ++q) {
+        const double t = reduce_t<RT>(d[q], lane);
+        if (lead && my_row < nrow && q0 + q < k) local += t * t;
+      }
     }
   }
+  local = wave_sum64(local);
   if (lane == 0) wsum[wave] = local;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -52,10 +112,12 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Operand op, int64
   }
 }
 
+// Fixed-order sum of the partials: lane l adds parts l, l + 64, ...; then a fixed butterfly.
 __global__ void residual_finish(const double* __restrict__ partial, int parts, double* out, nsk_info* info) {
-  if (threadIdx.x != 0) return;
   double t = 0;
-  for (int i = 0; i < parts; ++i) t += partial[i];
+  for (int i = threadIdx.x; i < parts; i += 64) t += partial[i];
+  t = wave_sum64(t);
+  if (threadIdx.x != 0) return;
   const double r = sqrt(t);
   if (out) *out = r;
   if (info) info->residual = r;
@@ -65,10 +127,19 @@ hipError_t launch_residual(const Operand& op, int64_t m, const double* Vk, int k
                            double* out, nsk_info* info, hipStream_t st) {
   const int N = op.col0[op.nb];
   const size_t lds = (size_t)N * k * sizeof(double);
-  if (op.dtype == NSK_F64)
-    residual_kernel<double><<<parts, kResThreads, lds, st>>>(op, m, N, Vk, k, partial);
-  else
-    residual_kernel<float><<<parts, kResThreads, lds, st>>>(op, m, N, Vk, k, partial);
+#define NSK_RES(T, KQ, RT, CI) \
+  residual_kernel<T, KQ, RT, CI><<<parts, kResThreads, lds, st>>>(op, m, N, Vk, k, partial)
+  const bool wide = N > 128;
+  if (op.dtype == NSK_F64) {
+    if (k == 1) { if (wide) NSK_RES(double, 1, 8, 4); else NSK_RES(double, 1, 16, 2); }
+    else if (k == 2) { if (wide) NSK_RES(double, 2, 8, 4); else NSK_RES(double, 2, 16, 2); }
+    else { if (wide) NSK_RES(double, 4, 4, 4); else NSK_RES(double, 4, 8, 2); }
+  } else {
+    if (k == 1) { if (wide) NSK_RES(float, 1, 16, 4); else NSK_RES(float, 1, 16, 2); }
+    else if (k == 2) { if (wide) NSK_RES(float, 2, 16, 4); else NSK_RES(float, 2, 16, 2); }
+    else { if (wide) NSK_RES(float, 4, 8, 4); else NSK_RES(float, 4, 8, 2); }
+  }
+#undef NSK_RES
   residual_finish<<<1, 64, 0, st>>>(partial, parts, out, info);
   return hipGetLastError();
 }
@@ -97,6 +168,7 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
   const int ncols = js.nb * js.B;
   double* xb = sm;             // ncols
   double* wl = xb + ncols;     // N: w
+  double2* stage = reinterpret_cast<double2*>(sm + ((ncols + N + 1) & ~1));
   __shared__ double red[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = N - 1;
@@ -116,7 +188,7 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
   for (int e = tid; e < ncols; e += blockDim.x) xb[e] = e < N ? inv * (e < n ? gx[e] : gx_x) : 0.0;
   __syncthreads();
   const int sweeps = tb.jres->sweeps;
-  if (wave == 0) replay_dispatch(xb, tb.log, js, sweeps, true, lane);
+  if (wave == 0) replay_any(xb, tb.log, js, sweeps, true, lane, stage);
   __syncthreads();
   const int cN = tb.order[N - 1];
   const double lamN = tb.colnorm[cN] * tb.colnorm[cN];
@@ -125,7 +197,7 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
     xb[c] = (c < N && c != cN) ? xb[c] / (lamN - sc * sc) : 0.0;
   }
   __syncthreads();
-  if (wave == 0) replay_dispatch(xb, tb.log, js, sweeps, false, lane);
+  if (wave == 0) replay_any(xb, tb.log, js, sweeps, false, lane, stage);
   __syncthreads();
   for (int e = tid; e < N; e += blockDim.x) wl[e] = xb[e];
   __syncthreads();
@@ -232,7 +304,7 @@ hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const TlsBack& tb
                                void* dA, int64_t ldda, void* db, int out_dtype, hipStream_t st) {
   const int N = p.N, s = p.s;
   const JacobiShape js = jacobi_shape(N);
-  const size_t alds = (size_t)(js.nb * js.B + N) * sizeof(double);
+  const size_t alds = (size_t)((js.nb * js.B + N + 1) & ~1) * sizeof(double) + replay_stage_bytes();
   tls_adjoint_kernel<<<1, 512, alds, st>>>(s, N, tb, gx, work);
   const size_t lds = (size_t)(2 * s + 2 * N) * sizeof(double) + (size_t)s * 4;
   const unsigned blocks = (unsigned)((m + 4 * 64 - 1) / (4 * 64)) < 4096u ? (unsigned)((m + 255) / 256) : 4096u;

@@ -5,8 +5,9 @@
 // alpha = a_jj and sigma^2 the squared norm below it, beta = -sign(alpha) sqrt(alpha^2 +
 // sigma^2), tau = (beta - alpha) / beta and v = (x - beta e) / (alpha - beta) (v_jj = 1);
 // v goes to LDS and the later panel columns apply H = I - tau v v^T.  The columns to the
-// right of the panel are then loaded once per panel, receive the NB reflections in order and
-// are written back, so the trailing matrix is read and written once per NB columns.  R is
+// right of the panel are then loaded once per panel, CPW at a time per wave, receive the NB
+// reflections in order and are written back, so the trailing matrix is read and written once
+// per NB columns and each Householder vector is read from LDS once per CPW columns.  R is
 // written into a zero-filled N_pad x N_pad column-major buffer whose extra rows/columns stay
 // zero.
 #pragma once
@@ -21,7 +22,7 @@ namespace nsk {
 // LDS bytes: NB * s doubles of Householder vectors + NB taus.
 __host__ __device__ inline size_t qr_panel_lds_bytes(int s, int NB) { return (size_t)NB * s * 8 + NB * 8 + 64; }
 
-template <int RPL, int NB>
+template <int RPL, int NB, int CPW>
 __device__ inline void qr_panel(double* __restrict__ A, int s, int N, double* __restrict__ R, int ldr,
                                 unsigned char* smem) {
   double* vbuf = reinterpret_cast<double*>(smem);      // NB x s (relative rows)
@@ -30,10 +31,12 @@ __device__ inline void qr_panel(double* __restrict__ A, int s, int N, double* __
   for (int j0 = 0; j0 < N; j0 += NB) {
     const int nbc = N - j0 < NB ? N - j0 : NB;
     const int rows = s - j0;  // relative rows 0..rows-1
-    double col[RPL];
+    // cl[0] holds a wave's panel column; all of cl holds its trailing columns afterwards
+    double cl[CPW][RPL];
+    double (&col)[RPL] = cl[0];
     const bool owner = wave < nbc;
     if (owner) {
-      const double* a = A + (size_t)(j0 + wave) * s + j0;
+      const double* a = uniform_ptr(A + (size_t)(j0 + wave) * s + j0);
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int rr = lane + 64 * i;
@@ -91,33 +94,50 @@ __device__ inline void qr_panel(double* __restrict__ A, int s, int N, double* __
       }
     }
     // trailing columns: the panel's reflections in order, one load/store per column
-    for (int c = j0 + nbc + wave; c < N; c += nw) {
-      double* a = A + (size_t)c * s + j0;
+    for (int c0 = j0 + nbc + wave * CPW; c0 < N; c0 += nw * CPW) {
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int rr = lane + 64 * i;
-        col[i] = rr < rows ? a[rr] : 0.0;
+      for (int u = 0; u < CPW; ++u) {
+        const bool cu = c0 + u < N;
+        const double* a = uniform_ptr(A + (size_t)(cu ? c0 + u : c0) * s + j0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          cl[u][i] = cu && rr < rows ? a[rr] : 0.0;
+        }
       }
       for (int jj = 0; jj < nbc; ++jj) {
         const double* v = vbuf + (size_t)jj * s;
-        double d = 0;
+        double d[CPW];
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) d[u] = 0;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
           const int rr = lane + 64 * i;
-          if (rr < rows) d += v[rr] * col[i];
+          const double vv = rr < rows ? v[rr] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) d[u] += vv * cl[u][i];
         }
-        d = wave_sum64(d) * tau[jj];
+        const double tj = tau[jj];
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) d[u] = wave_sum64(d[u]) * tj;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
           const int rr = lane + 64 * i;
-          if (rr < rows) col[i] -= d * v[rr];
+          const double vv = rr < rows ? v[rr] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) cl[u][i] -= d[u] * vv;
         }
       }
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int rr = lane + 64 * i;
-        if (rr < nbc) R[(size_t)c * ldr + j0 + rr] = col[i];
-        else if (rr < rows) a[rr] = col[i];
+      for (int u = 0; u < CPW; ++u) {
+        if (c0 + u >= N) continue;
+        double* a = opaque_uniform(A + (size_t)(c0 + u) * s + j0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          if (rr < nbc) R[(size_t)(c0 + u) * ldr + j0 + rr] = cl[u][i];
+          else if (rr < rows) a[rr] = cl[u][i];
+        }
       }
     }
     __syncthreads();

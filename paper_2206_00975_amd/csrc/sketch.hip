@@ -21,6 +21,7 @@
 
 #include "nsk_internal.hpp"
 #include "sketch_device.hpp"
+#include "wave_ops.hpp"
 
 namespace nsk {
 
@@ -31,68 +32,107 @@ static hipError_t set_lds_limit(const void* fn, size_t bytes) {
 }
 
 // ============================================================================ sparse sign
-constexpr int kSpCols = 16;
+// Workgroup (column tile of COLS columns, row group g) keeps an s x COLS accumulator of SA in
+// LDS.  Rows are taken in chunks of kSpThreads: thread t draws the zeta (row, sign) pairs of
+// input row r0 + t into LDS, and thread (rs, col) adds its column's value of rows r0 + rs +
+// (kSpThreads / COLS) i into those zeta accumulator rows with LDS atomics.  The pipeline is
+// one chunk deep: while chunk i is accumulated, chunk i + 1's values are in flight to
+// registers and its draws are written to the other half of a double-buffered table.
 constexpr int kSpThreads = 1024;
 
-template <typename TIn, typename TAcc, int ZMAX>
+template <typename TIn, typename TAcc, int ZMAX, int COLS>
 __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t m, int N, int s,
                                                             int zeta, uint64_t seed, int groups,
                                                             TAcc* __restrict__ partial) {
+  constexpr int RPP = kSpThreads / COLS;  // rows per pass of the workgroup
+  constexpr int VPT = COLS;               // values per thread per chunk (kSpThreads / RPP)
   extern __shared__ unsigned char smem_raw[];
-  TAcc* acc = reinterpret_cast<TAcc*>(smem_raw);                       // s x kSpCols
-  uint16_t* hrow = reinterpret_cast<uint16_t*>(acc + (size_t)s * kSpCols);  // kSpThreads x ZMAX
-  uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + kSpThreads * ZMAX + 16);
+  TAcc* acc = reinterpret_cast<TAcc*>(smem_raw);                                  // s x COLS
+  uint16_t* hrow = reinterpret_cast<uint16_t*>(acc + (size_t)s * COLS);          // 2 x kSpThreads x ZMAX
+  uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + 2 * kSpThreads * ZMAX);     // 2 x kSpThreads
 
   const int t = threadIdx.x;
-  const int col = t & (kSpCols - 1);
-  const int rs = t >> 4;  // 0..63
-  const int c = blockIdx.x * kSpCols + col;
+  const int col = t % COLS;
+  const int rs = t / COLS;
+  const int c = blockIdx.x * COLS + col;
   const bool live = c < N;
   const int g = blockIdx.y;
 
+  // dead columns read column 0 and are masked after the load (no branch around the loads)
   const TIn* base = nullptr;
   int64_t ld = 0;
-  if (live) column_ref<TIn>(op, c, base, ld);
+  column_ref<TIn>(op, live ? c : 0, base, ld);
 
-  for (int i = t; i < s * kSpCols; i += kSpThreads) acc[i] = 0;
+  for (int i = t; i < s * COLS; i += kSpThreads) acc[i] = 0;
 
   const int64_t rows_per_group = ((m + groups - 1) / groups + kSpThreads - 1) / kSpThreads * kSpThreads;
   const int64_t gr0 = (int64_t)g * rows_per_group;
   const int64_t gr1 = gr0 + rows_per_group < m ? gr0 + rows_per_group : m;
 
-  for (int64_t r0 = gr0; r0 < gr1; r0 += kSpThreads) {
-    __syncthreads();
-    {  // hashes of rows r0 + t
-      const int64_t j = r0 + t;
-      if (j < gr1) {
-        int rw[ZMAX];
-        uint32_t nb;
-        sparse_column<ZMAX>(seed, (uint64_t)j, s, zeta, rw, nb);
+  auto draw = [&](int64_t r0, int buf) {
+    const int64_t j = r0 + t;
+    if (j < gr1) {
+      int rw[ZMAX];
+      uint32_t nb;
+      sparse_column<ZMAX>(seed, (uint64_t)j, s, zeta, rw, nb);
+      uint16_t* hr = hrow + (size_t)buf * kSpThreads * ZMAX;
 #pragma unroll
-        for (int q = 0; q < ZMAX; ++q)
-          if (q < zeta) hrow[t * ZMAX + q] = (uint16_t)rw[q];
-        hneg[t] = nb;
-      }
+      for (int q = 0; q < ZMAX; ++q)
+        if (q < zeta) hr[t * ZMAX + q] = (uint16_t)rw[q];
+      hneg[buf * kSpThreads + t] = nb;
     }
-    __syncthreads();
-    const int nrow = (int)((gr1 - r0) < kSpThreads ? (gr1 - r0) : kSpThreads);
-    for (int q = rs; q < nrow; q += kSpThreads / kSpCols) {
-      if (!live) break;
-      const TAcc a = (TAcc)to_f64(base[(r0 + q) * ld]);
-      const uint32_t nb = hneg[q];
+  };
+  auto fetch = [&](int64_t r0, TIn (&v)[VPT]) {
 #pragma unroll
-      for (int z = 0; z < ZMAX; ++z) {
-        if (z < zeta) {
-          const int h = hrow[q * ZMAX + z];
-          atomicAdd(&acc[h * kSpCols + col], ((nb >> z) & 1u) ? -a : a);
+    for (int i = 0; i < VPT; ++i) {
+      const int64_t r = r0 + rs + RPP * i;
+      v[i] = base[(r < gr1 ? r : r0) * ld];
+    }
+  };
+
+  // chunk i + 1's values load into the register set chunk i does not use (two sets taken in
+  // turn, so no copy forces an early wait on the loads in flight)
+  auto step = [&](int64_t r0, int buf, TIn (&cur)[VPT], TIn (&nxt)[VPT]) {
+    const int64_t r1 = r0 + kSpThreads;
+    if (r1 < gr1) {
+      fetch(r1, nxt);
+      draw(r1, buf ^ 1);
+    }
+    if (live) {
+      const uint16_t* hr = hrow + (size_t)buf * kSpThreads * ZMAX;
+      const uint32_t* hn = hneg + buf * kSpThreads;
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int q = rs + RPP * i;
+        if (r0 + q < gr1) {
+          const TAcc a = (TAcc)to_f64(cur[i]);
+          const uint32_t nb = hn[q];
+#pragma unroll
+          for (int z = 0; z < ZMAX; ++z) {
+            if (z < zeta) {
+              const int h = hr[q * ZMAX + z];
+              atomicAdd(&acc[h * COLS + col], ((nb >> z) & 1u) ? -a : a);
+            }
+          }
         }
       }
     }
+    lds_barrier();
+  };
+
+  TIn va[VPT], vb[VPT];
+  if (gr0 < gr1) {
+    fetch(gr0, va);
+    draw(gr0, 0);
   }
-  __syncthreads();
+  lds_barrier();
+  for (int64_t r0 = gr0; r0 < gr1; r0 += 2 * kSpThreads) {
+    step(r0, 0, va, vb);
+    if (r0 + kSpThreads < gr1) step(r0 + kSpThreads, 1, vb, va);
+  }
   TAcc* out = partial + (size_t)g * s * N;
-  for (int i = t; i < s * kSpCols; i += kSpThreads) {
-    const int row = i / kSpCols, cc = blockIdx.x * kSpCols + (i % kSpCols);
+  for (int i = t; i < s * COLS; i += kSpThreads) {
+    const int row = i / COLS, cc = blockIdx.x * COLS + (i % COLS);
     if (cc < N) out[(size_t)row * N + cc] = acc[i];
   }
 }
@@ -245,26 +285,37 @@ static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStrea
   return hipGetLastError();
 }
 
-template <typename TIn, typename TAcc>
-static hipError_t sparse_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
-  dim3 grid((p.N + kSpCols - 1) / kSpCols, p.groups);
-  const int zmax = p.zeta <= 8 ? 8 : 32;
-  const size_t lds = (size_t)p.s * kSpCols * sizeof(TAcc) + (size_t)kSpThreads * zmax * 2 + 64 +
-                     kSpThreads * 4;
-  TAcc* part = static_cast<TAcc*>(p.partial);
-  if (zmax == 8) {
-    if (hipError_t e = set_lds_limit((const void*)sparse_kernel<TIn, TAcc, 8>, lds)) return e;
-    sparse_kernel<TIn, TAcc, 8><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.zeta, p.seed, p.groups, part);
-  } else {
-    if (hipError_t e = set_lds_limit((const void*)sparse_kernel<TIn, TAcc, 32>, lds)) return e;
-    sparse_kernel<TIn, TAcc, 32><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.zeta, p.seed, p.groups, part);
-  }
-  return hipGetLastError();
-}
-
 size_t sparse_lds_bytes(int s, int zeta, int acc) {
   const int zmax = zeta <= 8 ? 8 : 32;
-  return (size_t)s * kSpCols * (acc == NSK_F64 ? 8 : 4) + (size_t)kSpThreads * zmax * 2 + 64 + kSpThreads * 4;
+  return (size_t)s * sparse_cols(s, zeta, acc) * (acc == NSK_F64 ? 8 : 4) + (size_t)2 * kSpThreads * zmax * 2 +
+         (size_t)2 * kSpThreads * 4;
+}
+
+template <typename TIn, typename TAcc>
+static hipError_t sparse_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
+  const int acc = sizeof(TAcc) == 8 ? NSK_F64 : NSK_F32;
+  const int cols = sparse_cols(p.s, p.zeta, acc);
+  dim3 grid((p.N + cols - 1) / cols, p.groups);
+  const int zmax = p.zeta <= 8 ? 8 : 32;
+  const size_t lds = sparse_lds_bytes(p.s, p.zeta, acc);
+  TAcc* part = static_cast<TAcc*>(p.partial);
+#define NSK_SPARSE(Z, C)                                                                               \
+  {                                                                                                    \
+    if (hipError_t e = set_lds_limit((const void*)sparse_kernel<TIn, TAcc, Z, C>, lds)) return e;      \
+    sparse_kernel<TIn, TAcc, Z, C><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.zeta, p.seed,   \
+                                                                   p.groups, part);                     \
+  }
+  if (zmax == 8) {
+    if (cols == 16) NSK_SPARSE(8, 16)
+    else if (cols == 8) NSK_SPARSE(8, 8)
+    else NSK_SPARSE(8, 4)
+  } else {
+    if (cols == 16) NSK_SPARSE(32, 16)
+    else if (cols == 8) NSK_SPARSE(32, 8)
+    else NSK_SPARSE(32, 4)
+  }
+#undef NSK_SPARSE
+  return hipGetLastError();
 }
 
 size_t gauss_lds_bytes(int s, int N, int dtype) {

@@ -75,9 +75,10 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
   const int c = ctile * kSrhtCols + col;
   const bool live = c < N;
 
+  // dead columns read column 0 and are masked after the load (no branch around the loads)
   const TIn* base = nullptr;
   int64_t ld = 0;
-  if (live) column_ref<TIn>(op, c, base, ld);
+  column_ref<TIn>(op, live ? c : 0, base, ld);
 
   __syncthreads();
   for (int i = t; i < s; i += kSrhtThreads) srow[i] = rows[i];
@@ -98,12 +99,16 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
     __syncthreads();
     // phase 1: rows rs + 32k, butterflies over row bits 5..9 (bits of k)
     TAcc x[32];
+    TIn raw[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int64_t row = r0 + rs + 32 * k;
+      raw[k] = base[(row < m ? row : r0) * ld];
+    }
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
       const int rl = rs + 32 * k;
-      const int64_t row = r0 + rl;
-      TAcc v = 0;
-      if (live && row < m) v = (TAcc)to_f64(base[row * ld]);
+      const TAcc v = live && r0 + rl < m ? (TAcc)to_f64(raw[k]) : (TAcc)0;
       const bool neg = (signbits[rl >> 5] >> (rl & 31)) & 1u;
       x[k] = neg ? -v : v;
     }

@@ -37,10 +37,11 @@ static SvdWork to_work(const SvdPlan& p) {
   return w;
 }
 
-// QR with 64 rows per lane and the replay with 8 log entries per lane need more than the
-// 128 VGPRs a 1024-thread workgroup leaves each wave; they run 512 threads.
-__host__ __device__ constexpr int qr_threads(int rpl) { return rpl >= 64 ? 512 : 1024; }
-__host__ __device__ constexpr int finish_threads(int epl) { return epl >= 8 ? 512 : 1024; }
+// The QR (CPW x RPL = 64 trailing-column doubles per lane) and the log replay (prefetch
+// registers plus a block pair per lane) need more than the 128 VGPRs a 1024-thread
+// workgroup leaves each wave; they run 512 threads.
+__host__ __device__ constexpr int qr_threads(int rpl) { return rpl >= 64 ? 256 : 512; }
+constexpr int kFinishThreads = 512;
 
 template <int RPL>
 __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_kernel(SvdWork w) {
@@ -54,10 +55,10 @@ __global__ __launch_bounds__(jacobi_threads(NR)) void svd_jacobi_kernel(SvdWork 
   svd_stage_jacobi_nr<NR, JacobiB<NR>::value>(w, smem);
 }
 
-template <int EPL>
-__global__ __launch_bounds__(finish_threads(EPL)) void svd_finish_kernel(SvdWork w) {
+template <int NR>
+__global__ __launch_bounds__(kFinishThreads) void svd_finish_kernel(SvdWork w) {
   extern __shared__ unsigned char smem[];
-  svd_stage_finish_epl<EPL>(w, smem);
+  svd_stage_finish_nr<NR>(w, smem);
 }
 
 __global__ __launch_bounds__(kSvdThreads) void svd_kernel(SvdPlan p) {
@@ -108,9 +109,9 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
       case 4: svd_jacobi_kernel<4><<<1, jacobi_threads(4), 0, st>>>(w); break;
       default: svd_jacobi_kernel<5><<<1, jacobi_threads(5), 0, st>>>(w); break;
     }
-    const int epl = finish_epl(p.N), tf = finish_threads(epl);
+    const int tf = kFinishThreads;
     const size_t lf = svd_fast_lds_bytes(p.s, p.N, tf / 64);
-    switch (epl) {
+    switch (jacobi_shape(p.N).NR) {
       case 1:
         e = lds_attr((const void*)svd_finish_kernel<1>, lf);
         if (e == hipSuccess) svd_finish_kernel<1><<<1, tf, lf, st>>>(w);
@@ -119,13 +120,17 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
         e = lds_attr((const void*)svd_finish_kernel<2>, lf);
         if (e == hipSuccess) svd_finish_kernel<2><<<1, tf, lf, st>>>(w);
         break;
+      case 3:
+        e = lds_attr((const void*)svd_finish_kernel<3>, lf);
+        if (e == hipSuccess) svd_finish_kernel<3><<<1, tf, lf, st>>>(w);
+        break;
       case 4:
         e = lds_attr((const void*)svd_finish_kernel<4>, lf);
         if (e == hipSuccess) svd_finish_kernel<4><<<1, tf, lf, st>>>(w);
         break;
       default:
-        e = lds_attr((const void*)svd_finish_kernel<8>, lf);
-        if (e == hipSuccess) svd_finish_kernel<8><<<1, tf, lf, st>>>(w);
+        e = lds_attr((const void*)svd_finish_kernel<5>, lf);
+        if (e == hipSuccess) svd_finish_kernel<5><<<1, tf, lf, st>>>(w);
         break;
     }
     if (e != hipSuccess) return e;

@@ -52,10 +52,19 @@ __host__ __device__ inline int qr_panel_width(int s, int nwaves) {
   return nb;
 }
 
-__host__ __device__ inline size_t svd_fast_lds_bytes(int s, int N, int nwaves) {
+// waves of the finish stage that replay vectors concurrently
+__host__ __device__ inline int finish_replay_waves(int nwaves) { return nwaves < 2 ? nwaves : 2; }
+
+__host__ __device__ inline size_t finish_head_bytes(int N) { return ((size_t)N * 12 + 255) & ~(size_t)255; }
+
+__host__ __device__ inline size_t finish_wave_bytes(int N) {
   const JacobiShape js = jacobi_shape(N);
+  return (((size_t)js.nb * js.B * 8 + 255) & ~(size_t)255) + replay_stage_bytes();
+}
+
+__host__ __device__ inline size_t svd_fast_lds_bytes(int s, int N, int nwaves) {
   const size_t qr = qr_panel_lds_bytes(s, qr_panel_width(s, nwaves));
-  const size_t fin = (size_t)N * 12 + (size_t)nwaves * js.nb * js.B * 8 + 256;
+  const size_t fin = finish_head_bytes(N) + (size_t)finish_replay_waves(nwaves) * finish_wave_bytes(N);
   return qr > fin ? qr : fin;
 }
 
@@ -63,19 +72,26 @@ __host__ __device__ inline size_t svd_fast_lds_bytes(int s, int N, int nwaves) {
 // rows per lane of a panel column: s <= 64 RPL
 __host__ __device__ inline int qr_rpl(int s) { return s <= 1024 ? 16 : s <= 2048 ? 32 : 64; }
 
+// trailing-update columns per wave: CPW x RPL doubles stay in registers
+template <int RPL>
+struct QrCpw {
+  static constexpr int value = RPL <= 16 ? 4 : RPL <= 32 ? 2 : 1;
+};
+
 template <int RPL>
 __device__ inline void svd_stage_qr_rpl(const SvdWork& w, unsigned char* smem) {
+  constexpr int C = QrCpw<RPL>::value;
   const JacobiShape js = jacobi_shape(w.N);
   const int ldr = 64 * js.NR;
   const size_t total = (size_t)ldr * js.nb * js.B;
   for (size_t e = threadIdx.x; e < total; e += blockDim.x) w.R[e] = 0.0;
   __syncthreads();
   switch (qr_panel_width(w.s, blockDim.x >> 6)) {
-    case 16: qr_panel<RPL, 16>(w.sa, w.s, w.N, w.R, ldr, smem); break;
-    case 8: qr_panel<RPL, 8>(w.sa, w.s, w.N, w.R, ldr, smem); break;
-    case 4: qr_panel<RPL, 4>(w.sa, w.s, w.N, w.R, ldr, smem); break;
-    case 2: qr_panel<RPL, 2>(w.sa, w.s, w.N, w.R, ldr, smem); break;
-    default: qr_panel<RPL, 1>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    case 16: qr_panel<RPL, 16, C>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    case 8: qr_panel<RPL, 8, C>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    case 4: qr_panel<RPL, 4, C>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    case 2: qr_panel<RPL, 2, C>(w.sa, w.s, w.N, w.R, ldr, smem); break;
+    default: qr_panel<RPL, 1, C>(w.sa, w.s, w.N, w.R, ldr, smem); break;
   }
   __syncthreads();
 }
@@ -121,24 +137,20 @@ __device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
 }
 
 // ---------------------------------------------------------------- stage 3: finish
-// log entries per lane of the widest replay step
-__host__ __device__ inline int finish_epl(int N) {
-  const int e = replay_epl(jacobi_shape(N));
-  return e <= 1 ? 1 : e <= 2 ? 2 : e <= 4 ? 4 : 8;
+// x <- V x (fwd = false) or V^T x (fwd = true) for one wave, any block size
+__device__ inline void replay_any(double* x, const double2* log, const JacobiShape& js, int sweeps, bool fwd,
+                                  int lane, double2* stage) {
+  switch (js.NR) {
+    case 1: jacobi_replay<jacobi_block_size(1)>(x, log, js, sweeps, fwd, lane, stage); break;
+    case 2: jacobi_replay<jacobi_block_size(2)>(x, log, js, sweeps, fwd, lane, stage); break;
+    case 3: jacobi_replay<jacobi_block_size(3)>(x, log, js, sweeps, fwd, lane, stage); break;
+    case 4: jacobi_replay<jacobi_block_size(4)>(x, log, js, sweeps, fwd, lane, stage); break;
+    default: jacobi_replay<jacobi_block_size(5)>(x, log, js, sweeps, fwd, lane, stage); break;
+  }
 }
 
-// x <- V x (transpose = false) or V^T x for one wave; any workgroup size up to 512 threads
-__device__ inline void replay_dispatch(double* x, const double2* log, const JacobiShape& js, int sweeps,
-                                       bool transpose, int lane) {
-  const int epl = replay_epl(js);
-  if (epl <= 1) jacobi_replay<1>(x, log, js, sweeps, transpose, lane);
-  else if (epl <= 2) jacobi_replay<2>(x, log, js, sweeps, transpose, lane);
-  else if (epl <= 4) jacobi_replay<4>(x, log, js, sweeps, transpose, lane);
-  else jacobi_replay<8>(x, log, js, sweeps, transpose, lane);
-}
-
-template <int EPL>
-__device__ inline void svd_stage_finish_epl(const SvdWork& w, unsigned char* smem) {
+template <int NR>
+__device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem) {
   const JacobiShape js = jacobi_shape(w.N);
   const int N = w.N, k = w.k;
   const int ldr = 64 * js.NR;
@@ -146,7 +158,10 @@ __device__ inline void svd_stage_finish_epl(const SvdWork& w, unsigned char* sme
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   double* nrm = reinterpret_cast<double*>(smem);
   int* rk = reinterpret_cast<int*>(nrm + N);
-  double* xs = reinterpret_cast<double*>(smem + (((size_t)N * 12 + 255) & ~(size_t)255));
+  const int nrep = finish_replay_waves(nw);
+  unsigned char* mine = smem + finish_head_bytes(N) + (size_t)(wave < nrep ? wave : 0) * finish_wave_bytes(N);
+  double* x = reinterpret_cast<double*>(mine);
+  double2* stage = reinterpret_cast<double2*>(mine + finish_wave_bytes(N) - replay_stage_bytes());
   // singular values: column norms of the rotated R
   for (int c = wave; c < N; c += nw) {
     double a = 0;
@@ -161,12 +176,12 @@ __device__ inline void svd_stage_finish_epl(const SvdWork& w, unsigned char* sme
   // rank by (norm descending, index ascending); NaN ranks last so ranks are a permutation
   for (int c = tid; c < N; c += blockDim.x) {
     const double xv = nrm[c];
-    const double x = xv != xv ? -1.0 : xv;
+    const double kx = xv != xv ? -1.0 : xv;
     int r = 0;
     for (int d = 0; d < N; ++d) {
       const double yv = nrm[d];
-      const double y = yv != yv ? -1.0 : yv;
-      r += (y > x) || (y == x && d < c);
+      const double ky = yv != yv ? -1.0 : yv;
+      r += (ky > kx) || (ky == kx && d < c);
     }
     rk[c] = r;
     w.order[r] = c;
@@ -175,25 +190,32 @@ __device__ inline void svd_stage_finish_epl(const SvdWork& w, unsigned char* sme
   __syncthreads();
   const int sweeps = w.jres->sweeps;
   // trailing vectors: wave q rebuilds V e_{order[N-k+q]} from the log
-  for (int q0 = 0; q0 < k; q0 += nw) {
+  for (int q0 = 0; q0 < k; q0 += nrep) {
     const int q = q0 + wave;
-    double* x = xs + (size_t)wave * ncols;
-    if (q < k) {
+    if (wave < nrep && q < k) {
       const int c = w.order[N - k + q];
       for (int e = lane; e < ncols; e += 64) x[e] = e == c ? 1.0 : 0.0;
-      jacobi_replay<EPL>(x, w.log, js, sweeps, false, lane);
+      __builtin_amdgcn_wave_barrier();
+      jacobi_replay<jacobi_block_size(NR)>(x, w.log, js, sweeps, false, lane, stage);
+      __builtin_amdgcn_wave_barrier();
       // sign: largest-magnitude entry positive, lowest index on ties
       double best = -1;
       int bi = 0;
       for (int e = lane; e < N; e += 64) {
         const double a = fabs(x[e]);
-        if (a > best) { best = a; bi = e; }
+        if (a > best) {
+          best = a;
+          bi = e;
+        }
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         const double ob = __shfl_xor(best, o, 64);
         const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
       }
       const double sgn = x[bi] < 0 ? -1.0 : 1.0;
       if (w.Vk)
@@ -212,11 +234,12 @@ __device__ inline void svd_stage_finish_epl(const SvdWork& w, unsigned char* sme
 }
 
 __device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
-  switch (finish_epl(w.N)) {
-    case 1: svd_stage_finish_epl<1>(w, smem); break;
-    case 2: svd_stage_finish_epl<2>(w, smem); break;
-    case 4: svd_stage_finish_epl<4>(w, smem); break;
-    default: svd_stage_finish_epl<8>(w, smem); break;
+  switch (jacobi_shape(w.N).NR) {
+    case 1: svd_stage_finish_nr<1>(w, smem); break;
+    case 2: svd_stage_finish_nr<2>(w, smem); break;
+    case 3: svd_stage_finish_nr<3>(w, smem); break;
+    case 4: svd_stage_finish_nr<4>(w, smem); break;
+    default: svd_stage_finish_nr<5>(w, smem); break;
   }
 }
 

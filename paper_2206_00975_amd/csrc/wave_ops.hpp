@@ -128,6 +128,15 @@ __device__ inline T* opaque_uniform(T* p) {
   return p;
 }
 
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads() it does not wait
+// for global loads in flight, so prefetches can cross it.  Only for barriers whose producers
+// and consumers communicate through LDS.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sum over all 64 lanes, result in every lane.
 __device__ inline double wave_sum64(double v) {
   v = sum_xor32(v);
