@@ -73,6 +73,12 @@ __host__ __device__ inline size_t jacobi_log_entries_per_sweep(const JacobiShape
 }
 
 // ---------------------------------------------------------------- wave primitives
+struct JacobiResult {
+  int sweeps;
+  int converged;
+  double off;
+};
+
 struct JacobiCtx {
   double tol;
   int rotations;   // per-lane count

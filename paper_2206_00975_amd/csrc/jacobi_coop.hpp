@@ -1,0 +1,257 @@
+// Block one-sided Jacobi spread over workgroups (cooperative launch).
+//
+// Same sweep, schedule, rotation formulas and log as the single-workgroup version: an intra
+// phase in which every block rotates its own column pairs in circle order, then nb - 1 block
+// rounds in which the nb / 2 disjoint block pairs of the round meet.  Here workgroup g owns
+// block pair g of every round (and blocks g, g + nb/2 of the intra phase), so the pairs of a
+// round run on different CUs; a grid barrier separates the phases.  Inside a workgroup the NW
+// waves split the rows: wave w holds rows 64 w .. 64 w + 63 of the two blocks, one row per
+// lane.  Column dot products are reduced per wave with one transposed reduction and summed
+// over the waves through LDS in wave order, so every wave derives the same rotation
+// parameters.  The first wave writes the log and counts the rotations.
+#pragma once
+
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "jacobi_block.hpp"
+#include "wave_ops.hpp"
+
+namespace nsk {
+
+// Per-sweep rotation counts and largest relative cosines, appended to the rotation log.
+__host__ __device__ inline size_t jacobi_coop_counter_bytes(int max_sweeps) {
+  return (size_t)max_sweeps * 2 * sizeof(unsigned long long);
+}
+
+// Wave totals of the first P values of v, summed over the NW waves.  Lane l receives the
+// total of value l >> (6 - ceil_log2(P)) (zero past P).  part: LDS [2][NW][16], used in turn.
+template <int P, int NW>
+__device__ inline double coop_reduce(double (&v)[16], int lane, int wave, double (*part)[NW][16], int& buf) {
+  constexpr int SH = 6 - ceil_log2(P);
+  const double t = reduce_t<P>(v, lane);
+  const int pi = lane >> SH;
+  if ((lane & ((1 << SH) - 1)) == 0 && pi < P) part[buf][wave][pi] = t;
+  lds_barrier();
+  double s = 0;
+  if (pi < P)
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += part[buf][w][pi];
+  buf ^= 1;
+  return s;
+}
+
+struct CoopCount {
+  int rotations;   // counted by the first wave's leading lanes only
+  double offmax;
+};
+
+template <int NW, int B>
+__device__ inline void coop_intra_block(double* __restrict__ R, int ld, int blk, double2* lg, int stride,
+                                        double tol, CoopCount& cc, double (*part)[NW][16], int& buf, int lane,
+                                        int wave) {
+  constexpr int BQ = B + (B & 1);
+  constexpr int H = BQ / 2;
+  constexpr int SH = 6 - ceil_log2(H);
+  const int pi = lane >> SH;
+  const bool lead = wave == 0 && (lane & ((1 << SH) - 1)) == 0 && pi < H;
+  double* p = uniform_ptr(R + (size_t)blk * B * ld) + 64 * wave + lane;
+  double X[BQ];
+#pragma unroll
+  for (int b = 0; b < BQ; ++b) X[b] = b < B ? p[(size_t)b * ld] : 0.0;
+  for (int q = 0; q < BQ - 1; ++q) {
+    double sab[3];
+#pragma unroll
+    for (int which = 0; which < 3; ++which) {
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        const double a = X[i], b = X[BQ - 1 - i];
+        v[i] = which == 0 ? a * a : which == 1 ? b * b : a * b;
+      }
+      sab[which] = coop_reduce<H, NW>(v, lane, wave, part, buf);
+    }
+    double c, s, t;
+    bool act;
+    jacobi_params(sab[0], sab[1], sab[2], tol, c, s, t, act);
+    if (lead) {
+      const double nab = sqrt(sab[0] * sab[1]);
+      if (nab > 0) cc.offmax = fmax(cc.offmax, fabs(sab[2]) / nab);
+      if (act) cc.rotations++;
+      lg[pi] = make_double2(c, s);
+    }
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double ci = bcast_d(c, i << SH), si = bcast_d(s, i << SH);
+      const double a = X[i], b = X[BQ - 1 - i];
+      X[i] = ci * a - si * b;
+      X[BQ - 1 - i] = si * a + ci * b;
+    }
+    const double first = X[1];
+#pragma unroll
+    for (int b = 1; b < BQ - 1; ++b) X[b] = X[b + 1];
+    X[BQ - 1] = first;
+    lg += stride;
+  }
+#pragma unroll
+  for (int b = 0; b < B; ++b) p[(size_t)b * ld] = X[b];
+}
+
+template <int NW, int B>
+__device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, int J, double2* lg, int stride,
+                                       double tol, CoopCount& cc, double (*part)[NW][16], int& buf, int lane,
+                                       int wave) {
+  constexpr int SH = 6 - ceil_log2(B);
+  const int pi = lane >> SH;
+  const bool valid = pi < B;
+  const bool lead = wave == 0 && (lane & ((1 << SH) - 1)) == 0 && valid;
+  double* pt = uniform_ptr(R + (size_t)I * B * ld) + 64 * wave + lane;
+  double* pu = uniform_ptr(R + (size_t)J * B * ld) + 64 * wave + lane;
+  double T[B], U[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    T[b] = pt[(size_t)b * ld];
+    U[b] = pu[(size_t)b * ld];
+  }
+  double alpha, beta;
+  {
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < B; ++i) v[i] = T[i] * T[i];
+    alpha = coop_reduce<B, NW>(v, lane, wave, part, buf);
+  }
+  {
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < B; ++i) v[i] = U[i] * U[i];
+    beta = coop_reduce<B, NW>(v, lane, wave, part, buf);
+  }
+  const int nxt_pair = pi + 1 == B ? 0 : (valid ? pi + 1 : pi);
+  const int nxt_lane = (nxt_pair << SH) | (lane & ((1 << SH) - 1));
+  for (int j = 0; j < B; ++j) {
+    // slot i of U holds block column (i + j) mod B
+    double z[16];
+#pragma unroll
+    for (int i = 0; i < B; ++i) z[i] = T[i] * U[i];
+    const double g = coop_reduce<B, NW>(z, lane, wave, part, buf);
+    double c, s, t;
+    bool act;
+    jacobi_params(alpha, beta, g, tol, c, s, t, act);
+    if (!valid) {
+      c = 1.0;
+      s = 0.0;
+      t = 0.0;
+      act = false;
+    }
+    if (lead) {
+      const double nab = sqrt(alpha * beta);
+      if (nab > 0) cc.offmax = fmax(cc.offmax, fabs(g) / nab);
+      if (act) cc.rotations++;
+      lg[pi] = make_double2(c, s);
+    }
+    if (act) {
+      alpha = fmax(alpha - t * g, 0.0);
+      beta = fmax(beta + t * g, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const double ci = bcast_d(c, i << SH), si = bcast_d(s, i << SH);
+      const double a = T[i], b = U[i];
+      T[i] = ci * a - si * b;
+      U[i] = si * a + ci * b;
+    }
+    const double first = U[0];
+#pragma unroll
+    for (int b = 0; b < B - 1; ++b) U[b] = U[b + 1];
+    U[B - 1] = first;
+    beta = __shfl(beta, nxt_lane, 64);
+    lg += stride;
+  }
+  pt = opaque_uniform(pt - lane) + lane;
+  pu = opaque_uniform(pu - lane) + lane;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    pt[(size_t)b * ld] = T[b];
+    pu[(size_t)b * ld] = U[b];
+  }
+}
+
+// Sweeps until one performs no rotation (or max_sweeps).  Launched cooperatively with
+// nb / 2 workgroups of NW * 64 threads, NW = rows / 64.  counters: 2 * max_sweeps words.
+template <int NW, int B>
+__device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max_sweeps, double2* __restrict__ log,
+                                          unsigned long long* __restrict__ counters, JacobiResult* jres) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  __shared__ double part[2][NW][16];
+  __shared__ int sh_rot;
+  __shared__ double sh_off;
+  const JacobiShape js = jacobi_shape(N);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ld = 64 * NW;
+  const int nbp = js.nb / 2;
+  const size_t per_sweep = jacobi_log_entries_per_sweep(js);
+  const double tol = (double)N * 0x1p-53;
+  unsigned long long* rot_count = counters;
+  unsigned long long* off_bits = counters + max_sweeps;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < 2 * max_sweeps; i += blockDim.x) counters[i] = 0;
+  int buf = 0;
+  int sweeps = 0, conv = 0;
+  if (threadIdx.x == 0) sh_off = 0.0;
+  grid.sync();
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    CoopCount cc{0, 0.0};
+    double2* sweep_log = log + (size_t)sw * per_sweep;
+    for (int b = blockIdx.x; b < js.nb; b += gridDim.x)
+      coop_intra_block<NW, B>(R, ld, b, sweep_log + (size_t)b * 16, js.nb * 16, tol, cc, part, buf, lane, wave);
+    grid.sync();
+    for (int r = 0; r < js.nb - 1; ++r) {
+      double2* round_log = sweep_log + jacobi_log_step_offset(js, js.bq - 1 + r * B);
+      for (int i = blockIdx.x; i < nbp; i += gridDim.x) {
+        int I = circle_pos(i, r, js.nb), J = circle_pos(js.nb - 1 - i, r, js.nb);
+        if (I > J) {
+          const int t = I;
+          I = J;
+          J = t;
+        }
+        coop_inter_pair<NW, B>(R, ld, I, J, round_log + (size_t)i * 16, nbp * 16, tol, cc, part, buf, lane, wave);
+      }
+      if (r == js.nb - 2 && wave == 0) {
+        // this workgroup's counts of the sweep, published before the round's grid barrier
+        int rot = cc.rotations;
+        double om = cc.offmax;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          rot += __shfl_xor(rot, o, 64);
+          om = fmax(om, __shfl_xor(om, o, 64));
+        }
+        if (lane == 0) {
+          atomicAdd(&rot_count[sw], (unsigned long long)rot);
+          atomicMax(&off_bits[sw], (unsigned long long)__double_as_longlong(om));
+        }
+      }
+      grid.sync();
+    }
+    if (threadIdx.x == 0) {
+      sh_rot = (int)__hip_atomic_load(&rot_count[sw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sh_off = __longlong_as_double(
+          (long long)__hip_atomic_load(&off_bits[sw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    __syncthreads();
+    const int total = sh_rot;
+    sweeps = sw + 1;
+    __syncthreads();
+    if (total == 0) {
+      conv = 1;
+      break;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    jres->sweeps = sweeps;
+    jres->converged = conv;
+    jres->off = sweeps > 0 ? sh_off : 0.0;
+  }
+}
+
+}  // namespace nsk

@@ -55,6 +55,21 @@ __global__ __launch_bounds__(jacobi_threads(NR)) void svd_jacobi_kernel(SvdWork 
   svd_stage_jacobi_nr<NR, JacobiB<NR>::value>(w, smem);
 }
 
+// Multi-workgroup Jacobi: nb / 2 workgroups of NR waves (one row per lane).
+template <int NR>
+__global__ __launch_bounds__(NR * 64) void svd_jacobi_coop_kernel(SvdWork w) {
+  jacobi_coop_sweeps<NR, JacobiB<NR>::value>(w.R, w.N, w.max_sweeps, w.log,
+                                             jacobi_counters(w.log, w.N, w.max_sweeps), w.jres);
+}
+
+template <int NR>
+static hipError_t launch_jacobi_coop(SvdWork& w, hipStream_t st) {
+  void* args[] = {&w};
+  const int groups = jacobi_shape(w.N).nb / 2;
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_jacobi_coop_kernel<NR>), dim3(groups),
+                                    dim3(NR * 64), args, 0, st);
+}
+
 template <int NR>
 __global__ __launch_bounds__(kFinishThreads) void svd_finish_kernel(SvdWork w) {
   extern __shared__ unsigned char smem[];
@@ -83,7 +98,7 @@ size_t svd_work_log_bytes(int s, int N, int max_sweeps) {
 
 hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
   if (svd_fast_path(p.s, p.N)) {
-    const SvdWork w = to_work(p);
+    SvdWork w = to_work(p);
     hipError_t e = hipSuccess;
     const int rpl = qr_rpl(p.s), tq = qr_threads(rpl);
     const size_t lq = svd_fast_lds_bytes(p.s, p.N, tq / 64);
@@ -102,13 +117,15 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
         break;
     }
     if (e != hipSuccess) return e;
+    // the block pairs of a round run on separate CUs once there are rows enough (N > 64)
     switch (jacobi_shape(p.N).NR) {
       case 1: svd_jacobi_kernel<1><<<1, jacobi_threads(1), 0, st>>>(w); break;
-      case 2: svd_jacobi_kernel<2><<<1, jacobi_threads(2), 0, st>>>(w); break;
-      case 3: svd_jacobi_kernel<3><<<1, jacobi_threads(3), 0, st>>>(w); break;
-      case 4: svd_jacobi_kernel<4><<<1, jacobi_threads(4), 0, st>>>(w); break;
-      default: svd_jacobi_kernel<5><<<1, jacobi_threads(5), 0, st>>>(w); break;
+      case 2: e = launch_jacobi_coop<2>(w, st); break;
+      case 3: e = launch_jacobi_coop<3>(w, st); break;
+      case 4: e = launch_jacobi_coop<4>(w, st); break;
+      default: e = launch_jacobi_coop<5>(w, st); break;
     }
+    if (e != hipSuccess) return e;
     const int tf = kFinishThreads;
     const size_t lf = svd_fast_lds_bytes(p.s, p.N, tf / 64);
     switch (jacobi_shape(p.N).NR) {

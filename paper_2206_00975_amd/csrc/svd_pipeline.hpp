@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "jacobi_block.hpp"
+#include "jacobi_coop.hpp"
 #include "nsk_internal.hpp"
 #include "qr_panel.hpp"
 
@@ -15,12 +16,6 @@ namespace nsk {
 
 constexpr int kFastMaxN = 320;
 constexpr int kFastMaxS = 4096;
-
-struct JacobiResult {
-  int sweeps;
-  int converged;
-  double off;
-};
 
 struct SvdWork {
   double* sa;          // s x N column-major, overwritten by the QR
@@ -36,9 +31,16 @@ struct SvdWork {
   int s, N, k, max_sweeps;
 };
 
+// rotation log, followed by the per-sweep counters of the multi-workgroup Jacobi
 __host__ __device__ inline size_t svd_fast_log_bytes(int N, int max_sweeps) {
   const JacobiShape js = jacobi_shape(N);
-  return (size_t)max_sweeps * jacobi_log_entries_per_sweep(js) * sizeof(double2);
+  return (size_t)max_sweeps * jacobi_log_entries_per_sweep(js) * sizeof(double2) +
+         jacobi_coop_counter_bytes(max_sweeps);
+}
+
+__host__ __device__ inline unsigned long long* jacobi_counters(double2* log, int N, int max_sweeps) {
+  const JacobiShape js = jacobi_shape(N);
+  return reinterpret_cast<unsigned long long*>(log + (size_t)max_sweeps * jacobi_log_entries_per_sweep(js));
 }
 
 __host__ __device__ inline size_t svd_fast_R_bytes(int N) {
