@@ -217,11 +217,12 @@ int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state,
  * NSK_PROF_STAGES+1 HIP events for each of up to max_calls subsequent calls of
  * nsk_trailing_rsv / nsk_tls_solve / nsk_sketch and records them on the call's stream at
  * the stage boundaries (0 host draws and uploads, 1 sketch kernel, 2 partial reduce,
- * 3 QR + Jacobi, 4 post-processing: residual or TLS extraction).  nsk_profile_read waits
+ * 3 Householder QR of SA, 4 one-sided Jacobi, 5 ranking and vector rebuild from the
+ * rotation log, 6 post-processing: residual or TLS extraction).  nsk_profile_read waits
  * for the recorded events and returns the summed milliseconds per stage and the number of
  * profiled calls; nsk_profile_enable(0) stops recording and frees the events.
  */
-#define NSK_PROF_STAGES 5
+#define NSK_PROF_STAGES 7
 int nsk_profile_enable(int32_t max_calls);
 int nsk_profile_read(double* ms /* NSK_PROF_STAGES */, int32_t* calls);
 

@@ -354,7 +354,7 @@ class TLSSketch(torch.autograd.Function):
 
 
 # ------------------------------------------------------------------------ profiler
-PROF_STAGES = ("draws", "sketch", "reduce", "svd", "post")
+PROF_STAGES = ("draws", "sketch", "reduce", "qr", "jacobi", "finish", "post")
 
 
 def profile_enable(max_calls):

@@ -211,10 +211,14 @@ void prof_begin(hipStream_t st) {
   (void)hipEventRecord(g_prof.ev[(size_t)g_prof.cur * (NSK_PROF_STAGES + 1)], st);
 }
 
-void prof_mark(int stage, hipStream_t st) {  // end of stage `stage`
+}  // namespace
+
+void nsk::prof_mark(int stage, hipStream_t st) {  // end of stage `stage`
   if (g_prof.cur < 0) return;
   (void)hipEventRecord(g_prof.ev[(size_t)g_prof.cur * (NSK_PROF_STAGES + 1) + stage + 1], st);
 }
+
+namespace {
 
 // Sketch + reduce; SA written column-major into the workspace and optionally row-major out.
 int run_sketch(const Operand& op, const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws, const Layout& L,
@@ -269,8 +273,7 @@ int nsk_sketch(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_
   if (ws_bytes < L.total) return NSK_EWORKSPACE;
   SketchPlan p;
   rc = run_sketch(op, d, m, N, static_cast<unsigned char*>(ws), L, SA, ldsa, (hipStream_t)stream, p);
-  prof_mark(3, (hipStream_t)stream);
-  prof_mark(4, (hipStream_t)stream);
+  for (int stage = 3; stage < NSK_PROF_STAGES; ++stage) prof_mark(stage, (hipStream_t)stream);
   return rc;
 }
 
@@ -294,13 +297,12 @@ int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int6
   sp.sigma_k = sigma_k;
   sp.info = info;
   if ((rc = dev(launch_svd(sp, st)))) return rc;
-  prof_mark(3, st);
   if ((d->flags & NSK_FLAG_RESIDUAL) && info) {
     if (N * k > kMaxResidualVec) return NSK_EUNSUPPORTED;
     const int64_t parts = std::min<int64_t>(kResParts, std::max<int64_t>(1, m / 256));
     rc = dev(launch_residual(op, m, Vk, (int)k, reinterpret_cast<double*>(w + L.res), (int)parts, nullptr, info, st));
   }
-  prof_mark(4, st);
+  prof_mark(6, st);
   return rc;
 }
 
@@ -375,7 +377,6 @@ int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const n
   sp.sigma_k = nullptr;
   sp.info = info;
   if ((rc = dev(launch_svd(sp, st)))) return rc;
-  prof_mark(3, st);
   double* xs = reinterpret_cast<double*>(S + o[5]);
   if ((rc = dev(launch_tls_extract((int)N, sp.Vk, xs, st)))) return rc;
   if ((rc = dev(hipMemcpyAsync(x, xs, (size_t)n * 8, hipMemcpyDeviceToDevice, st)))) return rc;
@@ -383,7 +384,7 @@ int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const n
     const int64_t parts = std::min<int64_t>(kResParts, std::max<int64_t>(1, m / 256));
     rc = dev(launch_residual(op, m, sp.Vk, 1, reinterpret_cast<double*>(w + L.res), (int)parts, nullptr, info, st));
   }
-  prof_mark(4, st);
+  prof_mark(6, st);
   return rc;
 }
 

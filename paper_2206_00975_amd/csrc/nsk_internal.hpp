@@ -171,6 +171,9 @@ struct SvdPlan {
 bool svd_fast_path(int s, int N);
 size_t svd_work_R_bytes(int s, int N);
 size_t svd_work_log_bytes(int s, int N, int max_sweeps);
+// Records the end of profiler stage `stage` on st when the stage profiler is on (api.cpp);
+// launch_svd marks stages 3 (QR), 4 (Jacobi) and 5 (finish).
+void prof_mark(int stage, hipStream_t st);
 hipError_t launch_svd(const SvdPlan& p, hipStream_t st);
 
 hipError_t launch_residual(const Operand& op, int64_t m, const double* Vk, int k, double* partial,

@@ -117,6 +117,7 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
         break;
     }
     if (e != hipSuccess) return e;
+    prof_mark(3, st);
     // the block pairs of a round run on separate CUs once there are rows enough (N > 64)
     switch (jacobi_shape(p.N).NR) {
       case 1: svd_jacobi_kernel<1><<<1, jacobi_threads(1), 0, st>>>(w); break;
@@ -126,6 +127,7 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
       default: e = launch_jacobi_coop<5>(w, st); break;
     }
     if (e != hipSuccess) return e;
+    prof_mark(4, st);
     const int tf = kFinishThreads;
     const size_t lf = svd_fast_lds_bytes(p.s, p.N, tf / 64);
     switch (jacobi_shape(p.N).NR) {
@@ -151,11 +153,13 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
         break;
     }
     if (e != hipSuccess) return e;
+    prof_mark(5, st);
     return hipGetLastError();
   }
   const size_t lds = svd_lds_bytes(p.s, p.N);
   if (hipError_t e = lds_attr((const void*)svd_kernel, lds)) return e;
   svd_kernel<<<1, kSvdThreads, lds, st>>>(p);
+  for (int stage = 3; stage <= 5; ++stage) prof_mark(stage, st);
   return hipGetLastError();
 }
 
