@@ -341,24 +341,31 @@ __device__ inline int jacobi_block_sweeps(double* __restrict__ R, const JacobiSh
 }
 
 // ------------------------------------------------------------------ log replay
-// One wave applies the logged rotations to a vector x (LDS, nb * B doubles, zero beyond N).
-// x <- V x (fwd = false) takes the steps from last to first with [x_p, x_q] <- [c x_p + s x_q,
-// -s x_p + c x_q]; x <- V^T x (fwd = true) takes them from first to last with [x_p, x_q] <-
-// [c x_p - s x_q, s x_p + c x_q].  Lanes follow the Jacobi kernel's register schedule: in an
-// intra phase lane g holds block g, in block round r lane g holds the blocks of pair g, and
-// positions move between registers exactly as the columns did, so every slot of a step is a
-// compile-time register pair.  Rotations on padding columns were logged as (1, 0).
+// x <- V x (fwd = false) takes the logged steps from last to first with [x_p, x_q] <-
+// [c x_p + s x_q, -s x_p + c x_q]; x <- V^T x (fwd = true) takes them from first to last with
+// [x_p, x_q] <- [c x_p - s x_q, s x_p + c x_q].  Rotations on padding columns were logged as
+// (1, 0).
 //
-// The log streams through LDS (stage, replay_stage_bytes()) in chunks of whole steps of at
-// most kReplayE entries; the next chunk is loaded into registers while the current one is
-// applied.  Entry k of a chunk sits at k + k / 16 so that the lanes of a step, which read
-// entries 16 apart, fall in different banks.
-constexpr int kReplayCH = 24;
-constexpr int kReplayE = kReplayCH * 64;
+// One lane per logged rotation: in a block round, lane 16 g + i holds T_i and the U slot i of
+// block pair g; in an intra phase, lane 8 g + i holds positions i and BQ-1-i of block g.
+// Between steps the slots move exactly as the Jacobi kernel's registers did, here with lane
+// shuffles inside the 16- or 8-lane group.  A vector group of replay_waves(js) waves replays
+// one vector (x in LDS, nb * B doubles); several groups replay different vectors at once.
+//
+// The log streams through LDS (replay_stage_bytes()) in chunks of whole steps, shared by all
+// groups of the workgroup: every thread loads part of the next chunk into registers while the
+// current chunk is applied.  Entry k of a chunk sits at k + k / 16, so that the 16-entry
+// groups of one step fall in different LDS banks.
+constexpr int kReplayPer = 8;       // entries per thread per chunk
+constexpr int kReplayMaxThreads = 512;
 
+// LDS of the staged chunk for a workgroup of at most kReplayMaxThreads threads
 __host__ __device__ constexpr size_t replay_stage_bytes() {
-  return (size_t)(kReplayE + kReplayE / 16) * sizeof(double2);
+  return (size_t)(kReplayPer * kReplayMaxThreads * 17 / 16) * sizeof(double2);
 }
+
+// waves per vector group: max(8 nb, 16 nb / 2) lanes
+__host__ __device__ inline int replay_waves(const JacobiShape& js) { return (js.nb * 8 + 63) / 64; }
 
 __device__ inline int step_groups(const JacobiShape& js, int st) { return st < js.bq - 1 ? js.nb : js.nb / 2; }
 
@@ -382,6 +389,8 @@ __device__ inline void step_advance(const JacobiShape& js, StepPos& p, bool fwd)
   }
 }
 
+// Workgroup-wide log stream (every thread of the workgroup calls every member function);
+// chunks hold at most kReplayPer * blockDim.x entries.
 struct LogStream {
   const double2* log;
   double2* stage;
@@ -390,41 +399,37 @@ struct LogStream {
   long long steps;      // total steps to replay
   bool fwd;
   StepPos plan;         // position of step next_t (processing order)
-  long long next_t;     // first step of the prefetched chunk's successor
-  size_t pre_base;      // first log entry of the prefetched chunk
-  size_t pre_end;
+  long long next_t;
+  size_t pre_base;
   long long pre_t1;     // steps [.., pre_t1) are in the prefetched chunk
   long long cur_t1;     // steps [.., cur_t1) are staged in LDS
   size_t cur_base;
-  double2 pre[kReplayCH];
+  double2 pre[kReplayPer];
 
-  // plan the chunk starting at step next_t and load it into pre[]
-  __device__ void prefetch(int lane) {
+  __device__ void prefetch() {
     size_t lo = ~(size_t)0, hi = 0;
     long long t = next_t;
     while (t < steps) {
       const size_t b = step_begin(*js, per_sweep, plan);
       const size_t e = b + (size_t)step_groups(*js, plan.st) * 16;
       const size_t nlo = b < lo ? b : lo, nhi = e > hi ? e : hi;
-      if (nhi - nlo > (size_t)kReplayE) break;
+      if (nhi - nlo > (size_t)kReplayPer * blockDim.x) break;
       lo = nlo;
       hi = nhi;
       ++t;
       step_advance(*js, plan, fwd);
     }
     pre_base = lo;
-    pre_end = hi;
     pre_t1 = t;
     next_t = t;
 #pragma unroll
-    for (int u = 0; u < kReplayCH; ++u) {
-      const size_t e = lo + lane + 64 * u;
+    for (int u = 0; u < kReplayPer; ++u) {
+      const size_t e = lo + threadIdx.x + (size_t)blockDim.x * u;
       pre[u] = e < hi ? log[e] : make_double2(1.0, 0.0);
     }
   }
 
-  __device__ void init(const double2* lg, double2* stg, const JacobiShape* shape, int sweeps, bool forward,
-                       int lane) {
+  __device__ void init(const double2* lg, double2* stg, const JacobiShape* shape, int sweeps, bool forward) {
     log = lg;
     stage = stg;
     js = shape;
@@ -435,21 +440,22 @@ struct LogStream {
     next_t = 0;
     cur_t1 = 0;
     cur_base = 0;
-    if (steps > 0) prefetch(lane);
+    if (steps > 0) prefetch();
   }
 
-  // make step t (processing order) readable from LDS
-  __device__ void ensure(long long t, int lane) {
+  // make step t (processing order) readable from LDS; uniform over the workgroup
+  __device__ void ensure(long long t) {
     if (t < cur_t1) return;
+    lds_barrier();  // every group is done with the previous chunk
 #pragma unroll
-    for (int u = 0; u < kReplayCH; ++u) {
-      const int k = lane + 64 * u;
+    for (int u = 0; u < kReplayPer; ++u) {
+      const int k = threadIdx.x + blockDim.x * u;
       stage[k + (k >> 4)] = pre[u];
     }
-    __builtin_amdgcn_wave_barrier();
+    lds_barrier();
     cur_t1 = pre_t1;
     cur_base = pre_base;
-    if (next_t < steps) prefetch(lane);
+    if (next_t < steps) prefetch();
   }
 
   // (c, s) of slot i of group g at step position p (staged)
@@ -466,95 +472,96 @@ __device__ inline void rot_pair(double& x, double& y, double2 cs, bool fwd) {
   y = s * a + c * b;
 }
 
+// All threads of the workgroup call this with the same arguments except x and vl: vl is the
+// thread's lane within its vector group (0 .. 64 * replay_waves - 1), member is false for
+// threads outside any group (they take part in the barriers only), x the group's vector.
 template <int B>
 __device__ inline void jacobi_replay(double* x, const double2* __restrict__ log, const JacobiShape& js, int sweeps,
-                                     bool fwd, int lane, double2* stage) {
+                                     bool fwd, int vl, bool member, double2* stage) {
   constexpr int BQ = B + (B & 1);
   constexpr int H = BQ / 2;
   LogStream ls;
-  ls.init(log, stage, &js, sweeps, fwd, lane);
+  ls.init(log, stage, &js, sweeps, fwd);
   long long t = 0;
   const int nb = js.nb, nbp = js.nb / 2;
+  const int lane = threadIdx.x & 63;
   auto intra = [&](int sw) {
-    const bool act = lane < nb;
-    double X[BQ];
-#pragma unroll
-    for (int b = 0; b < BQ; ++b) X[b] = act && b < B ? x[lane * B + b] : 0.0;
+    const int g = vl >> 3, i = vl & 7;
+    const bool act = member && g < nb && i < H;
+    const int pa = i, pb = BQ - 1 - i;  // positions held
+    double a = act && pa < B ? x[g * B + pa] : 0.0;
+    double b = act && pb < B ? x[g * B + pb] : 0.0;
+    const int base = lane & ~7;
     for (int qi = 0; qi < BQ - 1; ++qi) {
       const int q = fwd ? qi : BQ - 2 - qi;
-      ls.ensure(t++, lane);
-      if (!fwd) {  // undo the circle shift that followed step q
-        const double last = X[BQ - 1];
-#pragma unroll
-        for (int b = BQ - 1; b > 1; --b) X[b] = X[b - 1];
-        X[1] = last;
+      ls.ensure(t++);
+      if (!fwd && H > 1) {  // undo the circle shift that followed step q
+        const double a_prev = __shfl(a, base + (i > 0 ? i - 1 : 0), 64);
+        const double b_prev = __shfl(b, base + (i > 0 ? i - 1 : 0), 64);
+        const double b_next = __shfl(b, base + (i + 1 < H ? i + 1 : i), 64);
+        const double na = i == 0 ? a : i == 1 ? b_prev : a_prev;
+        const double nbv = i + 1 < H ? b_next : a;
+        a = na;
+        b = nbv;
       }
-      if (act) {
-#pragma unroll
-        for (int i = 0; i < H; ++i) rot_pair(X[i], X[BQ - 1 - i], ls.entry(StepPos{sw, q}, lane, i), fwd);
-      }
-      if (fwd) {
-        const double first = X[1];
-#pragma unroll
-        for (int b = 1; b < BQ - 1; ++b) X[b] = X[b + 1];
-        X[BQ - 1] = first;
+      if (act) rot_pair(a, b, ls.entry(StepPos{sw, q}, g, i), fwd);
+      if (fwd && H > 1) {  // circle shift: position p takes p + 1 (p >= 1), the last takes 1
+        const double a_next = __shfl(a, base + (i + 1 < H ? i + 1 : i), 64);
+        const double b_prev = __shfl(b, base + (i > 0 ? i - 1 : 0), 64);
+        const double a_one = __shfl(a, base + (H > 1 ? 1 : 0), 64);
+        const double na = i == 0 ? a : i + 1 < H ? a_next : b;
+        const double nbv = i == 0 ? a_one : b_prev;
+        a = na;
+        b = nbv;
       }
     }
-    if (act)
-#pragma unroll
-      for (int b = 0; b < B; ++b) x[lane * B + b] = X[b];
+    if (act) {
+      if (pa < B) x[g * B + pa] = a;
+      if (pb < B) x[g * B + pb] = b;
+    }
   };
   auto round = [&](int sw, int r) {
-    const bool act = lane < nbp;
-    int I = circle_pos(lane, r, nb), J = circle_pos(nb - 1 - lane, r, nb);
+    const int g = vl >> 4, i = vl & 15;
+    const bool act = member && g < nbp && i < B;
+    int I = circle_pos(g < nbp ? g : 0, r, nb), J = circle_pos(nb - 1 - (g < nbp ? g : 0), r, nb);
     if (I > J) {
       const int u = I;
       I = J;
       J = u;
     }
-    if (!act) I = J = 0;
-    double T[B], U[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      T[b] = act ? x[I * B + b] : 0.0;
-      U[b] = act ? x[J * B + b] : 0.0;
-    }
+    double T = act ? x[I * B + i] : 0.0;
+    double U = act ? x[J * B + i] : 0.0;
+    const int base = lane & ~15;
+    const int up = base + (i + 1 < B ? i + 1 : 0);      // slot i takes slot i + 1 (mod B)
+    const int down = base + (i > 0 ? i - 1 : B - 1);    // inverse move
     for (int ji = 0; ji < B; ++ji) {
       const int j = fwd ? ji : B - 1 - ji;
-      ls.ensure(t++, lane);
-      if (!fwd) {  // undo the move of U's slots that followed sub-round j
-        const double last = U[B - 1];
-#pragma unroll
-        for (int b = B - 1; b > 0; --b) U[b] = U[b - 1];
-        U[0] = last;
-      }
-      if (act) {
-        const StepPos p{sw, js.bq - 1 + r * B + j};
-#pragma unroll
-        for (int i = 0; i < B; ++i) rot_pair(T[i], U[i], ls.entry(p, lane, i), fwd);
-      }
-      if (fwd) {
-        const double first = U[0];
-#pragma unroll
-        for (int b = 0; b < B - 1; ++b) U[b] = U[b + 1];
-        U[B - 1] = first;
-      }
+      ls.ensure(t++);
+      if (!fwd) U = __shfl(U, down, 64);
+      if (act) rot_pair(T, U, ls.entry(StepPos{sw, js.bq - 1 + r * B + j}, g, i), fwd);
+      if (fwd) U = __shfl(U, up, 64);
     }
-    if (act)
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        x[I * B + b] = T[b];
-        x[J * B + b] = U[b];
-      }
+    if (act) {
+      x[I * B + i] = T;
+      x[J * B + i] = U;
+    }
   };
   for (int si = 0; si < sweeps; ++si) {
     const int sw = fwd ? si : sweeps - 1 - si;
     if (fwd) {
       intra(sw);
-      for (int r = 0; r < nb - 1; ++r) round(sw, r);
+      lds_barrier();
+      for (int r = 0; r < nb - 1; ++r) {
+        round(sw, r);
+        lds_barrier();
+      }
     } else {
-      for (int r = nb - 2; r >= 0; --r) round(sw, r);
+      for (int r = nb - 2; r >= 0; --r) {
+        round(sw, r);
+        lds_barrier();
+      }
       intra(sw);
+      lds_barrier();
     }
   }
 }

@@ -188,7 +188,8 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
   for (int e = tid; e < ncols; e += blockDim.x) xb[e] = e < N ? inv * (e < n ? gx[e] : gx_x) : 0.0;
   __syncthreads();
   const int sweeps = tb.jres->sweeps;
-  if (wave == 0) replay_any(xb, tb.log, js, sweeps, true, lane, stage);
+  const int vw = replay_waves(js);
+  replay_any(xb, tb.log, js, sweeps, true, tid, wave < vw, stage);
   __syncthreads();
   const int cN = tb.order[N - 1];
   const double lamN = tb.colnorm[cN] * tb.colnorm[cN];
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
     xb[c] = (c < N && c != cN) ? xb[c] / (lamN - sc * sc) : 0.0;
   }
   __syncthreads();
-  if (wave == 0) replay_any(xb, tb.log, js, sweeps, false, lane, stage);
+  replay_any(xb, tb.log, js, sweeps, false, tid, wave < vw, stage);
   __syncthreads();
   for (int e = tid; e < N; e += blockDim.x) wl[e] = xb[e];
   __syncthreads();
@@ -300,32 +301,45 @@ __global__ __launch_bounds__(256) void tls_grad_srht_kernel(int64_t m, int N, in
   }
 }
 
+// Dynamic LDS above the 64 KB default must be requested per kernel (160 KB per CU).
+static hipError_t lds_limit(const void* fn, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const TlsBack& tb, const double* gx, double* work,
                                void* dA, int64_t ldda, void* db, int out_dtype, hipStream_t st) {
   const int N = p.N, s = p.s;
   const JacobiShape js = jacobi_shape(N);
   const size_t alds = (size_t)((js.nb * js.B + N + 1) & ~1) * sizeof(double) + replay_stage_bytes();
+  if (hipError_t e = lds_limit((const void*)tls_adjoint_kernel, alds)) return e;
   tls_adjoint_kernel<<<1, 512, alds, st>>>(s, N, tb, gx, work);
   const size_t lds = (size_t)(2 * s + 2 * N) * sizeof(double) + (size_t)s * 4;
   const unsigned blocks = (unsigned)((m + 4 * 64 - 1) / (4 * 64)) < 4096u ? (unsigned)((m + 255) / 256) : 4096u;
+#define NSK_GRAD(KERNEL, ...)                                                 \
+  {                                                                           \
+    if (hipError_t e = lds_limit((const void*)KERNEL, lds)) return e;         \
+    KERNEL<<<blocks, 256, lds, st>>>(__VA_ARGS__);                            \
+  }
   if (p.kind == NSK_SPARSE_SIGN) {
     if (out_dtype == NSK_F64) {
       if (p.zeta <= 8)
-        tls_grad_sparse_kernel<double, 8><<<blocks, 256, lds, st>>>(m, N, s, p.zeta, p.seed, work, (double*)dA, ldda, (double*)db);
+        NSK_GRAD((tls_grad_sparse_kernel<double, 8>), m, N, s, p.zeta, p.seed, work, (double*)dA, ldda, (double*)db)
       else
-        tls_grad_sparse_kernel<double, 32><<<blocks, 256, lds, st>>>(m, N, s, p.zeta, p.seed, work, (double*)dA, ldda, (double*)db);
+        NSK_GRAD((tls_grad_sparse_kernel<double, 32>), m, N, s, p.zeta, p.seed, work, (double*)dA, ldda, (double*)db)
     } else {
       if (p.zeta <= 8)
-        tls_grad_sparse_kernel<float, 8><<<blocks, 256, lds, st>>>(m, N, s, p.zeta, p.seed, work, (float*)dA, ldda, (float*)db);
+        NSK_GRAD((tls_grad_sparse_kernel<float, 8>), m, N, s, p.zeta, p.seed, work, (float*)dA, ldda, (float*)db)
       else
-        tls_grad_sparse_kernel<float, 32><<<blocks, 256, lds, st>>>(m, N, s, p.zeta, p.seed, work, (float*)dA, ldda, (float*)db);
+        NSK_GRAD((tls_grad_sparse_kernel<float, 32>), m, N, s, p.zeta, p.seed, work, (float*)dA, ldda, (float*)db)
     }
   } else {
     if (out_dtype == NSK_F64)
-      tls_grad_srht_kernel<double><<<blocks, 256, lds, st>>>(m, N, s, p.seed, p.rows, work, (double*)dA, ldda, (double*)db);
+      NSK_GRAD(tls_grad_srht_kernel<double>, m, N, s, p.seed, p.rows, work, (double*)dA, ldda, (double*)db)
     else
-      tls_grad_srht_kernel<float><<<blocks, 256, lds, st>>>(m, N, s, p.seed, p.rows, work, (float*)dA, ldda, (float*)db);
+      NSK_GRAD(tls_grad_srht_kernel<float>, m, N, s, p.seed, p.rows, work, (float*)dA, ldda, (float*)db)
   }
+#undef NSK_GRAD
   return hipGetLastError();
 }
 

@@ -75,7 +75,8 @@ __device__ inline void qr_panel(double* __restrict__ A, int s, int N, double* __
           R[(size_t)(j0 + jj) * ldr + j0 + jj] = beta;
         }
       }
-      __syncthreads();
+      // v and tau travel through LDS; R is not read again in this kernel
+      lds_barrier();
       if (owner && wave > jj) {
         const double* v = vbuf + (size_t)jj * s;
         const double t = tau[jj];
@@ -118,8 +119,16 @@ __device__ inline void qr_panel(double* __restrict__ A, int s, int N, double* __
           for (int u = 0; u < CPW; ++u) d[u] += vv * cl[u][i];
         }
         const double tj = tau[jj];
+        {
+          // one transposed reduction for the CPW dot products, then broadcasts
+          constexpr int SH = 6 - ceil_log2(CPW);
+          double v16[16];
 #pragma unroll
-        for (int u = 0; u < CPW; ++u) d[u] = wave_sum64(d[u]) * tj;
+          for (int u = 0; u < CPW; ++u) v16[u] = d[u];
+          const double tot = reduce_t<CPW>(v16, lane);
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) d[u] = bcast_d(tot, u << SH) * tj;
+        }
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
           const int rr = lane + 64 * i;

@@ -107,10 +107,17 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
         if (r0 + q < gr1) {
           const TAcc a = (TAcc)to_f64(cur[i]);
           const uint32_t nb = hn[q];
+          // all zeta targets of the row in 16-byte reads first, then the atomics back to back
+          // (an LDS read between two atomics would wait for the earlier atomic to finish)
+          uint4 hv[ZMAX / 8];
+#pragma unroll
+          for (int u = 0; u < ZMAX / 8; ++u) hv[u] = reinterpret_cast<const uint4*>(hr + q * ZMAX)[u];
 #pragma unroll
           for (int z = 0; z < ZMAX; ++z) {
             if (z < zeta) {
-              const int h = hr[q * ZMAX + z];
+              const uint4 w4 = hv[z >> 3];
+              const uint32_t w = (z & 7) < 2 ? w4.x : (z & 7) < 4 ? w4.y : (z & 7) < 6 ? w4.z : w4.w;
+              const int h = (int)((w >> (16 * (z & 1))) & 0xffffu);
               atomicAdd(&acc[h * COLS + col], ((nb >> z) & 1u) ? -a : a);
             }
           }

@@ -54,19 +54,22 @@ __host__ __device__ inline int qr_panel_width(int s, int nwaves) {
   return nb;
 }
 
-// waves of the finish stage that replay vectors concurrently
-__host__ __device__ inline int finish_replay_waves(int nwaves) { return nwaves < 2 ? nwaves : 2; }
+// vector groups of the finish stage that replay concurrently
+__host__ __device__ inline int finish_groups(int N, int nwaves) {
+  const int g = nwaves / replay_waves(jacobi_shape(N));
+  return g > 0 ? g : 1;
+}
 
 __host__ __device__ inline size_t finish_head_bytes(int N) { return ((size_t)N * 12 + 255) & ~(size_t)255; }
 
-__host__ __device__ inline size_t finish_wave_bytes(int N) {
+__host__ __device__ inline size_t finish_vec_bytes(int N) {
   const JacobiShape js = jacobi_shape(N);
-  return (((size_t)js.nb * js.B * 8 + 255) & ~(size_t)255) + replay_stage_bytes();
+  return ((size_t)js.nb * js.B * 8 + 255) & ~(size_t)255;
 }
 
 __host__ __device__ inline size_t svd_fast_lds_bytes(int s, int N, int nwaves) {
   const size_t qr = qr_panel_lds_bytes(s, qr_panel_width(s, nwaves));
-  const size_t fin = finish_head_bytes(N) + (size_t)finish_replay_waves(nwaves) * finish_wave_bytes(N);
+  const size_t fin = finish_head_bytes(N) + replay_stage_bytes() + (size_t)finish_groups(N, nwaves) * finish_vec_bytes(N);
   return qr > fin ? qr : fin;
 }
 
@@ -139,15 +142,16 @@ __device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
 }
 
 // ---------------------------------------------------------------- stage 3: finish
-// x <- V x (fwd = false) or V^T x (fwd = true) for one wave, any block size
+// x <- V x (fwd = false) or V^T x (fwd = true), any block size; called by every thread of
+// the workgroup (see jacobi_replay)
 __device__ inline void replay_any(double* x, const double2* log, const JacobiShape& js, int sweeps, bool fwd,
-                                  int lane, double2* stage) {
+                                  int vl, bool member, double2* stage) {
   switch (js.NR) {
-    case 1: jacobi_replay<jacobi_block_size(1)>(x, log, js, sweeps, fwd, lane, stage); break;
-    case 2: jacobi_replay<jacobi_block_size(2)>(x, log, js, sweeps, fwd, lane, stage); break;
-    case 3: jacobi_replay<jacobi_block_size(3)>(x, log, js, sweeps, fwd, lane, stage); break;
-    case 4: jacobi_replay<jacobi_block_size(4)>(x, log, js, sweeps, fwd, lane, stage); break;
-    default: jacobi_replay<jacobi_block_size(5)>(x, log, js, sweeps, fwd, lane, stage); break;
+    case 1: jacobi_replay<jacobi_block_size(1)>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    case 2: jacobi_replay<jacobi_block_size(2)>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    case 3: jacobi_replay<jacobi_block_size(3)>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    case 4: jacobi_replay<jacobi_block_size(4)>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    default: jacobi_replay<jacobi_block_size(5)>(x, log, js, sweeps, fwd, vl, member, stage); break;
   }
 }
 
@@ -160,10 +164,13 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   double* nrm = reinterpret_cast<double*>(smem);
   int* rk = reinterpret_cast<int*>(nrm + N);
-  const int nrep = finish_replay_waves(nw);
-  unsigned char* mine = smem + finish_head_bytes(N) + (size_t)(wave < nrep ? wave : 0) * finish_wave_bytes(N);
-  double* x = reinterpret_cast<double*>(mine);
-  double2* stage = reinterpret_cast<double2*>(mine + finish_wave_bytes(N) - replay_stage_bytes());
+  const int vw = replay_waves(js), ngroups = finish_groups(N, nw);
+  const int grp = wave / vw;
+  const bool member = grp < ngroups;
+  const int vl = (wave - grp * vw) * 64 + lane;
+  double2* stage = reinterpret_cast<double2*>(smem + finish_head_bytes(N));
+  double* x = reinterpret_cast<double*>(smem + finish_head_bytes(N) + replay_stage_bytes() +
+                                        (size_t)(member ? grp : 0) * finish_vec_bytes(N));
   // singular values: column norms of the rotated R
   for (int c = wave; c < N; c += nw) {
     double a = 0;
@@ -191,16 +198,18 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
   }
   __syncthreads();
   const int sweeps = w.jres->sweeps;
-  // trailing vectors: wave q rebuilds V e_{order[N-k+q]} from the log
-  for (int q0 = 0; q0 < k; q0 += nrep) {
-    const int q = q0 + wave;
-    if (wave < nrep && q < k) {
+  // trailing vectors: vector group q rebuilds V e_{order[N-k+q]} from the log
+  for (int q0 = 0; q0 < k; q0 += ngroups) {
+    const int q = q0 + grp;
+    const bool mine = member && q < k;
+    if (mine) {
       const int c = w.order[N - k + q];
-      for (int e = lane; e < ncols; e += 64) x[e] = e == c ? 1.0 : 0.0;
-      __builtin_amdgcn_wave_barrier();
-      jacobi_replay<jacobi_block_size(NR)>(x, w.log, js, sweeps, false, lane, stage);
-      __builtin_amdgcn_wave_barrier();
-      // sign: largest-magnitude entry positive, lowest index on ties
+      for (int e = vl; e < ncols; e += vw * 64) x[e] = e == c ? 1.0 : 0.0;
+    }
+    lds_barrier();
+    jacobi_replay<jacobi_block_size(NR)>(x, w.log, js, sweeps, false, vl, mine, stage);
+    // sign: largest-magnitude entry positive, lowest index on ties (first wave of the group)
+    if (mine && vl < 64) {
       double best = -1;
       int bi = 0;
       for (int e = lane; e < N; e += 64) {
