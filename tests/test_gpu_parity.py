@@ -165,6 +165,21 @@ def test_planted_near_null_subspace_k4(lib):
     assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-9, atol=1e-13 * sig[0])
 
 
+# Column counts that select each rows-per-lane variant of the Jacobi (N > 64 runs the
+# multi-workgroup kernel) and k large enough to need several replay batches.
+@pytest.mark.parametrize("m,N,k,kind", [(8000, 100, 3, "sparse"), (9000, 150, 5, "srht"),
+                                        (12_000, 201, 2, "sparse"), (15_000, 300, 4, "sparse")])
+def test_trailing_vectors_block_jacobi_shapes(lib, m, N, k, kind):
+    a = W.planted_matrix(m, N, k=k, level=1e-4, seed=(8, N))[0].astype(np.float64)
+    s = 4 * N
+    Vk, sk, info = lib.trailing_rsv(t(a), k, kind=kind, s=s, seed=11)
+    torch.cuda.synchronize()
+    vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a, k, kind, s, 11, return_all=True)
+    assert metrics.sin_theta(vk_ref, Vk.cpu().numpy()) <= vec_tol(sig, k)
+    assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-10, atol=1e-14 * sig[0])
+    assert lib.read_info(info).converged
+
+
 @pytest.mark.parametrize("m,n,k,s,kind", [(64, 16, 16, 64, "srht"), (300, 1, 1, 8, "sparse"),
                                           (1000, 8, 3, 1000, "srht"), (513, 5, 2, 10, "sparse")])
 def test_edge_shapes(lib, m, n, k, s, kind):
@@ -225,6 +240,21 @@ def test_tls_solution_and_gradient(lib):
     torch.cuda.synchronize()
     g_gpu = np.hstack([dA.cpu().numpy(), db.cpu().numpy()[:, None]])
     assert rel(g_gpu, grad) < 1e-10, rel(g_gpu, grad)
+
+
+def test_tls_gradient_wide(lib):
+    # N = 201: multi-workgroup Jacobi and a replay spread over three waves in the adjoint
+    m, n, s = 5000, 200, 804
+    M, _ = W.tls_matrix(m=m, n=n, seed=24, dtype=np.float64)
+    xt = W.tls_target(n, seed=11)
+    x, state, _ = lib.tls_solve(t(M[:, :n]), t(M[:, n]), kind="sparse", s=s, seed=12)
+    grad, x_ref, _ = method.tls_grad(M, xt, "sparse", s, 12)
+    gx = 2.0 * (x - t(xt))
+    dA, db = lib.tls_backward(state, m, n, gx, kind="sparse", s=s, seed=12, out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    g_gpu = np.hstack([dA.cpu().numpy(), db.cpu().numpy()[:, None]])
+    assert rel(x.cpu().numpy(), x_ref) < 1e-10
+    assert rel(g_gpu, grad) < 1e-9, rel(g_gpu, grad)
 
 
 def test_tls_gradient_srht_kind(lib):
