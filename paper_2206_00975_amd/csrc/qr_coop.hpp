@@ -1,0 +1,187 @@
+// Householder QR of the sketch SA spread over workgroups (cooperative launch).
+//
+// The columns are dealt out in panels of NB: panel p belongs to workgroup p mod G, which
+// keeps every column of its panels up to date.  For panel p its owner factorises the panel
+// exactly as the single-workgroup QR does (wave w holds panel column w in registers; the
+// reflector of column jj is formed by its wave and applied by the later ones), stores each
+// Householder vector below the diagonal of its column of SA (the unit leading entry is
+// implicit) and tau in a scratch array, and writes the panel's entries of R.  After a grid
+// barrier every workgroup copies the panel's vectors into LDS and applies the NB reflectors,
+// in order, to its own columns to the right of the panel, CPW columns per wave; the rows of
+// the panel become final entries of R.  One grid barrier per panel; the owner of panel p + 1
+// factorises it as soon as its own columns have received panel p.
+#pragma once
+
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "qr_panel.hpp"
+#include "wave_ops.hpp"
+
+namespace nsk {
+
+// A (s x N column-major, ld s) is overwritten; R (ldr rows, zeroed here) receives the N x N
+// upper triangle; tau (N doubles of global scratch).  NB <= waves per workgroup.
+template <int RPL, int NB, int CPW>
+__device__ inline void qr_coop(double* __restrict__ A, int s, int N, double* __restrict__ R, int ldr, size_t r_elems,
+                               double* __restrict__ tau_g, unsigned char* smem) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  double* vbuf = reinterpret_cast<double*>(smem);  // NB x s (rows relative to the panel)
+  double* tau = vbuf + (size_t)NB * s;             // NB
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int G = gridDim.x, me = blockIdx.x;
+  for (size_t e = (size_t)me * blockDim.x + threadIdx.x; e < r_elems; e += (size_t)G * blockDim.x) R[e] = 0.0;
+  grid.sync();
+  const int npanels = (N + NB - 1) / NB;
+  for (int p = 0; p < npanels; ++p) {
+    const int j0 = p * NB;
+    const int nbc = N - j0 < NB ? N - j0 : NB;
+    const int rows = s - j0;
+    double cl[CPW][RPL];
+    if (p % G == me) {
+      // ---- factorise panel p (its columns already hold every earlier reflection)
+      double (&col)[RPL] = cl[0];
+      const bool owner = wave < nbc;
+      if (owner) {
+        const double* a = uniform_ptr(A + (size_t)(j0 + wave) * s + j0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          col[i] = rr < rows ? a[rr] : 0.0;
+        }
+      }
+      for (int jj = 0; jj < nbc; ++jj) {
+        if (wave == jj) {
+          double ss = 0, alpha_part = 0;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int rr = lane + 64 * i;
+            if (rr > jj) ss += col[i] * col[i];
+            if (rr == jj) alpha_part = col[i];
+          }
+          ss = wave_sum64(ss);
+          const double alpha = wave_sum64(alpha_part);
+          double t = 0, beta = alpha, scal = 0;
+          if (ss > 0) {
+            const double nrm = sqrt(alpha * alpha + ss);
+            beta = alpha >= 0 ? -nrm : nrm;
+            t = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+          }
+          double* v = vbuf + (size_t)jj * s;
+          double* acol = A + (size_t)(j0 + jj) * s + j0;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int rr = lane + 64 * i;
+            if (rr < rows) {
+              const double vv = rr < jj ? 0.0 : rr == jj ? 1.0 : col[i] * scal;
+              v[rr] = vv;
+              if (rr > jj) acol[rr] = vv;  // the reflector, below the diagonal
+            }
+            if (rr < jj) R[(size_t)(j0 + jj) * ldr + j0 + rr] = col[i];
+          }
+          if (lane == 0) {
+            tau[jj] = t;
+            tau_g[j0 + jj] = t;
+            R[(size_t)(j0 + jj) * ldr + j0 + jj] = beta;
+          }
+        }
+        lds_barrier();
+        if (owner && wave > jj) {
+          const double* v = vbuf + (size_t)jj * s;
+          const double t = tau[jj];
+          double d = 0;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int rr = lane + 64 * i;
+            if (rr < rows) d += v[rr] * col[i];
+          }
+          d = wave_sum64(d) * t;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int rr = lane + 64 * i;
+            if (rr < rows) col[i] -= d * v[rr];
+          }
+        }
+      }
+    }
+    grid.sync();
+    if (p % G != me) {
+      // ---- the panel's reflectors into LDS (unit leading entries and zeros implicit)
+      for (int jj = 0; jj < nbc; ++jj) {
+        const double* acol = A + (size_t)(j0 + jj) * s + j0;
+        for (int rr = threadIdx.x; rr < rows; rr += blockDim.x)
+          vbuf[(size_t)jj * s + rr] = rr < jj ? 0.0 : rr == jj ? 1.0 : acol[rr];
+      }
+      if (threadIdx.x < nbc) tau[threadIdx.x] = tau_g[j0 + threadIdx.x];
+    }
+    __syncthreads();
+    // ---- apply panel p to this workgroup's columns right of it
+    // owned columns: panels q > p with q mod G == me; CPW consecutive columns per wave task
+    const int first_q = p + 1 + ((me - (p + 1) % G) % G + G) % G;
+    const int per_panel_tasks = (NB + CPW - 1) / CPW;
+    int ntasks = 0;
+    for (int q = first_q; q < npanels; q += G) ++ntasks;
+    ntasks *= per_panel_tasks;
+    for (int task = wave; task < ntasks; task += nw) {
+      const int q = first_q + (task / per_panel_tasks) * G;
+      const int c0 = q * NB + (task % per_panel_tasks) * CPW;
+      const int cend = (q + 1) * NB < N ? (q + 1) * NB : N;
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        const bool cu = c0 + u < cend;
+        const double* a = uniform_ptr(A + (size_t)(cu ? c0 + u : c0) * s + j0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          cl[u][i] = cu && rr < rows ? a[rr] : 0.0;
+        }
+      }
+      for (int jj = 0; jj < nbc; ++jj) {
+        const double* v = vbuf + (size_t)jj * s;
+        double d[CPW];
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) d[u] = 0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          const double vv = rr < rows ? v[rr] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) d[u] += vv * cl[u][i];
+        }
+        const double tj = tau[jj];
+        {
+          constexpr int SH = 6 - ceil_log2(CPW);
+          double v16[16];
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) v16[u] = d[u];
+          const double tot = reduce_t<CPW>(v16, lane);
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) d[u] = bcast_d(tot, u << SH) * tj;
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          const double vv = rr < rows ? v[rr] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) cl[u][i] -= d[u] * vv;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        if (c0 + u >= cend) continue;
+        double* a = opaque_uniform(A + (size_t)(c0 + u) * s + j0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          if (rr < nbc) R[(size_t)(c0 + u) * ldr + j0 + rr] = cl[u][i];
+          else if (rr < rows) a[rr] = cl[u][i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace nsk

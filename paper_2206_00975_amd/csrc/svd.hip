@@ -11,6 +11,7 @@
 
 #include "nsk_internal.hpp"
 #include "svd_device.hpp"
+#include "qr_coop.hpp"
 #include "svd_pipeline.hpp"
 
 namespace nsk {
@@ -55,6 +56,46 @@ __global__ __launch_bounds__(jacobi_threads(NR)) void svd_jacobi_kernel(SvdWork 
   svd_stage_jacobi_nr<NR, JacobiB<NR>::value>(w, smem);
 }
 
+static hipError_t lds_attr(const void* fn, size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// Multi-workgroup QR: panels of NB columns dealt round-robin over the workgroups; tau in
+// the sigma array (overwritten by the finish stage).
+template <int RPL>
+__global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_coop_kernel(SvdWork w) {
+  extern __shared__ unsigned char smem[];
+  constexpr int C = QrCpw<RPL>::value;
+  const JacobiShape js = jacobi_shape(w.N);
+  const int ldr = 64 * js.NR;
+  const size_t relems = (size_t)ldr * js.nb * js.B;
+  switch (qr_panel_width(w.s, blockDim.x >> 6)) {
+    case 16: qr_coop<RPL, 16, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    case 8: qr_coop<RPL, 8, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    case 4: qr_coop<RPL, 4, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    case 2: qr_coop<RPL, 2, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    default: qr_coop<RPL, 1, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+  }
+}
+
+// workgroups of the multi-workgroup QR: one per panel, at most 16
+static int qr_coop_groups(int s, int N, int threads) {
+  const int nb = qr_panel_width(s, threads / 64);
+  const int panels = (N + nb - 1) / nb;
+  return panels < 16 ? panels : 16;
+}
+
+template <int RPL>
+static hipError_t launch_qr_coop(SvdWork& w, hipStream_t st) {
+  const int threads = qr_threads(RPL);
+  const size_t lds = qr_panel_lds_bytes(w.s, qr_panel_width(w.s, threads / 64));
+  if (hipError_t e = lds_attr((const void*)svd_qr_coop_kernel<RPL>, lds)) return e;
+  void* args[] = {&w};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_qr_coop_kernel<RPL>),
+                                    dim3(qr_coop_groups(w.s, w.N, threads)), dim3(threads), args, lds, st);
+}
+
 // Multi-workgroup Jacobi: nb / 2 workgroups of NR waves (one row per lane).
 template <int NR>
 __global__ __launch_bounds__(NR * 64) void svd_jacobi_coop_kernel(SvdWork w) {
@@ -81,10 +122,6 @@ __global__ __launch_bounds__(kSvdThreads) void svd_kernel(SvdPlan p) {
   svd_instance(p.sa, p.s, p.N, p.k, p.max_sweeps, p.R, p.V, p.sigma, p.order, p.Vk, p.sigma_k, p.info, smem);
 }
 
-static hipError_t lds_attr(const void* fn, size_t lds) {
-  if (lds <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
 
 bool svd_fast_path(int s, int N) { return N <= kFastMaxN && s <= kFastMaxS; }
 
@@ -101,20 +138,29 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
     SvdWork w = to_work(p);
     hipError_t e = hipSuccess;
     const int rpl = qr_rpl(p.s), tq = qr_threads(rpl);
-    const size_t lq = svd_fast_lds_bytes(p.s, p.N, tq / 64);
-    switch (rpl) {
-      case 16:
-        e = lds_attr((const void*)svd_qr_kernel<16>, lq);
-        if (e == hipSuccess) svd_qr_kernel<16><<<1, tq, lq, st>>>(w);
-        break;
-      case 32:
-        e = lds_attr((const void*)svd_qr_kernel<32>, lq);
-        if (e == hipSuccess) svd_qr_kernel<32><<<1, tq, lq, st>>>(w);
-        break;
-      default:
-        e = lds_attr((const void*)svd_qr_kernel<64>, lq);
-        if (e == hipSuccess) svd_qr_kernel<64><<<1, tq, lq, st>>>(w);
-        break;
+    if (p.N > 64) {
+      // the panels' trailing updates run on several CUs
+      switch (rpl) {
+        case 16: e = launch_qr_coop<16>(w, st); break;
+        case 32: e = launch_qr_coop<32>(w, st); break;
+        default: e = launch_qr_coop<64>(w, st); break;
+      }
+    } else {
+      const size_t lq = svd_fast_lds_bytes(p.s, p.N, tq / 64);
+      switch (rpl) {
+        case 16:
+          e = lds_attr((const void*)svd_qr_kernel<16>, lq);
+          if (e == hipSuccess) svd_qr_kernel<16><<<1, tq, lq, st>>>(w);
+          break;
+        case 32:
+          e = lds_attr((const void*)svd_qr_kernel<32>, lq);
+          if (e == hipSuccess) svd_qr_kernel<32><<<1, tq, lq, st>>>(w);
+          break;
+        default:
+          e = lds_attr((const void*)svd_qr_kernel<64>, lq);
+          if (e == hipSuccess) svd_qr_kernel<64><<<1, tq, lq, st>>>(w);
+          break;
+      }
     }
     if (e != hipSuccess) return e;
     prof_mark(3, st);
