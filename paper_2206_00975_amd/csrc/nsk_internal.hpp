@@ -77,6 +77,19 @@ __host__ __device__ inline int sparse_cols(int s, int zeta, int acc) {
   return 4;
 }
 
+// XCD-aware placement.  MI355X hands the workgroups of a grid to its 8 XCDs round-robin
+// (workgroup b to XCD b mod 8), and every XCD has its own L2.  A 1-D grid of xcd_grid(n)
+// workgroups is remapped so that XCD x runs work items x*per .. x*per + per - 1 in order:
+// consecutive work items (the column tiles of one row range, which read the same cache
+// lines) share an L2.  xcd_work_item returns -1 for the padding workgroups.
+constexpr int kXcds = 8;
+__host__ __device__ inline int64_t xcd_grid(int64_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
+__host__ __device__ inline int64_t xcd_work_item(int64_t b, int64_t n) {
+  const int64_t per = xcd_grid(n) / kXcds;
+  const int64_t w = (b % kXcds) * per + b / kXcds;
+  return w < n ? w : -1;
+}
+
 __host__ __device__ inline int64_t next_pow2(int64_t m) {
   int64_t p = 1;
   while (p < m) p <<= 1;

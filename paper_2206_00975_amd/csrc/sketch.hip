@@ -51,12 +51,16 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
   uint16_t* hrow = reinterpret_cast<uint16_t*>(acc + (size_t)s * COLS);          // 2 x kSpThreads x ZMAX
   uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + 2 * kSpThreads * ZMAX);     // 2 x kSpThreads
 
+  const int tiles = (N + COLS - 1) / COLS;
+  const int64_t item = xcd_work_item(blockIdx.x, (int64_t)tiles * groups);
+  if (item < 0) return;
+  const int tile = (int)(item % tiles);
+  const int g = (int)(item / tiles);
   const int t = threadIdx.x;
   const int col = t % COLS;
   const int rs = t / COLS;
-  const int c = blockIdx.x * COLS + col;
+  const int c = tile * COLS + col;
   const bool live = c < N;
-  const int g = blockIdx.y;
 
   // dead columns read column 0 and are masked after the load (no branch around the loads)
   const TIn* base = nullptr;
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
   }
   TAcc* out = partial + (size_t)g * s * N;
   for (int i = t; i < s * COLS; i += kSpThreads) {
-    const int row = i / COLS, cc = blockIdx.x * COLS + (i % COLS);
+    const int row = i / COLS, cc = tile * COLS + (i % COLS);
     if (cc < N) out[(size_t)row * N + cc] = acc[i];
   }
 }
@@ -275,7 +279,7 @@ __global__ void srht_small_kernel(Operand op, int64_t m, int N, int s, uint64_t 
 // ============================================================================== launches
 template <typename TIn, typename TAcc>
 static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
-  dim3 grid((p.N + kSrhtCols - 1) / kSrhtCols, p.groups);
+  dim3 grid((unsigned)xcd_grid((int64_t)((p.N + kSrhtCols - 1) / kSrhtCols) * p.groups));
   TAcc* part = static_cast<TAcc*>(p.partial);
   const size_t lds = srht_smem_bytes(p.s);
 #define NSK_SRHT_CASE(U)                                                                        \
@@ -302,7 +306,7 @@ template <typename TIn, typename TAcc>
 static hipError_t sparse_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
   const int acc = sizeof(TAcc) == 8 ? NSK_F64 : NSK_F32;
   const int cols = sparse_cols(p.s, p.zeta, acc);
-  dim3 grid((p.N + cols - 1) / cols, p.groups);
+  dim3 grid((unsigned)xcd_grid((int64_t)((p.N + cols - 1) / cols) * p.groups));
   const int zmax = p.zeta <= 8 ? 8 : 32;
   const size_t lds = sparse_lds_bytes(p.s, p.zeta, acc);
   TAcc* part = static_cast<TAcc*>(p.partial);

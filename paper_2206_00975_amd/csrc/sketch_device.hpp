@@ -181,8 +181,11 @@ __global__ __launch_bounds__(kSrhtThreads) void srht_kernel(Operand op, int64_t 
                                                             uint64_t seed, const int* __restrict__ rows,
                                                             int groups, TAcc* __restrict__ partial) {
   extern __shared__ unsigned char smem[];
-  srht_tile<TIn, TAcc, UMAX>(op, m, N, s, seed, rows, blockIdx.x, blockIdx.y, groups,
-                             partial + (size_t)blockIdx.y * s * N, smem);
+  const int tiles = (N + kSrhtCols - 1) / kSrhtCols;
+  const int64_t item = xcd_work_item(blockIdx.x, (int64_t)tiles * groups);
+  if (item < 0) return;
+  const int tile = (int)(item % tiles), g = (int)(item / tiles);
+  srht_tile<TIn, TAcc, UMAX>(op, m, N, s, seed, rows, tile, g, groups, partial + (size_t)g * s * N, smem);
 }
 
 }  // namespace nsk
