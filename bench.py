@@ -63,6 +63,124 @@ def cpu_baseline(M, s, seed, n_rep=3):
                       f"s={s}), FP64, {dt:.2f} s each"}
 
 
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, out
+
+
+def suite(nsk, W, torch, np):
+    """Precision forms on the AAA-shaped Loewner matrix, the 512-instance batch and the TLS
+    gradient at 2,000,000 x 256; one JSON line per workload (values measured live)."""
+    from oracle import method, metrics
+    dev = torch.device("cuda:0")
+    nsk.load()
+
+    # ---------------------------------------------------------------- precision forms
+    print("[suite] Loewner matrix (greedy AAA, FP64 host)", file=sys.stderr, flush=True)
+    L, _, _, _ = W.loewner_aaa()
+    m, n = L.shape
+    s, k, seed = 2 * n, 1, 3
+    l2 = float(np.linalg.norm(L, 2))
+    _, _, vt = np.linalg.svd(L, full_matrices=False)
+    w_exact = vt[-1][:, None]
+    L64 = torch.from_numpy(L).to(dev)
+    e = np.floor(np.log2(448.0 / np.abs(L).max(axis=0))).astype(np.int8)
+    fp8 = (L64 * torch.from_numpy(2.0 ** e.astype(np.float64)).to(dev)[None, :]).to(torch.float8_e4m3fn)
+    forms = {
+        "gaussian_bf16": (L64.to(torch.bfloat16), "gauss", "f64",
+                          lambda: L64.to(torch.bfloat16).to(torch.float64).cpu().numpy(), "bf16", 2 * s * m * n, 2500.0),
+        "gaussian_e4m3": ([(fp8, torch.from_numpy(-e).to(dev))], "gauss", "f64",
+                          lambda: fp8.to(torch.float64).cpu().numpy() * 2.0 ** (-e.astype(np.float64))[None, :],
+                          "e4m3", 2 * s * m * n, 5000.0),
+        "srht_fp32_f64acc": (L64.to(torch.float32), "srht", "f64",
+                             lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
+        "srht_fp32_plain": (L64.to(torch.float32), "srht", "f32",
+                            lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
+    }
+    rec3 = {"workload": f"Loewner (AAA, tanh(50z)) {m} x {n}, s = {s}, k = 1", "forms": {}}
+    w_oracle64, _, _, sig64, _, _ = method.trailing_rsv(L, k, "srht", s, seed, return_all=True)
+    rec3["oracle_fp64_exact_L"] = {"residual_over_norm": float(np.linalg.norm(L @ w_oracle64)) / l2,
+                                   "sin_theta_vs_svd_of_L": metrics.sin_theta(w_exact, w_oracle64)}
+    for name, (A, kind, acc, stored_fn, gdt, flops, peak) in forms.items():
+        ms_sk, _ = _timed(torch, lambda: nsk.sketch(A, kind, s, seed, acc=acc), 20)
+        ms_solve, (Vk, sk, _) = _timed(torch, lambda: nsk.trailing_rsv(A, k, kind=kind, s=s, seed=seed, acc=acc), 10)
+        w = Vk.cpu().numpy()
+        stored = stored_fn()
+        w_ref, _, _, sig, _, _ = method.trailing_rsv(stored, k, kind, s, seed, gauss_dtype=gdt, return_all=True)
+        r = {"sketch_us": ms_sk * 1e3, "solve_us": ms_solve * 1e3,
+             "sin_theta_vs_oracle_same_input": metrics.sin_theta(w_ref, w),
+             "sin_theta_vs_fp64_oracle": metrics.sin_theta(w_oracle64, w),
+             "residual_over_norm": float(np.linalg.norm(L @ w)) / l2,
+             "sketch_input_gbs": A_bytes(A) / (ms_sk * 1e-3) / 1e9}
+        if flops:
+            r["mfma_tflops"] = flops / (ms_sk * 1e-3) / 1e12
+            r["mfma_frac_of_dense_peak"] = r["mfma_tflops"] / peak
+        rec3["forms"][name] = r
+        print(f"[suite] {name} {r}", file=sys.stderr, flush=True)
+    print(json.dumps({"suite": "precision", **rec3}), flush=True)
+    del L64, fp8
+
+    # ---------------------------------------------------------------- batched
+    print("[suite] batched instances (device generation)", file=sys.stderr, flush=True)
+    shapes = W.batched_sizes(512)
+    As, Vps = [], []
+    for i, (mi, ni) in enumerate(shapes):
+        a, vp = W.planted_matrix_torch(mi, ni, i, dev)
+        As.append(a)
+        Vps.append(vp)
+    ks = [4] * len(As)
+    ss = [4 * ni for _, ni in shapes]
+    seeds = [4000 + i for i in range(len(As))]
+    nsk.trailing_rsv_batched(As, ks, ss, seeds, autotune=True)
+    ms_b, outs = _timed(torch, lambda: nsk.trailing_rsv_batched(As, ks, ss, seeds), 3)
+    total_bytes = sum(mi * ni * 4 for mi, ni in shapes)
+    ang = [metrics.sin_theta(vp.cpu().numpy(), o[0].cpu().numpy()) for vp, o in zip(Vps[:64], outs[:64])]
+    rec4 = {"suite": "batched", "workload": "512 planted instances, m in [5000, 200000], n in [16, 256], "
+                                             "FP32, SRHT s = 4n, k = 4",
+            "ms": ms_b, "instances_per_s": 512 / (ms_b * 1e-3), "input_gb": total_bytes / 1e9,
+            "input_gbs": total_bytes / (ms_b * 1e-3) / 1e9,
+            "planted_subspace_sin_theta_median_first64": float(np.median(ang))}
+    print(json.dumps(rec4), flush=True)
+    del As, outs
+
+    # ---------------------------------------------------------------- gradient
+    print("[suite] TLS gradient workload (host generation)", file=sys.stderr, flush=True)
+    mg, ng, sg = 2_000_000, 256, 1024
+    M, _ = W.tls_matrix(m=mg, n=ng, seed=5)
+    xt = torch.from_numpy(W.tls_target(ng)).to(dev)
+    Mt = torch.from_numpy(M).to(dev)
+    del M
+    A, b = Mt[:, :ng], Mt[:, ng:]
+    ws = nsk._ws(nsk.workspace_bytes(mg, ng + 1, 1, nsk.make_desc("sparse", sg, 5, 8)), dev)
+    state = nsk._ws(nsk.load().nsk_tls_state_bytes(ng, sg, 0), dev)
+    ms_f, (x, _, _) = _timed(torch, lambda: nsk.tls_solve(A, b, kind="sparse", s=sg, seed=5, ws=ws, state=state), 5)
+    gx = 2.0 * (x - xt)
+    ms_bw, (dA, db) = _timed(torch, lambda: nsk.tls_backward(state, mg, ng, gx, kind="sparse", s=sg, seed=5), 5)
+    gbytes = mg * (ng + 1) * 4
+    rec5 = {"suite": "gradient", "workload": "TLS [A|b] 2,000,000 x 257 FP32, sparse-sign s = 1024, "
+                                             "loss |x - x_target|^2",
+            "forward_ms": ms_f, "backward_ms": ms_bw, "forward_read_gbs": gbytes / (ms_f * 1e-3) / 1e9,
+            "backward_write_gbs": gbytes / (ms_bw * 1e-3) / 1e9,
+            "loss": float(((x - xt) ** 2).sum())}
+    print(json.dumps(rec5), flush=True)
+
+
+def A_bytes(A):
+    mats = A if isinstance(A, list) else [A]
+    tot = 0
+    for t in mats:
+        t = t[0] if isinstance(t, tuple) else t
+        tot += t.numel() * t.element_size()
+    return tot
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +191,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--suite", action="store_true",
+                    help="measure the precision (Loewner), batched and gradient workloads instead; one JSON line each")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 1 GiB and exit (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -95,6 +215,10 @@ def main():
 
     import paper_2206_00975_amd as nsk
     import workloads as W
+
+    if args.suite:
+        suite(nsk, W, torch, np)
+        return
 
     nsk.load()
     dev = torch.device("cuda:0")

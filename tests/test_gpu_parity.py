@@ -257,6 +257,21 @@ def test_tls_gradient_wide(lib):
     assert rel(g_gpu, grad) < 1e-9, rel(g_gpu, grad)
 
 
+def test_tls_gradient_at_finite_difference_shape(lib):
+    # the gradient workload's check shape: m = 5000, n = 256, s = 1024, FP64
+    m, n, s = 5000, 256, 1024
+    M, _ = W.tls_matrix(m=m, n=n, seed=5, dtype=np.float64)
+    xt = W.tls_target(n)
+    x, state, _ = lib.tls_solve(t(M[:, :n]), t(M[:, n]), kind="sparse", s=s, seed=5)
+    grad, x_ref, _ = method.tls_grad(M, xt, "sparse", s, 5)
+    gx = 2.0 * (x - t(xt))
+    dA, db = lib.tls_backward(state, m, n, gx, kind="sparse", s=s, seed=5, out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    g_gpu = np.hstack([dA.cpu().numpy(), db.cpu().numpy()[:, None]])
+    assert rel(x.cpu().numpy(), x_ref) < 1e-10
+    assert rel(g_gpu, grad) < 1e-9, rel(g_gpu, grad)
+
+
 def test_tls_gradient_srht_kind(lib):
     m, n, s = 2000, 12, 52
     M, _ = W.tls_matrix(m=m, n=n, seed=22, dtype=np.float64)
