@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kSrhtThreads) void batched_kernel(const BatchInst* 
       w.N = I.N;
       w.k = I.k;
       w.max_sweeps = I.max_sweeps;
-      svd_pipeline(w, smem);
+      svd_pipeline<kSrhtThreads>(w, smem);
     }
     __syncthreads();
   }

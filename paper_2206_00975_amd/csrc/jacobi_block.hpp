@@ -85,19 +85,19 @@ struct JacobiCtx {
   double offmax;   // per-lane largest relative cosine
 };
 
+// The rotation test and the rotation itself are computed side by side and combined with a
+// select (no branch), so the two dependency chains overlap.  When the pair is not rotated
+// (including g = 0, where zeta is infinite or NaN) the result is (c, s, t) = (1, 0, 0).
 __device__ inline void jacobi_params(double a, double b, double g, double tol, double& c, double& s,
                                      double& t, bool& act) {
   const double nab = sqrt(a * b);
   act = fabs(g) > tol * nab;
-  c = 1.0;
-  s = 0.0;
-  t = 0.0;
-  if (act) {
-    const double zeta = (b - a) / (2.0 * g);
-    t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    c = 1.0 / sqrt(1.0 + t * t);
-    s = c * t;
-  }
+  const double zeta = (b - a) / (2.0 * g);
+  const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cc = 1.0 / sqrt(1.0 + tt * tt);
+  c = act ? cc : 1.0;
+  s = act ? cc * tt : 0.0;
+  t = act ? tt : 0.0;
 }
 
 template <int NR>
@@ -348,122 +348,67 @@ __device__ inline int jacobi_block_sweeps(double* __restrict__ R, const JacobiSh
 //
 // One lane per logged rotation: in a block round, lane 16 g + i holds T_i and the U slot i of
 // block pair g; in an intra phase, lane 8 g + i holds positions i and BQ-1-i of block g.
-// Between steps the slots move exactly as the Jacobi kernel's registers did, here with lane
-// shuffles inside the 16- or 8-lane group.  A vector group of replay_waves(js) waves replays
-// one vector (x in LDS, nb * B doubles); several groups replay different vectors at once.
+// Between steps the slots move exactly as the Jacobi kernel's registers did, here with DPP
+// row rotations inside the 16- or 8-lane group.  A vector group of replay_waves(js) waves
+// replays one vector (x in LDS, nb * B doubles); several groups replay different vectors at
+// once, all from one copy of the log.
 //
-// The log streams through LDS (replay_stage_bytes()) in chunks of whole steps, shared by all
-// groups of the workgroup: every thread loads part of the next chunk into registers while the
-// current chunk is applied.  Entry k of a chunk sits at k + k / 16, so that the 16-entry
-// groups of one step fall in different LDS banks.
-constexpr int kReplayPer = 8;       // entries per thread per chunk
-constexpr int kReplayMaxThreads = 512;
+// The log is staged one phase (the intra phase of a sweep, or one block round) at a time:
+// the whole workgroup loads the next phase's entries into registers while the current phase
+// is applied from LDS.  Entry k of a phase sits at k + k / 16 in LDS, so that the 16-entry
+// groups of one step fall in different banks.
+constexpr int kReplayMaxEntries = 4608;  // largest phase for N <= 320: 9 steps x 32 blocks x 16
 
-// LDS of the staged chunk for a workgroup of at most kReplayMaxThreads threads
 __host__ __device__ constexpr size_t replay_stage_bytes() {
-  return (size_t)(kReplayPer * kReplayMaxThreads * 17 / 16) * sizeof(double2);
+  return (size_t)(kReplayMaxEntries + kReplayMaxEntries / 16) * sizeof(double2);
 }
 
-// waves per vector group: max(8 nb, 16 nb / 2) lanes
+// entries per thread that a workgroup of `threads` threads prefetches per phase
+__host__ __device__ constexpr int replay_per_thread(int threads) {
+  return (kReplayMaxEntries + threads - 1) / threads;
+}
+
+// waves per vector group: 8 lanes per block in the intra phase (16 per pair in a round)
 __host__ __device__ inline int replay_waves(const JacobiShape& js) { return (js.nb * 8 + 63) / 64; }
 
-__device__ inline int step_groups(const JacobiShape& js, int st) { return st < js.bq - 1 ? js.nb : js.nb / 2; }
-
-struct StepPos {
-  int sw, st;
+// Phase k of the replay (processing order) of `sweeps` sweeps: its sweep, round (-1 for the
+// intra phase), first log entry and entry count.
+struct ReplayPhase {
+  int sw, r;
+  size_t begin;
+  int len;
 };
 
-__device__ inline size_t step_begin(const JacobiShape& js, size_t per_sweep, StepPos p) {
-  return (size_t)p.sw * per_sweep + jacobi_log_step_offset(js, p.st);
+__device__ inline ReplayPhase replay_phase(const JacobiShape& js, size_t per_sweep, int sweeps, bool fwd, int k) {
+  const int per = js.nb;  // phases per sweep: intra + (nb - 1) rounds
+  const int si = k / per, pi = k % per;
+  ReplayPhase ph;
+  ph.sw = fwd ? si : sweeps - 1 - si;
+  ph.r = fwd ? pi - 1 : (pi < per - 1 ? per - 2 - pi : -1);
+  const size_t intra = (size_t)(js.bq - 1) * js.nb * 16;
+  const size_t round = (size_t)js.B * (js.nb / 2) * 16;
+  ph.begin = (size_t)ph.sw * per_sweep + (ph.r < 0 ? 0 : intra + (size_t)ph.r * round);
+  ph.len = (int)(ph.r < 0 ? intra : round);
+  return ph;
 }
 
-__device__ inline void step_advance(const JacobiShape& js, StepPos& p, bool fwd) {
-  if (fwd) {
-    if (++p.st == js.spw) {
-      p.st = 0;
-      ++p.sw;
-    }
-  } else if (p.st-- == 0) {
-    p.st = js.spw - 1;
-    --p.sw;
+template <int PER>
+__device__ inline void replay_prefetch(const double2* __restrict__ log, const ReplayPhase& ph, double2 (&pre)[PER]) {
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + (int)blockDim.x * u;
+    pre[u] = e < ph.len ? log[ph.begin + e] : make_double2(1.0, 0.0);
   }
 }
 
-// Workgroup-wide log stream (every thread of the workgroup calls every member function);
-// chunks hold at most kReplayPer * blockDim.x entries.
-struct LogStream {
-  const double2* log;
-  double2* stage;
-  const JacobiShape* js;
-  size_t per_sweep;
-  long long steps;      // total steps to replay
-  bool fwd;
-  StepPos plan;         // position of step next_t (processing order)
-  long long next_t;
-  size_t pre_base;
-  long long pre_t1;     // steps [.., pre_t1) are in the prefetched chunk
-  long long cur_t1;     // steps [.., cur_t1) are staged in LDS
-  size_t cur_base;
-  double2 pre[kReplayPer];
-
-  __device__ void prefetch() {
-    size_t lo = ~(size_t)0, hi = 0;
-    long long t = next_t;
-    while (t < steps) {
-      const size_t b = step_begin(*js, per_sweep, plan);
-      const size_t e = b + (size_t)step_groups(*js, plan.st) * 16;
-      const size_t nlo = b < lo ? b : lo, nhi = e > hi ? e : hi;
-      if (nhi - nlo > (size_t)kReplayPer * blockDim.x) break;
-      lo = nlo;
-      hi = nhi;
-      ++t;
-      step_advance(*js, plan, fwd);
-    }
-    pre_base = lo;
-    pre_t1 = t;
-    next_t = t;
+template <int PER>
+__device__ inline void replay_stage(double2* stage, const double2 (&pre)[PER]) {
 #pragma unroll
-    for (int u = 0; u < kReplayPer; ++u) {
-      const size_t e = lo + threadIdx.x + (size_t)blockDim.x * u;
-      pre[u] = e < hi ? log[e] : make_double2(1.0, 0.0);
-    }
+  for (int u = 0; u < PER; ++u) {
+    const int k = threadIdx.x + (int)blockDim.x * u;
+    if (k < kReplayMaxEntries) stage[k + (k >> 4)] = pre[u];
   }
-
-  __device__ void init(const double2* lg, double2* stg, const JacobiShape* shape, int sweeps, bool forward) {
-    log = lg;
-    stage = stg;
-    js = shape;
-    per_sweep = jacobi_log_entries_per_sweep(*shape);
-    steps = (long long)sweeps * shape->spw;
-    fwd = forward;
-    plan = forward ? StepPos{0, 0} : StepPos{sweeps - 1, shape->spw - 1};
-    next_t = 0;
-    cur_t1 = 0;
-    cur_base = 0;
-    if (steps > 0) prefetch();
-  }
-
-  // make step t (processing order) readable from LDS; uniform over the workgroup
-  __device__ void ensure(long long t) {
-    if (t < cur_t1) return;
-    lds_barrier();  // every group is done with the previous chunk
-#pragma unroll
-    for (int u = 0; u < kReplayPer; ++u) {
-      const int k = threadIdx.x + blockDim.x * u;
-      stage[k + (k >> 4)] = pre[u];
-    }
-    lds_barrier();
-    cur_t1 = pre_t1;
-    cur_base = pre_base;
-    if (next_t < steps) prefetch();
-  }
-
-  // (c, s) of slot i of group g at step position p (staged)
-  __device__ double2 entry(StepPos p, int g, int i) const {
-    const size_t k0 = step_begin(*js, per_sweep, p) - cur_base;
-    return stage[17 * ((int)(k0 >> 4) + g) + i];
-  }
-};
+}
 
 __device__ inline void rot_pair(double& x, double& y, double2 cs, bool fwd) {
   const double c = cs.x, s = fwd ? cs.y : -cs.y;
@@ -475,95 +420,86 @@ __device__ inline void rot_pair(double& x, double& y, double2 cs, bool fwd) {
 // All threads of the workgroup call this with the same arguments except x and vl: vl is the
 // thread's lane within its vector group (0 .. 64 * replay_waves - 1), member is false for
 // threads outside any group (they take part in the barriers only), x the group's vector.
-template <int B>
+// PER >= replay_per_thread(blockDim.x).
+template <int B, int PER>
 __device__ inline void jacobi_replay(double* x, const double2* __restrict__ log, const JacobiShape& js, int sweeps,
                                      bool fwd, int vl, bool member, double2* stage) {
   constexpr int BQ = B + (B & 1);
   constexpr int H = BQ / 2;
-  LogStream ls;
-  ls.init(log, stage, &js, sweeps, fwd);
-  long long t = 0;
   const int nb = js.nb, nbp = js.nb / 2;
-  const int lane = threadIdx.x & 63;
-  auto intra = [&](int sw) {
-    const int g = vl >> 3, i = vl & 7;
-    const bool act = member && g < nb && i < H;
-    const int pa = i, pb = BQ - 1 - i;  // positions held
-    double a = act && pa < B ? x[g * B + pa] : 0.0;
-    double b = act && pb < B ? x[g * B + pb] : 0.0;
-    const int base = lane & ~7;
-    for (int qi = 0; qi < BQ - 1; ++qi) {
-      const int q = fwd ? qi : BQ - 2 - qi;
-      ls.ensure(t++);
-      if (!fwd && H > 1) {  // undo the circle shift that followed step q
-        const double a_prev = __shfl(a, base + (i > 0 ? i - 1 : 0), 64);
-        const double b_prev = __shfl(b, base + (i > 0 ? i - 1 : 0), 64);
-        const double b_next = __shfl(b, base + (i + 1 < H ? i + 1 : i), 64);
-        const double na = i == 0 ? a : i == 1 ? b_prev : a_prev;
-        const double nbv = i + 1 < H ? b_next : a;
-        a = na;
-        b = nbv;
+  const size_t per_sweep = jacobi_log_entries_per_sweep(js);
+  const int nphases = sweeps * nb;
+  double2 pre[PER];
+  if (nphases > 0) replay_prefetch<PER>(log, replay_phase(js, per_sweep, sweeps, fwd, 0), pre);
+  for (int k = 0; k < nphases; ++k) {
+    const ReplayPhase ph = replay_phase(js, per_sweep, sweeps, fwd, k);
+    lds_barrier();  // the previous phase is done with the stage and its x updates are visible
+    replay_stage<PER>(stage, pre);
+    lds_barrier();
+    if (k + 1 < nphases) replay_prefetch<PER>(log, replay_phase(js, per_sweep, sweeps, fwd, k + 1), pre);
+    if (ph.r < 0) {
+      // ---- intra phase: lane 8 g + i holds positions i and BQ-1-i of block g
+      const int g = vl >> 3, i = vl & 7;
+      const bool act = member && g < nb && i < H;
+      const int pa = i, pb = BQ - 1 - i;
+      double a = act && pa < B ? x[g * B + pa] : 0.0;
+      double b = act && pb < B ? x[g * B + pb] : 0.0;
+      const int base = 17 * g + i;  // entry (step q, group g, slot i) at 17 (q nb + g) + i
+      for (int qi = 0; qi < BQ - 1; ++qi) {
+        const int q = fwd ? qi : BQ - 2 - qi;
+        if (!fwd && H > 1) {  // undo the circle shift that followed step q
+          const double a_prev = lane_plus<15>(a), b_prev = lane_plus<15>(b), b_next = lane_plus<1>(b);
+          const double na = i == 0 ? a : i == 1 ? b_prev : a_prev;
+          const double nbv = i + 1 < H ? b_next : a;
+          a = na;
+          b = nbv;
+        }
+        if (act) rot_pair(a, b, stage[17 * q * nb + base], fwd);
+        if (fwd && H > 1) {  // circle shift: position p takes p + 1 (p >= 1), the last takes 1
+          const double a_next = lane_plus<1>(a), b_prev = lane_plus<15>(b);
+          const double na = i == 0 ? a : i + 1 < H ? a_next : b;
+          const double nbv = i == 0 ? a_next : b_prev;
+          a = na;
+          b = nbv;
+        }
       }
-      if (act) rot_pair(a, b, ls.entry(StepPos{sw, q}, g, i), fwd);
-      if (fwd && H > 1) {  // circle shift: position p takes p + 1 (p >= 1), the last takes 1
-        const double a_next = __shfl(a, base + (i + 1 < H ? i + 1 : i), 64);
-        const double b_prev = __shfl(b, base + (i > 0 ? i - 1 : 0), 64);
-        const double a_one = __shfl(a, base + (H > 1 ? 1 : 0), 64);
-        const double na = i == 0 ? a : i + 1 < H ? a_next : b;
-        const double nbv = i == 0 ? a_one : b_prev;
-        a = na;
-        b = nbv;
-      }
-    }
-    if (act) {
-      if (pa < B) x[g * B + pa] = a;
-      if (pb < B) x[g * B + pb] = b;
-    }
-  };
-  auto round = [&](int sw, int r) {
-    const int g = vl >> 4, i = vl & 15;
-    const bool act = member && g < nbp && i < B;
-    int I = circle_pos(g < nbp ? g : 0, r, nb), J = circle_pos(nb - 1 - (g < nbp ? g : 0), r, nb);
-    if (I > J) {
-      const int u = I;
-      I = J;
-      J = u;
-    }
-    double T = act ? x[I * B + i] : 0.0;
-    double U = act ? x[J * B + i] : 0.0;
-    const int base = lane & ~15;
-    const int up = base + (i + 1 < B ? i + 1 : 0);      // slot i takes slot i + 1 (mod B)
-    const int down = base + (i > 0 ? i - 1 : B - 1);    // inverse move
-    for (int ji = 0; ji < B; ++ji) {
-      const int j = fwd ? ji : B - 1 - ji;
-      ls.ensure(t++);
-      if (!fwd) U = __shfl(U, down, 64);
-      if (act) rot_pair(T, U, ls.entry(StepPos{sw, js.bq - 1 + r * B + j}, g, i), fwd);
-      if (fwd) U = __shfl(U, up, 64);
-    }
-    if (act) {
-      x[I * B + i] = T;
-      x[J * B + i] = U;
-    }
-  };
-  for (int si = 0; si < sweeps; ++si) {
-    const int sw = fwd ? si : sweeps - 1 - si;
-    if (fwd) {
-      intra(sw);
-      lds_barrier();
-      for (int r = 0; r < nb - 1; ++r) {
-        round(sw, r);
-        lds_barrier();
+      if (act) {
+        if (pa < B) x[g * B + pa] = a;
+        if (pb < B) x[g * B + pb] = b;
       }
     } else {
-      for (int r = nb - 2; r >= 0; --r) {
-        round(sw, r);
-        lds_barrier();
+      // ---- block round: lane 16 g + i holds T_i and U slot i of pair g
+      const int g = vl >> 4, i = vl & 15;
+      const bool act = member && g < nbp && i < B;
+      const int gg = g < nbp ? g : 0;
+      int I = circle_pos(gg, ph.r, nb), J = circle_pos(nb - 1 - gg, ph.r, nb);
+      if (I > J) {
+        const int u = I;
+        I = J;
+        J = u;
       }
-      intra(sw);
-      lds_barrier();
+      double T = act ? x[I * B + i] : 0.0;
+      double U = act ? x[J * B + i] : 0.0;
+      const int base = 17 * g + i;  // entry (step j, group g, slot i) at 17 (j nbp + g) + i
+      for (int ji = 0; ji < B; ++ji) {
+        const int j = fwd ? ji : B - 1 - ji;
+        if (!fwd) {  // undo the slot move that followed sub-round j
+          const double from_prev = lane_plus<15>(U), from_last = lane_plus<(B - 1) % 16 ? (B - 1) % 16 : 15>(U);
+          U = i == 0 ? from_last : from_prev;
+        }
+        if (act) rot_pair(T, U, stage[17 * j * nbp + base], fwd);
+        if (fwd) {  // slot i takes slot i + 1 (mod B)
+          const double from_next = lane_plus<1>(U), from_first = lane_plus<(17 - B) % 16 ? (17 - B) % 16 : 1>(U);
+          U = i == B - 1 ? from_first : from_next;
+        }
+      }
+      if (act) {
+        x[I * B + i] = T;
+        x[J * B + i] = U;
+      }
     }
   }
+  lds_barrier();
 }
 
 }  // namespace nsk

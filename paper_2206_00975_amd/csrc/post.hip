@@ -189,7 +189,7 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
   __syncthreads();
   const int sweeps = tb.jres->sweeps;
   const int vw = replay_waves(js);
-  replay_any(xb, tb.log, js, sweeps, true, tid, wave < vw, stage);
+  replay_any<replay_per_thread(512)>(xb, tb.log, js, sweeps, true, tid, wave < vw, stage);
   __syncthreads();
   const int cN = tb.order[N - 1];
   const double lamN = tb.colnorm[cN] * tb.colnorm[cN];
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
     xb[c] = (c < N && c != cN) ? xb[c] / (lamN - sc * sc) : 0.0;
   }
   __syncthreads();
-  replay_any(xb, tb.log, js, sweeps, false, tid, wave < vw, stage);
+  replay_any<replay_per_thread(512)>(xb, tb.log, js, sweeps, false, tid, wave < vw, stage);
   __syncthreads();
   for (int e = tid; e < N; e += blockDim.x) wl[e] = xb[e];
   __syncthreads();
@@ -216,6 +216,35 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
     work[2 * s + e] = tb.v[e];
     work[2 * s + N + e] = wl[e];
   }
+}
+
+// Rows r0 .. r0 + 63 of dM = p w^T + q v^T (lane l holds p, q of row r0 + l): the row's
+// scalars are broadcast with readlane, the lane's entries of w and v stay in registers for
+// a pass over 256 columns, and every row is written as contiguous 256-byte (FP32) segments.
+template <typename TOut>
+__device__ inline void grad_write_rows(double p, double q, int64_t r0, int64_t m, int n, const double* ww,
+                                       const double* vv, TOut* __restrict__ dA, int64_t ldda, TOut* __restrict__ db,
+                                       int lane) {
+  const int nrow = (int)(m - r0 < 64 ? m - r0 : 64);
+  for (int cb = 0; cb < n; cb += 256) {
+    double wr[4], vr[4];
+    bool live[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = cb + lane + 64 * i;
+      live[i] = c < n;
+      wr[i] = live[i] ? ww[c] : 0.0;
+      vr[i] = live[i] ? vv[c] : 0.0;
+    }
+    for (int rr = 0; rr < nrow; ++rr) {
+      const double pj = bcast_d(p, rr), qj = bcast_d(q, rr);
+      TOut* rowp = uniform_ptr(dA + (r0 + rr) * ldda + cb);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (live[i]) rowp[lane + 64 * i] = (TOut)(pj * wr[i] + qj * vr[i]);
+    }
+  }
+  if (lane < nrow) db[r0 + lane] = (TOut)(p * ww[n] + q * vv[n]);
 }
 
 template <typename TOut, int ZMAX>
@@ -249,13 +278,7 @@ __global__ __launch_bounds__(256) void tls_grad_sparse_kernel(int64_t m, int N, 
           q += sg * yw[rw[z]];
         }
     }
-    const int nrow = (int)(m - r0 < 64 ? m - r0 : 64);
-    for (int rr = 0; rr < nrow; ++rr) {
-      const double pj = __shfl(p, rr, 64), qj = __shfl(q, rr, 64);
-      const int64_t row = r0 + rr;
-      for (int c = lane; c < n; c += 64) dA[row * ldda + c] = (TOut)(pj * ww[c] + qj * vv[c]);
-      if (lane == 0) db[row] = (TOut)(pj * ww[n] + qj * vv[n]);
-    }
+    grad_write_rows<TOut>(p, q, r0, m, n, ww, vv, dA, ldda, db, lane);
   }
 }
 
@@ -291,13 +314,7 @@ __global__ __launch_bounds__(256) void tls_grad_srht_kernel(int64_t m, int N, in
       p *= d;
       q *= d;
     }
-    const int nrow = (int)(m - r0 < 64 ? m - r0 : 64);
-    for (int rr = 0; rr < nrow; ++rr) {
-      const double pj = __shfl(p, rr, 64), qj = __shfl(q, rr, 64);
-      const int64_t row = r0 + rr;
-      for (int c = lane; c < n; c += 64) dA[row * ldda + c] = (TOut)(pj * ww[c] + qj * vv[c]);
-      if (lane == 0) db[row] = (TOut)(pj * ww[n] + qj * vv[n]);
-    }
+    grad_write_rows<TOut>(p, q, r0, m, n, ww, vv, dA, ldda, db, lane);
   }
 }
 

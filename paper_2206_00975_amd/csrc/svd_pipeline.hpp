@@ -144,18 +144,20 @@ __device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
 // ---------------------------------------------------------------- stage 3: finish
 // x <- V x (fwd = false) or V^T x (fwd = true), any block size; called by every thread of
 // the workgroup (see jacobi_replay)
+template <int PER>
 __device__ inline void replay_any(double* x, const double2* log, const JacobiShape& js, int sweeps, bool fwd,
                                   int vl, bool member, double2* stage) {
   switch (js.NR) {
-    case 1: jacobi_replay<jacobi_block_size(1)>(x, log, js, sweeps, fwd, vl, member, stage); break;
-    case 2: jacobi_replay<jacobi_block_size(2)>(x, log, js, sweeps, fwd, vl, member, stage); break;
-    case 3: jacobi_replay<jacobi_block_size(3)>(x, log, js, sweeps, fwd, vl, member, stage); break;
-    case 4: jacobi_replay<jacobi_block_size(4)>(x, log, js, sweeps, fwd, vl, member, stage); break;
-    default: jacobi_replay<jacobi_block_size(5)>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    case 1: jacobi_replay<jacobi_block_size(1), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    case 2: jacobi_replay<jacobi_block_size(2), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    case 3: jacobi_replay<jacobi_block_size(3), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    case 4: jacobi_replay<jacobi_block_size(4), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    default: jacobi_replay<jacobi_block_size(5), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
   }
 }
 
-template <int NR>
+// PER = replay_per_thread(blockDim.x) of the calling kernel
+template <int NR, int PER>
 __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem) {
   const JacobiShape js = jacobi_shape(w.N);
   const int N = w.N, k = w.k;
@@ -207,7 +209,7 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
       for (int e = vl; e < ncols; e += vw * 64) x[e] = e == c ? 1.0 : 0.0;
     }
     lds_barrier();
-    jacobi_replay<jacobi_block_size(NR)>(x, w.log, js, sweeps, false, vl, mine, stage);
+    jacobi_replay<jacobi_block_size(NR), PER>(x, w.log, js, sweeps, false, vl, mine, stage);
     // sign: largest-magnitude entry positive, lowest index on ties (first wave of the group)
     if (mine && vl < 64) {
       double best = -1;
@@ -244,20 +246,23 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
   __syncthreads();
 }
 
+template <int PER>
 __device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
   switch (jacobi_shape(w.N).NR) {
-    case 1: svd_stage_finish_nr<1>(w, smem); break;
-    case 2: svd_stage_finish_nr<2>(w, smem); break;
-    case 3: svd_stage_finish_nr<3>(w, smem); break;
-    case 4: svd_stage_finish_nr<4>(w, smem); break;
-    default: svd_stage_finish_nr<5>(w, smem); break;
+    case 1: svd_stage_finish_nr<1, PER>(w, smem); break;
+    case 2: svd_stage_finish_nr<2, PER>(w, smem); break;
+    case 3: svd_stage_finish_nr<3, PER>(w, smem); break;
+    case 4: svd_stage_finish_nr<4, PER>(w, smem); break;
+    default: svd_stage_finish_nr<5, PER>(w, smem); break;
   }
 }
 
+// the single-workgroup SVD; THREADS = blockDim.x of the calling kernel
+template <int THREADS>
 __device__ inline void svd_pipeline(const SvdWork& w, unsigned char* smem) {
   svd_stage_qr(w, smem);
   svd_stage_jacobi(w, smem);
-  svd_stage_finish(w, smem);
+  svd_stage_finish<replay_per_thread(THREADS)>(w, smem);
 }
 
 }  // namespace nsk

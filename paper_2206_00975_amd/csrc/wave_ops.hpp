@@ -46,6 +46,17 @@ __device__ inline double xor_lane(double v) {
   return dpp_join(xor_lane_i<H>(dlo(v)), xor_lane_i<H>(dhi(v)));
 }
 
+// Value of lane (l + K) mod 16 of the same 16-lane row, 1 <= K <= 15.  DPP row_ror:R rotates
+// a row right (lane l receives lane l - R), so this is row_ror:(16 - K).  All lanes of the
+// row must be active.
+template <int K>
+__device__ inline double lane_plus(double v) {
+  static_assert(K >= 1 && K <= 15, "lane_plus takes 1..15");
+  constexpr int ctrl = 0x120 + (16 - K);
+  return dpp_join(__builtin_amdgcn_update_dpp(0, dlo(v), ctrl, 0xF, 0xF, false),
+                  __builtin_amdgcn_update_dpp(0, dhi(v), ctrl, 0xF, 0xF, false));
+}
+
 __device__ inline double bcast_d(double v, int lane) {
   return dpp_join(__builtin_amdgcn_readlane(dlo(v), lane), __builtin_amdgcn_readlane(dhi(v), lane));
 }

@@ -30,6 +30,15 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def assert_vectors(ref, got, tol):
+    """got spans ref's subspace to tol (sin theta), with orthonormal columns: sin theta alone
+    would accept a zero matrix."""
+    gram = got.T @ got
+    assert np.abs(gram - np.eye(gram.shape[0])).max() < 1e-9, gram
+    err = metrics.sin_theta(ref, got)
+    assert err <= tol, (err, tol)
+
+
 def vec_tol(sigma, k, u=U):
     N = sigma.size
     kappa = sigma[0] / max(sigma[N - k - 1] - sigma[N - k], 1e-300)
@@ -128,7 +137,7 @@ def test_plain_workload_trailing_vector(lib):
     torch.cuda.synchronize()
     vk_ref, sk_ref, sa, sig, V, sweeps = method.trailing_rsv(a, 1, "srht", 200, 1, return_all=True)
     Vk = Vk.cpu().numpy()
-    assert metrics.sin_theta(vk_ref, Vk) <= vec_tol(sig, 1)
+    assert_vectors(vk_ref, Vk, vec_tol(sig, 1))
     assert abs(float(sk[0]) - sk_ref[0]) <= 1e-14 * sig[0]
     inf = lib.read_info(info)
     assert inf.converged and inf.sweeps <= 30
@@ -148,8 +157,7 @@ def test_tls_trailing_vector_and_residual_ratio(lib, kind, dt, acc):
     M64 = M.astype(np.float64)
     vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(M64, 1, kind, s, 8, return_all=True)
     u = U if acc == "f64" else 2.0 ** -24
-    err = metrics.sin_theta(vk_ref, Vk.cpu().numpy())
-    assert err <= max(vec_tol(sig, 1, u), 1e-10 if acc == "f64" else 1e-4), err
+    assert_vectors(vk_ref, Vk.cpu().numpy(), max(vec_tol(sig, 1, u), 1e-10 if acc == "f64" else 1e-4))
     w_opt, _, _ = metrics.trailing_exact(M64, 1)
     r_gpu = metrics.residual_ratio(M64, Vk.cpu().numpy(), w_opt)
     r_ref = metrics.residual_ratio(M64, vk_ref, w_opt)
@@ -161,7 +169,7 @@ def test_planted_near_null_subspace_k4(lib):
     Vk, sk, _ = lib.trailing_rsv(t(a), 4, kind="srht", s=256, seed=3)
     torch.cuda.synchronize()
     vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a.astype(np.float64), 4, "srht", 256, 3, return_all=True)
-    assert metrics.sin_theta(vk_ref, Vk.cpu().numpy()) <= vec_tol(sig, 4)
+    assert_vectors(vk_ref, Vk.cpu().numpy(), vec_tol(sig, 4))
     assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-9, atol=1e-13 * sig[0])
 
 
@@ -175,7 +183,7 @@ def test_trailing_vectors_block_jacobi_shapes(lib, m, N, k, kind):
     Vk, sk, info = lib.trailing_rsv(t(a), k, kind=kind, s=s, seed=11)
     torch.cuda.synchronize()
     vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a, k, kind, s, 11, return_all=True)
-    assert metrics.sin_theta(vk_ref, Vk.cpu().numpy()) <= vec_tol(sig, k)
+    assert_vectors(vk_ref, Vk.cpu().numpy(), vec_tol(sig, k))
     assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-10, atol=1e-14 * sig[0])
     assert lib.read_info(info).converged
 
@@ -188,7 +196,7 @@ def test_edge_shapes(lib, m, n, k, s, kind):
     torch.cuda.synchronize()
     vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a, k, kind, s, 2, return_all=True)
     if k < n:
-        assert metrics.sin_theta(vk_ref, Vk.cpu().numpy()) <= vec_tol(sig, k)
+        assert_vectors(vk_ref, Vk.cpu().numpy(), vec_tol(sig, k))
     else:
         assert np.abs(Vk.cpu().numpy().T @ Vk.cpu().numpy() - np.eye(n)).max() < 1e-13
     assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-10, atol=1e-14 * sig[0])
@@ -313,6 +321,6 @@ def test_batched_matches_single_instances(lib):
     for a, (Vk, sk, info), k, s, seed in zip(As, outs, ks, ss, seeds):
         vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a.astype(np.float64), k, "srht", s, seed,
                                                              return_all=True)
-        assert metrics.sin_theta(vk_ref, Vk.cpu().numpy()) <= vec_tol(sig, k)
+        assert_vectors(vk_ref, Vk.cpu().numpy(), vec_tol(sig, k))
         assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-9, atol=1e-13 * sig[0])
         assert lib.read_info(info).converged
