@@ -161,12 +161,19 @@ def suite(nsk, W, torch, np):
     ws = nsk._ws(nsk.workspace_bytes(mg, ng + 1, 1, nsk.make_desc("sparse", sg, 5, 8)), dev)
     state = nsk._ws(nsk.load().nsk_tls_state_bytes(ng, sg, 0), dev)
     ms_f, (x, _, _) = _timed(torch, lambda: nsk.tls_solve(A, b, kind="sparse", s=sg, seed=5, ws=ws, state=state), 5)
+    nsk.profile_enable(3)
+    for _ in range(3):
+        nsk.tls_solve(A, b, kind="sparse", s=sg, seed=5, ws=ws, state=state)
+    torch.cuda.synchronize()
+    stages, calls = nsk.profile_read()
+    nsk.profile_enable(0)
     gx = 2.0 * (x - xt)
     ms_bw, (dA, db) = _timed(torch, lambda: nsk.tls_backward(state, mg, ng, gx, kind="sparse", s=sg, seed=5), 5)
     gbytes = mg * (ng + 1) * 4
     rec5 = {"suite": "gradient", "workload": "TLS [A|b] 2,000,000 x 257 FP32, sparse-sign s = 1024, "
                                              "loss |x - x_target|^2",
-            "forward_ms": ms_f, "backward_ms": ms_bw, "forward_read_gbs": gbytes / (ms_f * 1e-3) / 1e9,
+            "forward_ms": ms_f, "forward_stage_ms": {k: v / max(calls, 1) for k, v in stages.items()},
+            "backward_ms": ms_bw, "forward_read_gbs": gbytes / (ms_f * 1e-3) / 1e9,
             "backward_write_gbs": gbytes / (ms_bw * 1e-3) / 1e9,
             "loss": float(((x - xt) ** 2).sum())}
     print(json.dumps(rec5), flush=True)
