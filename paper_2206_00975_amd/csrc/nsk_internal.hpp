@@ -66,14 +66,14 @@ __host__ __device__ inline void sparse_column(uint64_t seed, uint64_t j, int s, 
   negbits = word(philox(seed, j >> 2, 0, kSparseSigns), (uint32_t)(j & 3));
 }
 
-// Columns per workgroup of the sparse-sign sketch: the widest of 16, 8, 4 whose s x cols
+// Columns per workgroup of the sparse-sign sketch: the widest of 16, 8, 4 whose (s + 1) x cols
 // accumulator plus the double-buffered draw table (1024 rows x zeta) fits in 160 KB of LDS.
 __host__ __device__ inline int sparse_cols(int s, int zeta, int acc) {
   const size_t zmax = zeta <= 8 ? 8 : 32;
   const size_t table = 2 * 1024 * zmax * 2 + 2 * 1024 * 4;
   const size_t el = acc == NSK_F64 ? 8 : 4;
   for (int c = 16; c > 4; c >>= 1)
-    if ((size_t)s * c * el + table <= 160 * 1024) return c;
+    if ((size_t)(s + 1) * c * el + table <= 160 * 1024) return c;
   return 4;
 }
 

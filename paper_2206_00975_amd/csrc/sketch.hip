@@ -32,23 +32,30 @@ static hipError_t set_lds_limit(const void* fn, size_t bytes) {
 }
 
 // ============================================================================ sparse sign
-// Workgroup (column tile of COLS columns, row group g) keeps an s x COLS accumulator of SA in
-// LDS.  Rows are taken in chunks of kSpThreads: thread t draws the zeta (row, sign) pairs of
-// input row r0 + t into LDS, and thread (rs, col) adds its column's value of rows r0 + rs +
-// (kSpThreads / COLS) i into those zeta accumulator rows with LDS atomics.  The pipeline is
-// one chunk deep: while chunk i is accumulated, chunk i + 1's values are in flight to
-// registers and its draws are written to the other half of a double-buffered table.
+// Workgroup (column tile of COLS columns, row group g) keeps an (s + 1) x COLS accumulator of
+// SA in LDS.  Rows are taken in chunks of kSpThreads: thread t draws the zeta (row, sign)
+// pairs of input row r0 + t into LDS, and thread (rs, col) adds its column's value of rows
+// r0 + rs + (kSpThreads / COLS) i into those zeta accumulator rows with LDS atomics.  The
+// pipeline is one chunk deep: while chunk i is accumulated, chunk i + 1's values are in
+// flight to registers and its draws are written to the other half of a double-buffered table.
+//
+// Nothing in the loop is conditional.  Row s of the accumulator is a dump that is never
+// written out: draw slots z >= zeta and rows past the group's end point at it, and loads past
+// the end re-read the group's last row.  A branch around a load or its use would make the
+// compiler wait for the loads in flight at the branch's join (it must be correct on the path
+// that skipped them), which serialises the prefetch with the accumulation.
 constexpr int kSpThreads = 1024;
 
 template <typename TIn, typename TAcc, int ZMAX, int COLS>
 __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t m, int N, int s,
                                                             int zeta, uint64_t seed, int groups,
                                                             TAcc* __restrict__ partial) {
+  static_assert(ZMAX % 8 == 0, "draw slots are stored eight to a 16-byte word");
   constexpr int RPP = kSpThreads / COLS;  // rows per pass of the workgroup
   constexpr int VPT = COLS;               // values per thread per chunk (kSpThreads / RPP)
   extern __shared__ unsigned char smem_raw[];
-  TAcc* acc = reinterpret_cast<TAcc*>(smem_raw);                                  // s x COLS
-  uint16_t* hrow = reinterpret_cast<uint16_t*>(acc + (size_t)s * COLS);          // 2 x kSpThreads x ZMAX
+  TAcc* acc = reinterpret_cast<TAcc*>(smem_raw);                                  // (s + 1) x COLS
+  uint16_t* hrow = reinterpret_cast<uint16_t*>(acc + (size_t)(s + 1) * COLS);    // 2 x kSpThreads x ZMAX
   uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + 2 * kSpThreads * ZMAX);     // 2 x kSpThreads
 
   const int tiles = (N + COLS - 1) / COLS;
@@ -60,86 +67,82 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
   const int col = t % COLS;
   const int rs = t / COLS;
   const int c = tile * COLS + col;
-  const bool live = c < N;
 
-  // dead columns read column 0 and are masked after the load (no branch around the loads)
+  // columns past N read column 0 into accumulator columns that are never written out
   const TIn* base = nullptr;
   int64_t ld = 0;
-  column_ref<TIn>(op, live ? c : 0, base, ld);
+  column_ref<TIn>(op, c < N ? c : 0, base, ld);
 
-  for (int i = t; i < s * COLS; i += kSpThreads) acc[i] = 0;
+  for (int i = t; i < (s + 1) * COLS; i += kSpThreads) acc[i] = 0;
 
   const int64_t rows_per_group = ((m + groups - 1) / groups + kSpThreads - 1) / kSpThreads * kSpThreads;
   const int64_t gr0 = (int64_t)g * rows_per_group;
   const int64_t gr1 = gr0 + rows_per_group < m ? gr0 + rows_per_group : m;
-
-  auto draw = [&](int64_t r0, int buf) {
-    const int64_t j = r0 + t;
-    if (j < gr1) {
+  if (gr0 >= gr1) {
+    __syncthreads();
+  } else {
+    auto draw = [&](int64_t r0, int buf) {
+      const int64_t j = r0 + t;
       int rw[ZMAX];
       uint32_t nb;
       sparse_column<ZMAX>(seed, (uint64_t)j, s, zeta, rw, nb);
-      uint16_t* hr = hrow + (size_t)buf * kSpThreads * ZMAX;
+      const bool in = j < gr1;
+      uint32_t pk[ZMAX / 2];
 #pragma unroll
-      for (int q = 0; q < ZMAX; ++q)
-        if (q < zeta) hr[t * ZMAX + q] = (uint16_t)rw[q];
+      for (int q = 0; q < ZMAX; q += 2) {
+        const uint32_t h0 = in && q < zeta ? (uint32_t)rw[q] : (uint32_t)s;
+        const uint32_t h1 = in && q + 1 < zeta ? (uint32_t)rw[q + 1] : (uint32_t)s;
+        pk[q / 2] = h0 | (h1 << 16);
+      }
+      uint4* hr = reinterpret_cast<uint4*>(hrow + ((size_t)buf * kSpThreads + t) * ZMAX);
+#pragma unroll
+      for (int u = 0; u < ZMAX / 8; ++u) hr[u] = make_uint4(pk[4 * u], pk[4 * u + 1], pk[4 * u + 2], pk[4 * u + 3]);
       hneg[buf * kSpThreads + t] = nb;
-    }
-  };
-  auto fetch = [&](int64_t r0, TIn (&v)[VPT]) {
+    };
+    auto fetch = [&](int64_t r0, TIn (&v)[VPT]) {
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-      const int64_t r = r0 + rs + RPP * i;
-      v[i] = base[(r < gr1 ? r : r0) * ld];
-    }
-  };
-
-  // chunk i + 1's values load into the register set chunk i does not use (two sets taken in
-  // turn, so no copy forces an early wait on the loads in flight)
-  auto step = [&](int64_t r0, int buf, TIn (&cur)[VPT], TIn (&nxt)[VPT]) {
-    const int64_t r1 = r0 + kSpThreads;
-    if (r1 < gr1) {
-      fetch(r1, nxt);
-      draw(r1, buf ^ 1);
-    }
-    if (live) {
+      for (int i = 0; i < VPT; ++i) {
+        const int64_t r = r0 + rs + RPP * i;
+        v[i] = base[(r < gr1 ? r : gr1 - 1) * ld];
+      }
+    };
+    // chunk i + 1's values load into the register set chunk i does not use (two sets taken in
+    // turn, so no copy forces an early wait on the loads in flight); the last chunk's prefetch
+    // re-reads the final row and is discarded
+    auto step = [&](int64_t r0, int buf, TIn (&cur)[VPT], TIn (&nxt)[VPT]) {
+      fetch(r0 + kSpThreads, nxt);
+      draw(r0 + kSpThreads, buf ^ 1);
       const uint16_t* hr = hrow + (size_t)buf * kSpThreads * ZMAX;
       const uint32_t* hn = hneg + buf * kSpThreads;
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
         const int q = rs + RPP * i;
-        if (r0 + q < gr1) {
-          const TAcc a = (TAcc)to_f64(cur[i]);
-          const uint32_t nb = hn[q];
-          // all zeta targets of the row in 16-byte reads first, then the atomics back to back
-          // (an LDS read between two atomics would wait for the earlier atomic to finish)
-          uint4 hv[ZMAX / 8];
+        const TAcc a = (TAcc)to_f64(cur[i]);
+        const uint32_t nb = hn[q];
+        // all zeta targets of the row in 16-byte reads first, then the atomics back to back
+        // (an LDS read between two atomics would wait for the earlier atomic to finish)
+        uint4 hv[ZMAX / 8];
 #pragma unroll
-          for (int u = 0; u < ZMAX / 8; ++u) hv[u] = reinterpret_cast<const uint4*>(hr + q * ZMAX)[u];
+        for (int u = 0; u < ZMAX / 8; ++u) hv[u] = reinterpret_cast<const uint4*>(hr + q * ZMAX)[u];
 #pragma unroll
-          for (int z = 0; z < ZMAX; ++z) {
-            if (z < zeta) {
-              const uint4 w4 = hv[z >> 3];
-              const uint32_t w = (z & 7) < 2 ? w4.x : (z & 7) < 4 ? w4.y : (z & 7) < 6 ? w4.z : w4.w;
-              const int h = (int)((w >> (16 * (z & 1))) & 0xffffu);
-              atomicAdd(&acc[h * COLS + col], ((nb >> z) & 1u) ? -a : a);
-            }
-          }
+        for (int z = 0; z < ZMAX; ++z) {
+          const uint4 w4 = hv[z >> 3];
+          const uint32_t w = (z & 7) < 2 ? w4.x : (z & 7) < 4 ? w4.y : (z & 7) < 6 ? w4.z : w4.w;
+          const int h = (int)((w >> (16 * (z & 1))) & 0xffffu);
+          atomicAdd(&acc[h * COLS + col], ((nb >> z) & 1u) ? -a : a);
         }
       }
-    }
-    lds_barrier();
-  };
+      lds_barrier();
+    };
 
-  TIn va[VPT], vb[VPT];
-  if (gr0 < gr1) {
+    TIn va[VPT], vb[VPT];
     fetch(gr0, va);
     draw(gr0, 0);
-  }
-  lds_barrier();
-  for (int64_t r0 = gr0; r0 < gr1; r0 += 2 * kSpThreads) {
-    step(r0, 0, va, vb);
-    if (r0 + kSpThreads < gr1) step(r0 + kSpThreads, 1, vb, va);
+    lds_barrier();
+    for (int64_t r0 = gr0; r0 < gr1; r0 += 2 * kSpThreads) {
+      step(r0, 0, va, vb);
+      if (r0 + kSpThreads < gr1) step(r0 + kSpThreads, 1, vb, va);
+    }
   }
   TAcc* out = partial + (size_t)g * s * N;
   for (int i = t; i < s * COLS; i += kSpThreads) {
@@ -298,8 +301,8 @@ static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStrea
 
 size_t sparse_lds_bytes(int s, int zeta, int acc) {
   const int zmax = zeta <= 8 ? 8 : 32;
-  return (size_t)s * sparse_cols(s, zeta, acc) * (acc == NSK_F64 ? 8 : 4) + (size_t)2 * kSpThreads * zmax * 2 +
-         (size_t)2 * kSpThreads * 4;
+  return (size_t)(s + 1) * sparse_cols(s, zeta, acc) * (acc == NSK_F64 ? 8 : 4) +
+         (size_t)2 * kSpThreads * zmax * 2 + (size_t)2 * kSpThreads * 4;
 }
 
 template <typename TIn, typename TAcc>
