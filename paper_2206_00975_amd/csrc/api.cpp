@@ -154,13 +154,23 @@ int build_operand(const nsk_operand* blocks, int nblocks, const nsk_desc* d, Ope
 void srht_rows_host(uint64_t seed, int64_t pool, int64_t s, std::vector<int64_t>& out) {
   out.clear();
   out.reserve((size_t)s);
-  std::vector<int64_t> taken;
+  // membership of the rows taken so far: open addressing, at most half full
+  size_t cap = 16;
+  while (cap < 2 * (size_t)s) cap <<= 1;
+  std::vector<int64_t> table(cap, -1);
+  auto slot = [&](int64_t x) {
+    size_t h = (size_t)(((uint64_t)x * 0x9E3779B97F4A7C15ull) >> 17) & (cap - 1);
+    while (table[h] != -1 && table[h] != x) h = (h + 1) & (cap - 1);
+    return h;
+  };
   for (int64_t t = 0; t < s; ++t) {
     const Words w = philox(seed, (uint64_t)t, 0, kRows);
     const unsigned __int128 u = (unsigned __int128)((uint64_t)w.w[0] | ((uint64_t)w.w[1] << 32));
     const int64_t i = pool - s + t;
     int64_t x = (int64_t)((u * (unsigned __int128)(uint64_t)(i + 1)) >> 64);
-    if (std::find(out.begin(), out.end(), x) != out.end()) x = i;
+    size_t h = slot(x);
+    if (table[h] == x) h = slot(x = i);  // i is new: every row taken so far is below it
+    table[h] = x;
     out.push_back(x);
   }
   std::sort(out.begin(), out.end());
@@ -546,8 +556,8 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
     return NSK_EDEVICE;
   int devid = 0, cus = 256;
   if (hipGetDevice(&devid) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, devid) == hipSuccess) cus = prop.multiProcessorCount;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, devid) == hipSuccess && v > 0) cus = v;
   }
   const size_t lds = batched_lds_bytes(s_max, n_max);
   const int per_cu = lds <= 80 * 1024 ? 2 : 1;
