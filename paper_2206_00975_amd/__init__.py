@@ -235,16 +235,26 @@ def residual(A, Vk):
 
 
 def _problems(As, ks, ss, seeds):
+    """Problem records and per-instance outputs, carved from three allocations (one each for
+    the vectors, the singular values and the info records) rather than three per instance."""
     n = len(As)
     probs = (Problem * n)()
     outs = []
+    dev = As[0].device
+    shapes = [tuple(A.shape) for A in As]
+    vk_all = torch.empty(sum(N * k for (_, N), k in zip(shapes, ks)), dtype=torch.float64, device=dev)
+    sig_all = torch.empty(sum(ks), dtype=torch.float64, device=dev)
+    info_all = torch.zeros((n, INFO_BYTES), dtype=torch.uint8, device=dev)
+    ov = os_ = 0
     for i, A in enumerate(As):
         if A.stride(1) != 1:
             raise ValueError("instances must be row-major")
-        m, N = A.shape
-        Vk = torch.empty((N, ks[i]), dtype=torch.float64, device=A.device)
-        sig = torch.empty(ks[i], dtype=torch.float64, device=A.device)
-        info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+        m, N = shapes[i]
+        Vk = vk_all[ov:ov + N * ks[i]].view(N, ks[i])
+        sig = sig_all[os_:os_ + ks[i]]
+        info = info_all[i]
+        ov += N * ks[i]
+        os_ += ks[i]
         probs[i] = Problem(A.data_ptr(), _TORCH_DT[A.dtype], 0, m, N, A.stride(0), ks[i], ss[i],
                            int(seeds[i]) & 0xFFFFFFFFFFFFFFFF, Vk.data_ptr(), sig.data_ptr(), info.data_ptr())
         outs.append((Vk, sig, info))

@@ -47,9 +47,12 @@ int dflt_acc(const nsk_desc* d) { return d->acc == NSK_F32 ? NSK_F32 : NSK_F64; 
 int plan_groups(const nsk_desc* d, int64_t m, int64_t N) {
   if (d->row_groups > 0) return d->row_groups;
   if (d->kind == NSK_SRHT) {
+    // about two workgroups per CU in total (a 16-column tile fills most of a CU's LDS)
     if (next_pow2(m) <= 64) return 1;
-    const int64_t ct = (N + 7) / 8, nb = (m + 1023) / 1024;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, (1024 + ct - 1) / ct));
+    const int cols = srht_cols((int)N, (int)d->s);
+    const int64_t ct = (N + cols - 1) / cols, nb = (m + 1023) / 1024;
+    const int64_t target = cols == 16 ? 512 : 1024;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, target / ct));
   }
   if (d->kind == NSK_SPARSE_SIGN) {
     // one workgroup per CU (the accumulator fills most of the LDS): about 256 workgroups
@@ -451,7 +454,7 @@ static int batch_plan(const nsk_problem* probs, int32_t count, const nsk_desc* b
     const int64_t nb = (q.m + 1023) / 1024;
     const int g = (int)std::max<int64_t>(1, (nb + rpt - 1) / rpt);
     B.groups[i] = g;
-    B.ntiles += g * (int)((q.n + 7) / 8);
+    B.ntiles += g * (int)((q.n + kBatchCols - 1) / kBatchCols);
     rows_total += align_up((size_t)q.s * 4);
   }
   size_t off = 0;
@@ -536,14 +539,14 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
     double* cn = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * 8);
     void* jr = base_i + o;
     batch_fill_inst(hinst.data() + (size_t)i * batch_inst_bytes(), op, q.m, (int)q.n, (int)q.s, (int)q.k,
-                    B.groups[i], (int)((q.n + 7) / 8), dflt_sweeps(base), q.seed,
+                    B.groups[i], (int)((q.n + kBatchCols - 1) / kBatchCols), dflt_sweeps(base), q.seed,
                     reinterpret_cast<const int*>(w + B.rows + rows_off[i]), partial, sa, R, lg, sig, order, cn, jr,
                     q.Vk, q.sigma_k, q.info);
   }
   int t = 0;
   for (int oi = 0; oi < count; ++oi) {
     const int i = ord[oi];
-    const int ct = (int)((probs[i].n + 7) / 8);
+    const int ct = (int)((probs[i].n + kBatchCols - 1) / kBatchCols);
     for (int g = 0; g < B.groups[i]; ++g)
       for (int c = 0; c < ct; ++c) batch_fill_tile(htile.data() + (size_t)(t++) * batch_tile_bytes(), i, c, g);
   }

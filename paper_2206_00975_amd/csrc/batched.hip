@@ -44,8 +44,10 @@ __global__ void batched_reset(int* counters, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counters[i] = 0;
 }
 
+constexpr int kBatchThreads = SrhtTile<kBatchCols>::kThreads;
+
 template <typename TIn, typename TAcc>
-__global__ __launch_bounds__(kSrhtThreads) void batched_kernel(const BatchInst* __restrict__ insts,
+__global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst* __restrict__ insts,
                                                                const BatchTile* __restrict__ tiles, int ntiles,
                                                                int* __restrict__ counters) {
   extern __shared__ unsigned char smem[];
@@ -62,11 +64,11 @@ __global__ __launch_bounds__(kSrhtThreads) void batched_kernel(const BatchInst* 
     const BatchInst& I = insts[tile.inst];
     TAcc* part = static_cast<TAcc*>(I.partial) + (size_t)tile.g * I.s * I.N;
     if (I.s <= 256)
-      srht_tile<TIn, TAcc, 8>(I.op, I.m, I.N, I.s, I.seed, I.rows, tile.ctile, tile.g, I.groups, part, smem);
+      srht_tile<TIn, TAcc, 8, kBatchCols, true>(I.op, I.m, I.N, I.s, I.seed, I.rows, tile.ctile, tile.g, I.groups, part, smem);
     else if (I.s <= 512)
-      srht_tile<TIn, TAcc, 16>(I.op, I.m, I.N, I.s, I.seed, I.rows, tile.ctile, tile.g, I.groups, part, smem);
+      srht_tile<TIn, TAcc, 16, kBatchCols, true>(I.op, I.m, I.N, I.s, I.seed, I.rows, tile.ctile, tile.g, I.groups, part, smem);
     else
-      srht_tile<TIn, TAcc, 32>(I.op, I.m, I.N, I.s, I.seed, I.rows, tile.ctile, tile.g, I.groups, part, smem);
+      srht_tile<TIn, TAcc, 32, kBatchCols, false>(I.op, I.m, I.N, I.s, I.seed, I.rows, tile.ctile, tile.g, I.groups, part, smem);
     __syncthreads();
     if (tid == 0) {
       const int prev = __hip_atomic_fetch_add(&counters[1 + tile.inst], 1, __ATOMIC_ACQ_REL,
@@ -100,14 +102,14 @@ __global__ __launch_bounds__(kSrhtThreads) void batched_kernel(const BatchInst* 
       w.N = I.N;
       w.k = I.k;
       w.max_sweeps = I.max_sweeps;
-      svd_pipeline<kSrhtThreads>(w, smem);
+      svd_pipeline<kBatchThreads>(w, smem);
     }
     __syncthreads();
   }
 }
 
 size_t batched_lds_bytes(int s_max, int n_max) {
-  const size_t a = srht_smem_bytes(s_max), b = svd_fast_lds_bytes(s_max, n_max, kSrhtThreads / 64);
+  const size_t a = srht_smem_bytes(s_max, kBatchCols), b = svd_fast_lds_bytes(s_max, n_max, kBatchThreads / 64);
   return a > b ? a : b;
 }
 
@@ -123,7 +125,7 @@ hipError_t launch_batched(const void* insts, const void* tiles, int ntiles, int*
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
       if (e != hipSuccess) return e;                                                                \
     }                                                                                               \
-    batched_kernel<TI, TA><<<grid, kSrhtThreads, lds, st>>>(I, T, ntiles, counters);                \
+    batched_kernel<TI, TA><<<grid, kBatchThreads, lds, st>>>(I, T, ntiles, counters);                \
   }
   if (dtype == NSK_F64) {
     if (acc == NSK_F64) NSK_BATCH(double, double) else NSK_BATCH(double, float)

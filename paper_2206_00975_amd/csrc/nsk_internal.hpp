@@ -77,6 +77,13 @@ __host__ __device__ inline int sparse_cols(int s, int zeta, int acc) {
   return 4;
 }
 
+// Columns per SRHT tile for an N-column operand sketched to s rows (host plans and kernels
+// share it): 16-column tiles (512 threads, 256 registers a thread) hold up to 32 sampled rows
+// per thread (s <= 1024); more samples per thread take 8-column tiles, which have twice the
+// registers.  And the column tile of the batched kernel.
+__host__ __device__ inline int srht_cols(int N, int s) { return N > 8 && s <= 1024 ? 16 : 8; }
+constexpr int kBatchCols = 16;
+
 // XCD-aware placement.  MI355X hands the workgroups of a grid to its 8 XCDs round-robin
 // (workgroup b to XCD b mod 8), and every XCD has its own L2.  A 1-D grid of xcd_grid(n)
 // workgroups is remapped so that XCD x runs work items x*per .. x*per + per - 1 in order:

@@ -280,16 +280,16 @@ __global__ void srht_small_kernel(Operand op, int64_t m, int N, int s, uint64_t 
 }
 
 // ============================================================================== launches
-template <typename TIn, typename TAcc>
-static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
-  dim3 grid((unsigned)xcd_grid((int64_t)((p.N + kSrhtCols - 1) / kSrhtCols) * p.groups));
+template <typename TIn, typename TAcc, int COLS>
+static hipError_t srht_dispatch_cols(const Operand& op, const SketchPlan& p, hipStream_t st) {
+  dim3 grid((unsigned)xcd_grid((int64_t)((p.N + COLS - 1) / COLS) * p.groups));
   TAcc* part = static_cast<TAcc*>(p.partial);
-  const size_t lds = srht_smem_bytes(p.s);
-#define NSK_SRHT_CASE(U)                                                                        \
-  {                                                                                             \
-    if (hipError_t e = set_lds_limit((const void*)srht_kernel<TIn, TAcc, U>, lds)) return e;                                      \
-    srht_kernel<TIn, TAcc, U><<<grid, kSrhtThreads, lds, st>>>(op, p.m, p.N, p.s, p.seed, p.rows, \
-                                                               p.groups, part);                 \
+  const size_t lds = srht_smem_bytes(p.s, COLS);
+  constexpr int NT = SrhtTile<COLS>::kThreads;
+#define NSK_SRHT_CASE(U)                                                                                \
+  {                                                                                                     \
+    if (hipError_t e = set_lds_limit((const void*)srht_kernel<TIn, TAcc, U, COLS>, lds)) return e;      \
+    srht_kernel<TIn, TAcc, U, COLS><<<grid, NT, lds, st>>>(op, p.m, p.N, p.s, p.seed, p.rows, p.groups, part); \
   }
   if (p.s <= 256) NSK_SRHT_CASE(8)
   else if (p.s <= 512) NSK_SRHT_CASE(16)
@@ -297,6 +297,11 @@ static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStrea
   else NSK_SRHT_CASE(64)
 #undef NSK_SRHT_CASE
   return hipGetLastError();
+}
+
+template <typename TIn, typename TAcc>
+static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
+  return srht_cols(p.N, p.s) == 8 ? srht_dispatch_cols<TIn, TAcc, 8>(op, p, st) : srht_dispatch_cols<TIn, TAcc, 16>(op, p, st);
 }
 
 size_t sparse_lds_bytes(int s, int zeta, int acc) {

@@ -49,68 +49,89 @@ __device__ inline void box_muller(uint32_t a, uint32_t b, float& g0, float& g1) 
 }
 
 // =================================================================================== SRHT
-constexpr int kT = 1024;       // rows per transform block
-constexpr int kSrhtCols = 8;   // columns per workgroup
-constexpr int kSrhtThreads = 256;
+constexpr int kT = 1024;  // rows per transform block
 
-// SRHT partial sketch of column tile `ctile` (kSrhtCols columns) over the row blocks
+// A workgroup of 32 * COLS threads sketches a tile of COLS columns: thread (rs, col) holds
+// rows rs + 32 k (k = 0..31) of its column for phase 1.  A wave covers 64 / COLS rows of COLS
+// adjacent columns per load, so wider tiles read longer contiguous pieces of each row.
+template <int COLS> struct SrhtTile {
+  static_assert(COLS == 8 || COLS == 16, "column tiles of 8 or 16");
+  static constexpr int kThreads = 32 * COLS;
+};
+
+// SRHT partial sketch of column tile `ctile` (COLS columns) over the row blocks
 // j1 = g0, g0 + gstride, ...; the result for the s sampled rows is written to
-// out[i * N + c].  Must be called by all kSrhtThreads threads of the workgroup.
-// smem: at least srht_smem_bytes(s) bytes.
-__host__ __device__ inline size_t srht_smem_bytes(int s) {
-  return (size_t)(kT * kSrhtCols + 64) * 8 + (kT / 32) * 4 + (size_t)((s + 1) & ~1) * 4;
+// out[i * N + c].  Must be called by all 32 * COLS threads of the workgroup.
+// smem: at least srht_smem_bytes(s, COLS) bytes.  PF: prefetch the next block's values while
+// the current one is transformed (32 more registers a thread).
+__host__ __device__ inline size_t srht_smem_bytes(int s, int cols) {
+  return (size_t)(kT * cols + 64) * 8 + (kT / 32) * 4 + (size_t)s * 8;
 }
 
-template <typename TIn, typename TAcc, int UMAX>
+template <typename TIn, typename TAcc, int UMAX, int COLS, bool PF = true>
 __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uint64_t seed,
                                  const int* __restrict__ rows, int ctile, int64_t g0, int64_t gstride,
                                  TAcc* __restrict__ out, unsigned char* smem) {
+  constexpr int NT = SrhtTile<COLS>::kThreads;
+  constexpr int RS = 32 * COLS + 2;            // doubles between rows rl and rl + 32 of the tile
   double* tile = reinterpret_cast<double*>(smem);
-  uint32_t* signbits = reinterpret_cast<uint32_t*>(tile + kT * kSrhtCols + 64);
-  int* srow = reinterpret_cast<int*>(signbits + kT / 32);
+  uint32_t* signbits = reinterpret_cast<uint32_t*>(tile + kT * COLS + 64);
+  int2* srec = reinterpret_cast<int2*>(signbits + kT / 32);  // per sample: tile offset of i2, i1
 
   const int t = threadIdx.x;
-  const int col = t & (kSrhtCols - 1);
-  const int rs = t >> 3;                      // 0..31
-  const int c = ctile * kSrhtCols + col;
+  const int col = t % COLS;
+  const int rs = t / COLS;                    // 0..31
+  const int c = ctile * COLS + col;
   const bool live = c < N;
 
-  // dead columns read column 0 and are masked after the load (no branch around the loads)
+  // columns past N read column 0; their sums are never written out
   const TIn* base = nullptr;
   int64_t ld = 0;
   column_ref<TIn>(op, live ? c : 0, base, ld);
 
   __syncthreads();
-  for (int i = t; i < s; i += kSrhtThreads) srow[i] = rows[i];
+  for (int i = t; i < s; i += NT) {
+    const int r = rows[i];
+    const int i2 = r & (kT - 1);
+    srec[i] = make_int2(i2 * COLS + (i2 >> 5) * 2, r >> 10);
+  }
 
   TAcc acc[UMAX];
 #pragma unroll
   for (int u = 0; u < UMAX; ++u) acc[u] = 0;
 
+  const int64_t nfull = m / kT;                 // blocks with all kT rows present
   const int64_t nblocks = (m + kT - 1) / kT;
-  for (int64_t j1 = g0; j1 < nblocks; j1 += gstride) {
-    const int64_t r0 = j1 * kT;
+  const TIn* lane0 = base + (int64_t)rs * ld;   // row rs of block 0
+  const int64_t kstep = 32 * ld;                // rows rs + 32 k
+  auto fetch_full = [&](int64_t j1, TIn (&raw)[32]) {
+    const TIn* p = lane0 + j1 * kT * ld;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) raw[k] = p[k * kstep];
+  };
+
+  // One block: signs, the kT-point transform (bits 5..9 in registers, LDS transpose, bits
+  // 0..4 in registers) and the sampled outer stage.  raw holds rows rs + 32 k of block j1
+  // (zero past m).
+  auto block = [&](int64_t j1, const TIn (&raw)[32]) {
     __syncthreads();
     if (t < kT / 128) {
-      const Words w = philox(seed, (uint64_t)(r0 >> 7) + t, 0, kSigns);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) signbits[t * 4 + q] = w.w[q];
+      const Words w = philox(seed, (uint64_t)(j1 * kT >> 7) + t, 0, kSigns);
+      *reinterpret_cast<uint4*>(signbits + 4 * t) = make_uint4(w.w[0], w.w[1], w.w[2], w.w[3]);
     }
     __syncthreads();
-    // phase 1: rows rs + 32k, butterflies over row bits 5..9 (bits of k)
+    // phase 1: row rs + 32 k carries bit rs of sign word k (the same word across the wave)
     TAcc x[32];
-    TIn raw[32];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int64_t row = r0 + rs + 32 * k;
-      raw[k] = base[(row < m ? row : r0) * ld];
-    }
+    for (int q = 0; q < 8; ++q) {
+      const uint4 w4 = reinterpret_cast<const uint4*>(signbits)[q];
+      const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int rl = rs + 32 * k;
-      const TAcc v = live && r0 + rl < m ? (TAcc)to_f64(raw[k]) : (TAcc)0;
-      const bool neg = (signbits[rl >> 5] >> (rl & 31)) & 1u;
-      x[k] = neg ? -v : v;
+      for (int e = 0; e < 4; ++e) {
+        const int k = 4 * q + e;
+        const TAcc v = (TAcc)to_f64(raw[k]);
+        x[k] = ((ws[e] >> rs) & 1u) ? -v : v;
+      }
     }
 #pragma unroll
     for (int h = 1; h < 32; h <<= 1) {
@@ -123,18 +144,15 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
         }
       }
     }
+    double* tw = tile + rs * COLS + col;      // row rs + 32 k at tw[k * RS]
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int rl = rs + 32 * k;
-      tile[rl * kSrhtCols + col + (rl >> 5) * 2] = (double)x[k];
-    }
+    for (int k = 0; k < 32; ++k) tw[k * RS] = (double)x[k];
     __syncthreads();
-    // phase 2: rows 32 rs + k, butterflies over row bits 0..4
+    // phase 2: rows 32 rs + k, butterflies over row bits 0..4; each thread writes back only
+    // the cells it read, so no barrier is needed between the read and the write
+    double* tr = tile + 32 * rs * COLS + col + rs * 2;  // row 32 rs + k at tr[k * COLS]
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int rl = 32 * rs + k;
-      x[k] = (TAcc)tile[rl * kSrhtCols + col + rs * 2];
-    }
+    for (int k = 0; k < 32; ++k) x[k] = (TAcc)tr[k * COLS];
 #pragma unroll
     for (int h = 1; h < 32; h <<= 1) {
 #pragma unroll
@@ -146,26 +164,52 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
         }
       }
     }
-    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int rl = 32 * rs + k;
-      tile[rl * kSrhtCols + col + rs * 2] = (double)x[k];
-    }
+    for (int k = 0; k < 32; ++k) tr[k * COLS] = (double)x[k];
     __syncthreads();
-    // sampled outer stage: sample i = rs + 32u takes signed row i2 of the block
+    // sampled outer stage: sample i = rs + 32 u takes row i2 of the block with the sign
+    // (-1)^popcount(i1 & j1)
+    const uint32_t jlo = (uint32_t)j1;
 #pragma unroll
     for (int u = 0; u < UMAX; ++u) {
       const int i = rs + 32 * u;
       if (i < s) {
-        const int r = srow[i];
-        const int i2 = r & (kT - 1);
-        const int64_t i1 = (int64_t)r >> 10;
-        const TAcc y = (TAcc)tile[i2 * kSrhtCols + col + (i2 >> 5) * 2];
-        const bool neg = __popcll((uint64_t)(i1 & j1)) & 1;
-        acc[u] += neg ? -y : y;
+        const int2 rec = srec[i];
+        const TAcc y = (TAcc)tile[rec.x + col];
+        acc[u] += (__popc((uint32_t)rec.y & jlo) & 1) ? -y : y;
       }
     }
+  };
+
+  // full blocks: the next block's values are in flight while this one is transformed; the
+  // prefetch issued with the last full block re-reads that block and is discarded
+  if (g0 < nfull) {
+    TIn cur[32];
+    fetch_full(g0, cur);
+    for (int64_t j1 = g0; j1 < nfull; j1 += gstride) {
+      if (PF) {
+        TIn nxt[32];
+        const int64_t jn = j1 + gstride < nfull ? j1 + gstride : j1;
+        fetch_full(jn, nxt);
+        block(j1, cur);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) cur[k] = nxt[k];
+      } else {
+        block(j1, cur);
+        if (j1 + gstride < nfull) fetch_full(j1 + gstride, cur);
+      }
+    }
+  }
+  // the partial last block, if this tile's blocks include it: rows past m read as zero
+  if (nblocks > nfull && (nfull - g0) % gstride == 0 && nfull >= g0) {
+    TIn raw[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int64_t row = nfull * kT + rs + 32 * k;
+      const TIn v = base[(row < m ? row : m - 1) * ld];
+      raw[k] = row < m ? v : (TIn)0;
+    }
+    block(nfull, raw);
   }
   if (live) {
 #pragma unroll
@@ -176,16 +220,16 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
   }
 }
 
-template <typename TIn, typename TAcc, int UMAX>
-__global__ __launch_bounds__(kSrhtThreads) void srht_kernel(Operand op, int64_t m, int N, int s,
-                                                            uint64_t seed, const int* __restrict__ rows,
-                                                            int groups, TAcc* __restrict__ partial) {
+template <typename TIn, typename TAcc, int UMAX, int COLS>
+__global__ __launch_bounds__(SrhtTile<COLS>::kThreads) void srht_kernel(Operand op, int64_t m, int N, int s,
+                                                                         uint64_t seed, const int* __restrict__ rows,
+                                                                         int groups, TAcc* __restrict__ partial) {
   extern __shared__ unsigned char smem[];
-  const int tiles = (N + kSrhtCols - 1) / kSrhtCols;
+  const int tiles = (N + COLS - 1) / COLS;
   const int64_t item = xcd_work_item(blockIdx.x, (int64_t)tiles * groups);
   if (item < 0) return;
   const int tile = (int)(item % tiles), g = (int)(item / tiles);
-  srht_tile<TIn, TAcc, UMAX>(op, m, N, s, seed, rows, tile, g, groups, partial + (size_t)g * s * N, smem);
+  srht_tile<TIn, TAcc, UMAX, COLS>(op, m, N, s, seed, rows, tile, g, groups, partial + (size_t)g * s * N, smem);
 }
 
 }  // namespace nsk

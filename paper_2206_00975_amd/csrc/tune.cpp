@@ -52,11 +52,11 @@ void save_locked() {
 }
 }  // namespace
 
-// Default: each tile's FP64 partial (s x 8) stays near 1/16 of the FP32 data it covers,
-// i.e. rows_per_tile ~ s / 64 blocks with s = 4n.
+// Default: each tile's FP64 partial (s x 16) stays near 1/16 of the FP32 data it covers
+// (1024-row blocks x 16 columns), i.e. rows_per_tile ~ s / 32 blocks with s = 4n.
 int heuristic_rows_per_tile(int n) {
   int r = 4;
-  while (r < n / 16 && r < 64) r <<= 1;
+  while (r < n / 8 && r < 64) r <<= 1;
   return r;
 }
 

@@ -111,7 +111,7 @@ def test_batched_plan_and_tuner_table(lib):
     assert nsk.batched_workspace_bytes(shapes, ks, ss) > 0
     assert nsk.batched_workspace_bytes([(5000, 300)], [4], [1200]) == 0       # n > 256
     nsk.tune_clear()
-    assert nsk.tune_lookup(256) == 16 and nsk.tune_lookup(16) == 4
+    assert nsk.tune_lookup(256) == 32 and nsk.tune_lookup(16) == 4
     nsk.tune_set(256, 32)
     assert nsk.tune_lookup(250) == 32
     nsk.tune_clear()
