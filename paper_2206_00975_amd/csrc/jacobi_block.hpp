@@ -82,19 +82,41 @@ struct JacobiResult {
 struct JacobiCtx {
   double tol;
   int rotations;   // per-lane count
-  double offmax;   // per-lane largest relative cosine
+  double offmax;   // per-lane largest squared relative cosine g^2 / (a b)
 };
 
-// The rotation test and the rotation itself are computed side by side and combined with a
-// select (no branch), so the two dependency chains overlap.  When the pair is not rotated
-// (including g = 0, where zeta is infinite or NaN) the result is (c, s, t) = (1, 0, 0).
+// Rutishauser's rotation for the column pair with squared norms a, b and inner product g
+// (the trig form of the two-sided Jacobi rotation): zeta = (b - a) / (2 g),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t.  The pair is
+// rotated when |g| > tol sqrt(a b), tested as g^2 > tol^2 a b.  Reciprocals and reciprocal
+// square roots start from the hardware estimates and take Newton steps: one for zeta and t
+// (their rounding only tilts the angle), two for c, so that c^2 + s^2 = c^2 (1 + t^2) = 1 to
+// working precision and the rotation stays orthogonal.  No branch: every quantity is computed
+// and the result selected, so the dependency chains overlap.  When the pair is not rotated
+// (including g = 0) the result is (c, s, t) = (1, 0, 0).
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ inline double rsq_nr(double x, int steps) {
+  double y = __builtin_amdgcn_rsq(x);
+  for (int k = 0; k < steps; ++k) {
+    const double h = fma(-x * y, y, 1.0);  // 1 - x y^2
+    y = fma(0.5 * y, h, y);
+  }
+  return y;
+}
 __device__ inline void jacobi_params(double a, double b, double g, double tol, double& c, double& s,
                                      double& t, bool& act) {
-  const double nab = sqrt(a * b);
-  act = fabs(g) > tol * nab;
-  const double zeta = (b - a) / (2.0 * g);
-  const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cc = 1.0 / sqrt(1.0 + tt * tt);
+  act = g * g > (tol * tol) * (a * b);
+  const double zeta = (b - a) * rcp_nr(2.0 * g);
+  const double az = fabs(zeta);
+  const double q = fma(zeta, zeta, 1.0);
+  const double root = az > 1e150 ? az : q * rsq_nr(q, 1);     // sqrt(1 + zeta^2)
+  const double r = rcp_nr(az + root);
+  const double tt = zeta >= 0 ? r : -r;
+  const double cc = rsq_nr(fma(tt, tt, 1.0), 2);
   c = act ? cc : 1.0;
   s = act ? cc * tt : 0.0;
   t = act ? tt : 0.0;
@@ -150,8 +172,8 @@ __device__ inline void jacobi_intra_block(double* __restrict__ R, int ld, int bl
     bool act;
     jacobi_params(sab[0], sab[1], sab[2], cx.tol, c, s, t, act);
     if (lead) {
-      const double nab = sqrt(sab[0] * sab[1]);
-      if (nab > 0) cx.offmax = fmax(cx.offmax, fabs(sab[2]) / nab);
+      const double ab = sab[0] * sab[1];
+      if (ab > 0) cx.offmax = fmax(cx.offmax, sab[2] * sab[2] * rcp_nr(ab));
       if (act) cx.rotations++;
       lg[pi] = make_double2(c, s);
     }
@@ -241,8 +263,8 @@ __device__ inline void jacobi_inter_pair(double* __restrict__ R, int ld, int I, 
       act = false;
     }
     if (lead) {
-      const double nab = sqrt(alpha * beta);
-      if (nab > 0) cx.offmax = fmax(cx.offmax, fabs(g) / nab);
+      const double ab = alpha * beta;
+      if (ab > 0) cx.offmax = fmax(cx.offmax, g * g * rcp_nr(ab));
       if (act) cx.rotations++;
       lg[pi] = make_double2(c, s);
     }
@@ -328,7 +350,7 @@ __device__ inline int jacobi_block_sweeps(double* __restrict__ R, const JacobiSh
     }
     __syncthreads();
     sweeps = sw + 1;
-    off = *sh_off;
+    off = sqrt(*sh_off);
     const int total = *sh_rot;
     __syncthreads();
     if (total == 0) {

@@ -43,13 +43,13 @@ __device__ inline double coop_reduce(double (&v)[16], int lane, int wave, double
 
 struct CoopCount {
   int rotations;   // counted by the first wave's leading lanes only
-  double offmax;
+  double offmax;   // largest squared relative cosine g^2 / (a b)
 };
 
 template <int NW, int B>
 __device__ inline void coop_intra_block(double* __restrict__ R, int ld, int blk, double2* lg, int stride,
                                         double tol, CoopCount& cc, double (*part)[NW][16], int& buf, int lane,
-                                        int wave) {
+                                        int wave, double2* bc) {
   constexpr int BQ = B + (B & 1);
   constexpr int H = BQ / 2;
   constexpr int SH = 6 - ceil_log2(H);
@@ -75,14 +75,21 @@ __device__ inline void coop_intra_block(double* __restrict__ R, int ld, int blk,
     bool act;
     jacobi_params(sab[0], sab[1], sab[2], tol, c, s, t, act);
     if (lead) {
-      const double nab = sqrt(sab[0] * sab[1]);
-      if (nab > 0) cc.offmax = fmax(cc.offmax, fabs(sab[2]) / nab);
+      const double ab = sab[0] * sab[1];
+      if (ab > 0) cc.offmax = fmax(cc.offmax, sab[2] * sab[2] * rcp_nr(ab));
       if (act) cc.rotations++;
       lg[pi] = make_double2(c, s);
     }
+    // every lane needs all H rotations: through this wave's LDS slots
+    if ((lane & ((1 << SH) - 1)) == 0 && pi < H) bc[pi] = make_double2(c, s);
+    wave_lds_sync();
+    double2 csv[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) csv[i] = bc[i];
+    __builtin_amdgcn_sched_barrier(0);  // all reads in flight before the first rotation
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-      const double ci = bcast_d(c, i << SH), si = bcast_d(s, i << SH);
+      const double ci = csv[i].x, si = csv[i].y;
       const double a = X[i], b = X[BQ - 1 - i];
       X[i] = ci * a - si * b;
       X[BQ - 1 - i] = si * a + ci * b;
@@ -100,7 +107,7 @@ __device__ inline void coop_intra_block(double* __restrict__ R, int ld, int blk,
 template <int NW, int B>
 __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, int J, double2* lg, int stride,
                                        double tol, CoopCount& cc, double (*part)[NW][16], int& buf, int lane,
-                                       int wave) {
+                                       int wave, double2* bc) {
   constexpr int SH = 6 - ceil_log2(B);
   const int pi = lane >> SH;
   const bool valid = pi < B;
@@ -144,8 +151,8 @@ __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, in
       act = false;
     }
     if (lead) {
-      const double nab = sqrt(alpha * beta);
-      if (nab > 0) cc.offmax = fmax(cc.offmax, fabs(g) / nab);
+      const double ab = alpha * beta;
+      if (ab > 0) cc.offmax = fmax(cc.offmax, g * g * rcp_nr(ab));
       if (act) cc.rotations++;
       lg[pi] = make_double2(c, s);
     }
@@ -153,9 +160,16 @@ __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, in
       alpha = fmax(alpha - t * g, 0.0);
       beta = fmax(beta + t * g, 0.0);
     }
+    // every lane needs all B rotations: through this wave's LDS slots
+    if ((lane & ((1 << SH) - 1)) == 0 && valid) bc[pi] = make_double2(c, s);
+    wave_lds_sync();
+    double2 csv[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) csv[i] = bc[i];
+    __builtin_amdgcn_sched_barrier(0);  // all reads in flight before the first rotation
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      const double ci = bcast_d(c, i << SH), si = bcast_d(s, i << SH);
+      const double ci = csv[i].x, si = csv[i].y;
       const double a = T[i], b = U[i];
       T[i] = ci * a - si * b;
       U[i] = si * a + ci * b;
@@ -184,6 +198,7 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
   __shared__ double part[2][NW][16];
+  __shared__ double2 bcs[NW][16];  // per wave: the rotations of the current step
   __shared__ int sh_rot;
   __shared__ double sh_off;
   const JacobiShape js = jacobi_shape(N);
@@ -204,7 +219,8 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
     CoopCount cc{0, 0.0};
     double2* sweep_log = log + (size_t)sw * per_sweep;
     for (int b = blockIdx.x; b < js.nb; b += gridDim.x)
-      coop_intra_block<NW, B>(R, ld, b, sweep_log + (size_t)b * 16, js.nb * 16, tol, cc, part, buf, lane, wave);
+      coop_intra_block<NW, B>(R, ld, b, sweep_log + (size_t)b * 16, js.nb * 16, tol, cc, part, buf, lane, wave,
+                              bcs[wave]);
     grid.sync();
     for (int r = 0; r < js.nb - 1; ++r) {
       double2* round_log = sweep_log + jacobi_log_step_offset(js, js.bq - 1 + r * B);
@@ -215,7 +231,8 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
           I = J;
           J = t;
         }
-        coop_inter_pair<NW, B>(R, ld, I, J, round_log + (size_t)i * 16, nbp * 16, tol, cc, part, buf, lane, wave);
+        coop_inter_pair<NW, B>(R, ld, I, J, round_log + (size_t)i * 16, nbp * 16, tol, cc, part, buf, lane, wave,
+                               bcs[wave]);
       }
       if (r == js.nb - 2 && wave == 0) {
         // this workgroup's counts of the sweep, published before the round's grid barrier
@@ -250,7 +267,7 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     jres->sweeps = sweeps;
     jres->converged = conv;
-    jres->off = sweeps > 0 ? sh_off : 0.0;
+    jres->off = sweeps > 0 ? sqrt(sh_off) : 0.0;
   }
 }
 

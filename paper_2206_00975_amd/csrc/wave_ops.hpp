@@ -139,6 +139,15 @@ __device__ inline T* opaque_uniform(T* p) {
   return p;
 }
 
+// Orders this wave's earlier LDS writes before its later LDS reads: the LDS runs a wave's
+// instructions in issue order, so lanes of the wave see each other's writes once the compiler
+// is kept from moving the accesses across this point.  No other wave is synchronised.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Workgroup barrier that orders LDS accesses only: unlike __syncthreads() it does not wait
 // for global loads in flight, so prefetches can cross it.  Only for barriers whose producers
 // and consumers communicate through LDS.
