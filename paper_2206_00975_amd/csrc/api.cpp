@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "nsk.h"
@@ -504,19 +505,33 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
   });
   std::vector<unsigned char> hinst((size_t)count * batch_inst_bytes());
   std::vector<unsigned char> htile((size_t)B.ntiles * batch_tile_bytes());
-  std::vector<int> hrows;
   std::vector<size_t> rows_off(count);
   size_t roff = 0;
   int s_max = 0, n_max = 0;
   const int acc = dflt_acc(base);
   for (int i = 0; i < count; ++i) {
-    const nsk_problem& q = probs[i];
     rows_off[i] = roff;
-    std::vector<int64_t> r;
-    srht_rows_host(q.seed, next_pow2(q.m), q.s, r);
-    hrows.resize(roff / 4 + align_up((size_t)q.s * 4) / 4, 0);
-    for (size_t t = 0; t < r.size(); ++t) hrows[roff / 4 + t] = (int)r[t];
-    roff += align_up((size_t)q.s * 4);
+    roff += align_up((size_t)probs[i].s * 4);
+  }
+  // every instance's sampled rows, drawn on host threads (independent per instance)
+  std::vector<int> hrows(roff / 4, 0);
+  {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int nthr = (int)std::min<unsigned>(hw, (unsigned)((count + 31) / 32));
+    auto work = [&](int part) {
+      std::vector<int64_t> r;
+      for (int i = part; i < count; i += nthr) {
+        srht_rows_host(probs[i].seed, next_pow2(probs[i].m), probs[i].s, r);
+        for (size_t t = 0; t < r.size(); ++t) hrows[rows_off[i] / 4 + t] = (int)r[t];
+      }
+    };
+    std::vector<std::thread> pool;
+    for (int part = 1; part < nthr; ++part) pool.emplace_back(work, part);
+    work(0);
+    for (std::thread& th : pool) th.join();
+  }
+  for (int i = 0; i < count; ++i) {
+    const nsk_problem& q = probs[i];
     s_max = std::max<int>(s_max, (int)q.s);
     n_max = std::max<int>(n_max, (int)q.n);
     Operand op;
