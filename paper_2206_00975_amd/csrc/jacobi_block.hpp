@@ -89,13 +89,15 @@ struct JacobiCtx {
 // (the trig form of the two-sided Jacobi rotation): zeta = (b - a) / (2 g),
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t.  The pair is
 // rotated when |g| > tol sqrt(a b), tested as g^2 > tol^2 a b.  Reciprocals and reciprocal
-// square roots start from the hardware estimates and take Newton steps: one for zeta and t
-// (their rounding only tilts the angle), two for c, so that c^2 + s^2 = c^2 (1 + t^2) = 1 to
-// working precision and the rotation stays orthogonal.  No branch: every quantity is computed
+// square roots start from the hardware estimates and take two Newton steps each, which brings
+// them to working precision: c^2 + s^2 = c^2 (1 + t^2) = 1, so the rotation stays orthogonal,
+// and t solves the rotation's quadratic closely enough that the rotated pair's cosine falls
+// below the tolerance (one step for t left cosines near 1e-13 and cost an extra sweep).  No branch: every quantity is computed
 // and the result selected, so the dependency chains overlap.  When the pair is not rotated
 // (including g = 0) the result is (c, s, t) = (1, 0, 0).
 __device__ inline double rcp_nr(double x) {
   double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
   y = fma(y, fma(-x, y, 1.0), y);
   return y;
 }
@@ -113,7 +115,7 @@ __device__ inline void jacobi_params(double a, double b, double g, double tol, d
   const double zeta = (b - a) * rcp_nr(2.0 * g);
   const double az = fabs(zeta);
   const double q = fma(zeta, zeta, 1.0);
-  const double root = az > 1e150 ? az : q * rsq_nr(q, 1);     // sqrt(1 + zeta^2)
+  const double root = az > 1e150 ? az : q * rsq_nr(q, 2);     // sqrt(1 + zeta^2)
   const double r = rcp_nr(az + root);
   const double tt = zeta >= 0 ? r : -r;
   const double cc = rsq_nr(fma(tt, tt, 1.0), 2);
