@@ -19,10 +19,20 @@
 
 namespace nsk {
 
-// Per-sweep rotation counts and largest relative cosines, appended to the rotation log.
+// Per-sweep rotation counts and largest relative cosines, then the two words of the Gram
+// check (violation flag, largest squared cosine), appended to the rotation log.
 __host__ __device__ inline size_t jacobi_coop_counter_bytes(int max_sweeps) {
-  return (size_t)max_sweeps * 2 * sizeof(unsigned long long);
+  return ((size_t)max_sweeps * 2 + 2) * sizeof(unsigned long long);
 }
+
+// A sweep performs no rotation exactly when every column pair's cosine is already within the
+// tolerance: no rotation means no column changes during the sweep, so each pair is tested on
+// the columns as they stood before it.  Near convergence the largest cosine falls roughly
+// quadratically from sweep to sweep (measured on the TLS sketch: 3e-2, 5e-7, 2e-14), so after a
+// sweep whose largest cosine was at most 1e-6 the multi-workgroup kernel checks the condition
+// directly on the Gram products of R (about a tenth of a sweep's time) and stops when it
+// holds, instead of running the confirming sweep.
+constexpr double kGramCheckCos2 = 1e-12;  // largest squared cosine of a sweep that triggers it
 
 // Wave totals of the first P values of v, summed over the NW waves.  Lane l receives the
 // total of value l >> (6 - ceil_log2(P)) (zero past P).  part: LDS [2][NW][16], used in turn.
@@ -190,11 +200,115 @@ __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, in
   }
 }
 
+// True when no column pair of R has |x_p . x_q| > tol |x_p| |x_q|.  Collective over the grid
+// (two grid barriers): column norms of each workgroup's blocks go to norms_g (N words of
+// global scratch), then each workgroup takes block pairs I <= J, forms the B x B products of
+// the pair's columns (one row per lane, transposed reductions in chunks of 16, wave partials
+// summed through LDS) and tests them.  flags: two words (violation, largest squared cosine,
+// which is returned in off2).
+template <int NW, int B>
+__device__ inline bool coop_gram_clear(const double* __restrict__ R, const JacobiShape& js, int N, double tol,
+                                       double* __restrict__ norms_g, unsigned long long* flags,
+                                       double (*part)[NW][16], int& buf, int lane, int wave, double& off2) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  constexpr int SH = 6 - ceil_log2(B);
+  constexpr int NCH = (B * B + 15) / 16;
+  __shared__ double norms[512];
+  __shared__ double gp[NW][NCH * 16];
+  __shared__ unsigned long long sh_flags[2];
+  const int ld = 64 * NW;
+  const int G = gridDim.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[1] = 0;
+  }
+  for (int b = blockIdx.x; b < js.nb; b += G) {
+    const double* p = uniform_ptr(R + (size_t)b * B * ld) + 64 * wave + lane;
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const double x = p[(size_t)i * ld];
+      v[i] = x * x;
+    }
+    const double nrm = coop_reduce<B, NW>(v, lane, wave, part, buf);
+    const int pi = lane >> SH;
+    if (wave == 0 && (lane & ((1 << SH) - 1)) == 0 && pi < B && b * B + pi < N) norms_g[b * B + pi] = nrm;
+  }
+  grid.sync();
+  for (int c = threadIdx.x; c < js.nb * B; c += blockDim.x) norms[c] = c < N ? norms_g[c] : 0.0;
+  __syncthreads();
+  const int npairs = js.nb * (js.nb + 1) / 2;
+  bool bad = false;
+  double om = 0.0;
+  for (int bp = blockIdx.x; bp < npairs; bp += G) {
+    int I = 0, rem = bp;
+    while (rem >= js.nb - I) {
+      rem -= js.nb - I;
+      ++I;
+    }
+    const int J = I + rem;
+    const double* pt = uniform_ptr(R + (size_t)I * B * ld) + 64 * wave + lane;
+    const double* pu = uniform_ptr(R + (size_t)J * B * ld) + 64 * wave + lane;
+    double T[B], U[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      T[i] = pt[(size_t)i * ld];
+      U[i] = pu[(size_t)i * ld];
+    }
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      double v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int q = ch * 16 + e;
+        v[e] = q < B * B ? T[q / B] * U[q % B] : 0.0;
+      }
+      const double t = reduce_t<16>(v, lane);  // lane l: total of product ch * 16 + (l >> 2)
+      if ((lane & 3) == 0) gp[wave][ch * 16 + (lane >> 2)] = t;
+    }
+    lds_barrier();
+    if (wave == 0) {
+      for (int q = lane; q < B * B; q += 64) {
+        const int i = q / B, j = q % B;
+        if (I == J && j <= i) continue;
+        double g = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) g += gp[w][q];
+        const double ab = norms[I * B + i] * norms[J * B + j];
+        bad |= g * g > (tol * tol) * ab;
+        if (ab > 0) om = fmax(om, g * g * rcp_nr(ab));
+      }
+    }
+    lds_barrier();
+  }
+  if (wave == 0) {
+    const bool any = __any(bad);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) om = fmax(om, __shfl_xor(om, o, 64));
+    if (lane == 0) {
+      if (any) atomicOr(&flags[0], 1ull);
+      atomicMax(&flags[1], (unsigned long long)__double_as_longlong(om));
+    }
+  }
+  grid.sync();
+  if (threadIdx.x == 0) {
+    sh_flags[0] = __hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sh_flags[1] = __hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  off2 = __longlong_as_double((long long)sh_flags[1]);
+  const bool clear = sh_flags[0] == 0;
+  __syncthreads();
+  return clear;
+}
+
 // Sweeps until one performs no rotation (or max_sweeps).  Launched cooperatively with
 // nb / 2 workgroups of NW * 64 threads, NW = rows / 64.  counters: 2 * max_sweeps words.
 template <int NW, int B>
 __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max_sweeps, double2* __restrict__ log,
-                                          unsigned long long* __restrict__ counters, JacobiResult* jres) {
+                                          unsigned long long* __restrict__ counters, JacobiResult* jres,
+                                          double* __restrict__ scratch) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
   __shared__ double part[2][NW][16];
@@ -262,6 +376,15 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
     if (total == 0) {
       conv = 1;
       break;
+    }
+    if (sh_off <= kGramCheckCos2) {
+      double off2 = 0.0;
+      if (coop_gram_clear<NW, B>(R, js, N, tol, scratch, counters + 2 * max_sweeps, part, buf, lane, wave, off2)) {
+        if (threadIdx.x == 0) sh_off = off2;
+        __syncthreads();
+        conv = 1;
+        break;
+      }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -99,8 +99,9 @@ static hipError_t launch_qr_coop(SvdWork& w, hipStream_t st) {
 // Multi-workgroup Jacobi: nb / 2 workgroups of NR waves (one row per lane).
 template <int NR>
 __global__ __launch_bounds__(NR * 64) void svd_jacobi_coop_kernel(SvdWork w) {
+  // colnorm is free until the finish stage recomputes it: scratch for the Gram check
   jacobi_coop_sweeps<NR, JacobiB<NR>::value>(w.R, w.N, w.max_sweeps, w.log,
-                                             jacobi_counters(w.log, w.N, w.max_sweeps), w.jres);
+                                             jacobi_counters(w.log, w.N, w.max_sweeps), w.jres, w.colnorm);
 }
 
 template <int NR>
