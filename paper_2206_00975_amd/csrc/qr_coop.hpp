@@ -184,4 +184,224 @@ __device__ inline void qr_coop(double* __restrict__ A, int s, int N, double* __r
   }
 }
 
+// The same factorisation with a one-panel lookahead.  After panel p is published, the owner
+// of panel p + 1 applies p's reflectors to panel p + 1 only and factorises it at once; its
+// other columns receive panel p after the next grid barrier, just before panel p + 1.  So the
+// barrier of panel p + 1 waits for one panel's worth of updates and one factorisation rather
+// than for the owner's whole share of the trailing matrix.  Reflectors of two panels live in
+// LDS at a time (double buffer).  Within a factorisation the pivot entry is read from its
+// lane, and the later columns keep the reflector in registers between the dot product and
+// the update.  Needs at least two workgroups (the lookahead owner differs from the panel's).
+// LDS: qr_coop_la_lds_bytes(s, NB).
+__host__ __device__ inline size_t qr_coop_la_lds_bytes(int s, int NB) {
+  return 2 * ((size_t)NB * s * 8 + (size_t)NB * 8) + 64;
+}
+
+template <int RPL, int NB, int CPW>
+__device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* __restrict__ R, int ldr,
+                                  size_t r_elems, double* __restrict__ tau_g, unsigned char* smem) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  double* vbase = reinterpret_cast<double*>(smem);
+  // buffer b: vbase + b * (NB * s + NB): NB x s reflector rows (relative to the panel), then NB taus
+  auto vbuf = [&](int p) { return vbase + (size_t)(p & 1) * ((size_t)NB * s + NB); };
+  auto taus = [&](int p) { return vbuf(p) + (size_t)NB * s; };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int G = gridDim.x, me = blockIdx.x;
+  for (size_t e = (size_t)me * blockDim.x + threadIdx.x; e < r_elems; e += (size_t)G * blockDim.x) R[e] = 0.0;
+  const int npanels = (N + NB - 1) / NB;
+
+  auto factorise = [&](int p) {
+    const int j0 = p * NB;
+    const int nbc = N - j0 < NB ? N - j0 : NB;
+    const int rows = s - j0;
+    double* vb = vbuf(p);
+    double* tau = taus(p);
+    double col[RPL];
+    const bool holds = wave < nbc;
+    {
+      const double* a = uniform_ptr(A + (size_t)(j0 + (holds ? wave : 0)) * s + j0);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int rr = lane + 64 * i;
+        const double x = a[rr < rows ? rr : 0];
+        col[i] = holds && rr < rows ? x : 0.0;
+      }
+    }
+    for (int jj = 0; jj < nbc; ++jj) {
+      if (wave == jj) {
+        double ss = 0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          ss += rr > jj ? col[i] * col[i] : 0.0;
+        }
+        ss = wave_sum64(ss);
+        const double alpha = bcast_d(col[0], jj);  // row jj sits in lane jj, register 0
+        double t = 0, beta = alpha, scal = 0;
+        if (ss > 0) {
+          const double nrm = sqrt(alpha * alpha + ss);
+          beta = alpha >= 0 ? -nrm : nrm;
+          t = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        double* v = vb + (size_t)jj * s;
+        double* acol = A + (size_t)(j0 + jj) * s + j0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          if (rr < rows) {
+            const double vv = rr < jj ? 0.0 : rr == jj ? 1.0 : col[i] * scal;
+            v[rr] = vv;
+            if (rr > jj) acol[rr] = vv;  // the reflector, below the diagonal
+          }
+          if (rr < jj) R[(size_t)(j0 + jj) * ldr + j0 + rr] = col[i];
+        }
+        if (lane == 0) {
+          tau[jj] = t;
+          tau_g[j0 + jj] = t;
+          R[(size_t)(j0 + jj) * ldr + j0 + jj] = beta;
+        }
+      }
+      lds_barrier();
+      if (holds && wave > jj) {
+        const double* v = vb + (size_t)jj * s;
+        double vv[RPL];
+        double d = 0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          vv[i] = rr < rows ? v[rr] : 0.0;
+          d += vv[i] * col[i];
+        }
+        d = wave_sum64(d) * tau[jj];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) col[i] -= d * vv[i];
+      }
+    }
+  };
+
+  // panel p's reflectors, as its owner stored them in A and tau_g, into this workgroup's LDS;
+  // every load is issued before the first store
+  auto copy = [&](int p) {
+    const int j0 = p * NB;
+    const int nbc = N - j0 < NB ? N - j0 : NB;
+    const int rows = s - j0;
+    double* vb = vbuf(p);
+    // rows per thread: s <= 64 RPL rows over the 512 (RPL < 64) or 256 (RPL = 64) threads
+    constexpr int RR = RPL >= 64 ? RPL / 4 : RPL / 8;
+    double val[NB][RR];
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj)
+#pragma unroll
+      for (int k = 0; k < RR; ++k) {
+        const int rr = threadIdx.x + k * (int)blockDim.x;
+        const bool ok = jj < nbc && rr < rows;
+        const double x = A[(size_t)(j0 + (ok ? jj : 0)) * s + j0 + (ok ? rr : 0)];
+        val[jj][k] = rr < jj ? 0.0 : rr == jj ? 1.0 : x;
+      }
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj)
+#pragma unroll
+      for (int k = 0; k < RR; ++k) {
+        const int rr = threadIdx.x + k * (int)blockDim.x;
+        if (jj < nbc && rr < rows) vb[(size_t)jj * s + rr] = val[jj][k];
+      }
+    if (threadIdx.x < nbc) taus(p)[threadIdx.x] = tau_g[j0 + threadIdx.x];
+  };
+
+  // panel pv's reflectors (in LDS) applied, in order, to this workgroup's columns in panels
+  // qa..qb (those with q mod G == me), CPW consecutive columns per wave task
+  auto apply = [&](int pv, int qa, int qb) {
+    const int j0 = pv * NB;
+    const int nbc = N - j0 < NB ? N - j0 : NB;
+    const int rows = s - j0;
+    const double* vb = vbuf(pv);
+    const double* tau = taus(pv);
+    const int first_q = qa + ((me - qa % G) % G + G) % G;
+    const int per_panel_tasks = (NB + CPW - 1) / CPW;
+    int ntasks = 0;
+    for (int q = first_q; q <= qb; q += G) ++ntasks;
+    ntasks *= per_panel_tasks;
+    for (int task = wave; task < ntasks; task += nw) {
+      const int q = first_q + (task / per_panel_tasks) * G;
+      const int c0 = q * NB + (task % per_panel_tasks) * CPW;
+      const int cend = (q + 1) * NB < N ? (q + 1) * NB : N;
+      double cl[CPW][RPL];
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        const bool cu = c0 + u < cend;
+        const double* a = uniform_ptr(A + (size_t)(cu ? c0 + u : c0) * s + j0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          const double x = a[rr < rows ? rr : 0];
+          cl[u][i] = cu && rr < rows ? x : 0.0;
+        }
+      }
+      for (int jj = 0; jj < nbc; ++jj) {
+        const double* v = vb + (size_t)jj * s;
+        double vv[RPL];
+        double d[CPW];
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) d[u] = 0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          vv[i] = rr < rows ? v[rr] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) d[u] += vv[i] * cl[u][i];
+        }
+        const double tj = tau[jj];
+        {
+          constexpr int SH = 6 - ceil_log2(CPW);
+          double v16[16];
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) v16[u] = d[u];
+          const double tot = reduce_t<CPW>(v16, lane);
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) d[u] = bcast_d(tot, u << SH) * tj;
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+#pragma unroll
+          for (int u = 0; u < CPW; ++u) cl[u][i] -= d[u] * vv[i];
+      }
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        if (c0 + u >= cend) continue;
+        double* a = opaque_uniform(A + (size_t)(c0 + u) * s + j0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = lane + 64 * i;
+          if (rr < nbc) R[(size_t)(c0 + u) * ldr + j0 + rr] = cl[u][i];
+          else if (rr < rows) a[rr] = cl[u][i];
+        }
+      }
+    }
+  };
+
+  grid.sync();  // R zeroed everywhere before any panel writes into it
+  if (me == 0 % G) factorise(0);
+  for (int p = 0; p < npanels; ++p) {
+    grid.sync();  // panel p's reflectors are in A and tau_g
+    const int owner = p % G;
+    const int nx = p + 1;
+    if (me != owner) copy(p);
+    __syncthreads();
+    if (nx < npanels && me == nx % G) {
+      apply(p, nx, nx);  // the next panel first, then factorise it
+      __syncthreads();
+      factorise(nx);
+    } else if (me == owner && p > 0) {
+      apply(p - 1, p + 1, npanels - 1);  // deferred while this workgroup factorised panel p
+      __syncthreads();
+      apply(p, p + 1, npanels - 1);
+    } else {
+      apply(p, p + 1, npanels - 1);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace nsk

@@ -79,6 +79,23 @@ __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_coop_kernel(SvdWork w)
   }
 }
 
+// Lookahead variant (two panels of reflectors in LDS, at least two workgroups).
+template <int RPL>
+__global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_coop_la_kernel(SvdWork w) {
+  extern __shared__ unsigned char smem[];
+  constexpr int C = QrCpw<RPL>::value;
+  const JacobiShape js = jacobi_shape(w.N);
+  const int ldr = 64 * js.NR;
+  const size_t relems = (size_t)ldr * js.nb * js.B;
+  switch (qr_panel_width(w.s, blockDim.x >> 6)) {
+    case 16: qr_coop_la<RPL, 16, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    case 8: qr_coop_la<RPL, 8, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    case 4: qr_coop_la<RPL, 4, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    case 2: qr_coop_la<RPL, 2, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    default: qr_coop_la<RPL, 1, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+  }
+}
+
 // workgroups of the multi-workgroup QR: one per panel, at most 16
 static int qr_coop_groups(int s, int N, int threads) {
   const int nb = qr_panel_width(s, threads / 64);
@@ -89,11 +106,20 @@ static int qr_coop_groups(int s, int N, int threads) {
 template <int RPL>
 static hipError_t launch_qr_coop(SvdWork& w, hipStream_t st) {
   const int threads = qr_threads(RPL);
-  const size_t lds = qr_panel_lds_bytes(w.s, qr_panel_width(w.s, threads / 64));
-  if (hipError_t e = lds_attr((const void*)svd_qr_coop_kernel<RPL>, lds)) return e;
+  const int nb = qr_panel_width(w.s, threads / 64);
+  const int groups = qr_coop_groups(w.s, w.N, threads);
   void* args[] = {&w};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_qr_coop_kernel<RPL>),
-                                    dim3(qr_coop_groups(w.s, w.N, threads)), dim3(threads), args, lds, st);
+  const size_t lds_la = qr_coop_la_lds_bytes(w.s, nb);
+  // up to 16 rows per lane (s <= 1024): the variant for more rows per lane spills registers
+  if (RPL <= 16 && groups >= 2 && lds_la <= 160 * 1024) {
+    if (hipError_t e = lds_attr((const void*)svd_qr_coop_la_kernel<RPL>, lds_la)) return e;
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_qr_coop_la_kernel<RPL>), dim3(groups),
+                                      dim3(threads), args, lds_la, st);
+  }
+  const size_t lds = qr_panel_lds_bytes(w.s, nb);
+  if (hipError_t e = lds_attr((const void*)svd_qr_coop_kernel<RPL>, lds)) return e;
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_qr_coop_kernel<RPL>), dim3(groups),
+                                    dim3(threads), args, lds, st);
 }
 
 // Multi-workgroup Jacobi: nb / 2 workgroups of NR waves (one row per lane).
