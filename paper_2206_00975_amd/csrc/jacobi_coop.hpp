@@ -25,14 +25,7 @@ __host__ __device__ inline size_t jacobi_coop_counter_bytes(int max_sweeps) {
   return ((size_t)max_sweeps * 2 + 2) * sizeof(unsigned long long);
 }
 
-// A sweep performs no rotation exactly when every column pair's cosine is already within the
-// tolerance: no rotation means no column changes during the sweep, so each pair is tested on
-// the columns as they stood before it.  Near convergence the largest cosine falls roughly
-// quadratically from sweep to sweep (measured on the TLS sketch: 3e-2, 5e-7, 2e-14), so after a
-// sweep whose largest cosine was at most 1e-6 the multi-workgroup kernel checks the condition
-// directly on the Gram products of R (about a tenth of a sweep's time) and stops when it
-// holds, instead of running the confirming sweep.
-constexpr double kGramCheckCos2 = 1e-12;  // largest squared cosine of a sweep that triggers it
+
 
 // Wave totals of the first P values of v, summed over the NW waves.  Lane l receives the
 // total of value l >> (6 - ceil_log2(P)) (zero past P).  part: LDS [2][NW][16], used in turn.
