@@ -20,7 +20,9 @@
  *   errors are detected on the host before anything is enqueued.  NaN and Inf inputs are
  *   not checked: they propagate to the outputs.
  * - The realisation of S is a pure function of (kind, m, s, zeta, seed): S is regenerated
- *   from Philox4x32-10 counters wherever it is applied and is never stored.
+ *   from Philox4x32-10 counters on every call and never kept between calls.  Within a
+ *   sparse-sign sketch the draws are expanded once into a per-call table in the workspace
+ *   (20 bytes per row of A for zeta <= 8, 68 for zeta <= 32) that its column tiles share.
  */
 #ifndef NSK_H
 #define NSK_H

@@ -66,7 +66,7 @@ int plan_groups(const nsk_desc* d, int64_t m, int64_t N) {
 }
 
 struct Layout {
-  size_t rows, partial, sa, R, V, log, sigma, order, colnorm, jres, res, work, total;
+  size_t rows, draws, partial, sa, R, V, log, sigma, order, colnorm, jres, res, work, total;
 };
 
 Layout layout(int64_t m, int64_t N, const nsk_desc* d) {
@@ -76,6 +76,7 @@ Layout layout(int64_t m, int64_t N, const nsk_desc* d) {
   const bool fast = svd_fast_path((int)s, (int)N);
   size_t off = 0;
   L.rows = off;    off = align_up(off + (size_t)s * 4);
+  L.draws = off;   off = align_up(off + (d->kind == NSK_SPARSE_SIGN ? sparse_table_bytes(m, dflt_zeta(d)) : 0));
   L.partial = off; off = align_up(off + (size_t)groups * s * N * 8);
   L.sa = off;      off = align_up(off + (size_t)s * N * 8);
   L.R = off;       off = align_up(off + svd_work_R_bytes((int)s, (int)N));
@@ -203,6 +204,7 @@ SketchPlan make_plan(const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws,
   p.groups = plan_groups(d, m, N);
   p.col_tile = 0;
   p.rows = reinterpret_cast<const int*>(ws + L.rows);
+  p.draws = ws + L.draws;
   p.partial = ws + L.partial;
   return p;
 }
@@ -241,6 +243,10 @@ int run_sketch(const Operand& op, const nsk_desc* d, int64_t m, int64_t N, unsig
   prof_begin(st);
   if (d->kind == NSK_SRHT) {
     const int rc = upload_rows(d->seed, m, d->s, reinterpret_cast<int*>(ws + L.rows), st);
+    if (rc) return rc;
+  }
+  if (d->kind == NSK_SPARSE_SIGN) {
+    const int rc = dev(launch_sparse_table(p, st));
     if (rc) return rc;
   }
   prof_mark(0, st);

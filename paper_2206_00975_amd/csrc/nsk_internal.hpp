@@ -164,8 +164,13 @@ struct SketchPlan {
   int groups;         // row groups = number of partial sketches
   int col_tile;       // columns per workgroup
   const int* rows;    // SRHT: sorted sampled rows (device)
+  void* draws;        // sparse sign: per-row draw table (device, sparse_table_bytes)
   void* partial;      // groups x s x N (acc type)
 };
+
+// sparse sign: the per-call table of every row's packed draws, and the pass that writes it
+size_t sparse_table_bytes(int64_t m, int zeta);
+hipError_t launch_sparse_table(const SketchPlan& p, hipStream_t st);
 
 hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st);
 // SA (FP64, s x N) = scale * sum_g partial_g; row-major (ld_rm) and/or column-major (ld_cm)

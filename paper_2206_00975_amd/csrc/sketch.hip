@@ -32,31 +32,64 @@ static hipError_t set_lds_limit(const void* fn, size_t bytes) {
 }
 
 // ============================================================================ sparse sign
-// Workgroup (column tile of COLS columns, row group g) keeps an (s + 1) x COLS accumulator of
-// SA in LDS.  Rows are taken in chunks of kSpThreads: thread t draws the zeta (row, sign)
-// pairs of input row r0 + t into LDS, and thread (rs, col) adds its column's value of rows
-// r0 + rs + (kSpThreads / COLS) i into those zeta accumulator rows with LDS atomics.  The
-// pipeline is one chunk deep: while chunk i is accumulated, chunk i + 1's values are in
-// flight to registers and its draws are written to the other half of a double-buffered table.
+// Draws first: sparse_table_kernel expands every row's zeta (row, sign) pairs once per call
+// into a table in the workspace (ZMAX/8 16-byte words of packed 16-bit target rows, then one
+// word of sign bits per row), so the column tiles share them instead of each recomputing the
+// Philox blocks and Floyd's rule.  Slots past zeta hold s, the dump row below.
 //
-// Nothing in the loop is conditional.  Row s of the accumulator is a dump that is never
-// written out: draw slots z >= zeta and rows past the group's end point at it, and loads past
-// the end re-read the group's last row.  A branch around a load or its use would make the
-// compiler wait for the loads in flight at the branch's join (it must be correct on the path
-// that skipped them), which serialises the prefetch with the accumulation.
+// Workgroup (column tile of COLS columns, row group g) keeps an (s + 1) x COLS accumulator of
+// SA in LDS.  Rows are taken in chunks of kSpThreads: thread t stages the table entry of input
+// row r0 + t in LDS, and thread (rs, col) adds its column's value of rows r0 + rs +
+// (kSpThreads / COLS) i into those zeta accumulator rows with LDS atomics.  Row s of the
+// accumulator is never written out: the dump for draw slots past zeta and rows past the
+// group's end.  Full chunks run a one-chunk-deep pipeline with no clamp or branch in it: while
+// chunk c is accumulated, chunk c + 1's values and table entries are in flight to registers
+// (table loads first, so that staging them in LDS at the end of the step does not wait for
+// the values); the staged table is double-buffered.  The one partial chunk (m not a multiple
+// of kSpThreads) is handled after the loop with clamped loads.
 constexpr int kSpThreads = 1024;
+
+template <int ZMAX>
+__global__ __launch_bounds__(256) void sparse_table_kernel(uint64_t seed, int64_t m, int s, int zeta,
+                                                           uint4* __restrict__ rows_tab,
+                                                           uint32_t* __restrict__ neg_tab) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= m) return;
+  int rw[ZMAX];
+  uint32_t nb;
+  sparse_column<ZMAX>(seed, (uint64_t)j, s, zeta, rw, nb);
+  uint32_t pk[ZMAX / 2];
+#pragma unroll
+  for (int q = 0; q < ZMAX; q += 2) {
+    const uint32_t h0 = q < zeta ? (uint32_t)rw[q] : (uint32_t)s;
+    const uint32_t h1 = q + 1 < zeta ? (uint32_t)rw[q + 1] : (uint32_t)s;
+    pk[q / 2] = h0 | (h1 << 16);
+  }
+#pragma unroll
+  for (int u = 0; u < ZMAX / 8; ++u)
+    rows_tab[(size_t)j * (ZMAX / 8) + u] = make_uint4(pk[4 * u], pk[4 * u + 1], pk[4 * u + 2], pk[4 * u + 3]);
+  neg_tab[j] = nb;
+}
+
+// bytes of the draw table for m rows
+size_t sparse_table_bytes(int64_t m, int zeta) {
+  const int zmax = zeta <= 8 ? 8 : 32;
+  return (size_t)m * (zmax / 8) * 16 + (size_t)m * 4;
+}
 
 template <typename TIn, typename TAcc, int ZMAX, int COLS>
 __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t m, int N, int s,
-                                                            int zeta, uint64_t seed, int groups,
+                                                            int groups, const uint4* __restrict__ rows_tab,
+                                                            const uint32_t* __restrict__ neg_tab,
                                                             TAcc* __restrict__ partial) {
   static_assert(ZMAX % 8 == 0, "draw slots are stored eight to a 16-byte word");
   constexpr int RPP = kSpThreads / COLS;  // rows per pass of the workgroup
   constexpr int VPT = COLS;               // values per thread per chunk (kSpThreads / RPP)
+  constexpr int ZW = ZMAX / 8;            // 16-byte table words per row
   extern __shared__ unsigned char smem_raw[];
   TAcc* acc = reinterpret_cast<TAcc*>(smem_raw);                                  // (s + 1) x COLS
-  uint16_t* hrow = reinterpret_cast<uint16_t*>(acc + (size_t)(s + 1) * COLS);    // 2 x kSpThreads x ZMAX
-  uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + 2 * kSpThreads * ZMAX);     // 2 x kSpThreads
+  uint4* hrow = reinterpret_cast<uint4*>(acc + (size_t)(s + 1) * COLS);          // 2 x kSpThreads x ZW
+  uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + 2 * kSpThreads * ZW);       // 2 x kSpThreads
 
   const int tiles = (N + COLS - 1) / COLS;
   const int64_t item = xcd_work_item(blockIdx.x, (int64_t)tiles * groups);
@@ -78,72 +111,108 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
   const int64_t rows_per_group = ((m + groups - 1) / groups + kSpThreads - 1) / kSpThreads * kSpThreads;
   const int64_t gr0 = (int64_t)g * rows_per_group;
   const int64_t gr1 = gr0 + rows_per_group < m ? gr0 + rows_per_group : m;
-  if (gr0 >= gr1) {
-    __syncthreads();
-  } else {
-    auto draw = [&](int64_t r0, int buf) {
-      const int64_t j = r0 + t;
-      int rw[ZMAX];
-      uint32_t nb;
-      sparse_column<ZMAX>(seed, (uint64_t)j, s, zeta, rw, nb);
-      const bool in = j < gr1;
-      uint32_t pk[ZMAX / 2];
+  const int64_t nfull = gr1 > gr0 ? (gr1 - gr0) / kSpThreads : 0;
+  const uint32_t dump = (uint32_t)s | ((uint32_t)s << 16);
+
+  // the zeta atomics of every staged row of chunk buffer buf, value cur[i] for row rs + RPP i
+  auto accumulate = [&](int buf, const TIn (&cur)[VPT]) {
+    const uint4* hr = hrow + (size_t)buf * kSpThreads * ZW;
+    const uint32_t* hn = hneg + buf * kSpThreads;
 #pragma unroll
-      for (int q = 0; q < ZMAX; q += 2) {
-        const uint32_t h0 = in && q < zeta ? (uint32_t)rw[q] : (uint32_t)s;
-        const uint32_t h1 = in && q + 1 < zeta ? (uint32_t)rw[q + 1] : (uint32_t)s;
-        pk[q / 2] = h0 | (h1 << 16);
+    for (int i = 0; i < VPT; ++i) {
+      const int q = rs + RPP * i;
+      const TAcc a = (TAcc)to_f64(cur[i]);
+      const uint32_t nb = hn[q];
+      // all zeta targets of the row in 16-byte reads first, then the atomics back to back
+      // (an LDS read between two atomics would wait for the earlier atomic to finish)
+      uint4 hv[ZW];
+#pragma unroll
+      for (int u = 0; u < ZW; ++u) hv[u] = hr[q * ZW + u];
+#pragma unroll
+      for (int z = 0; z < ZMAX; ++z) {
+        const uint4 w4 = hv[z >> 3];
+        const uint32_t w = (z & 7) < 2 ? w4.x : (z & 7) < 4 ? w4.y : (z & 7) < 6 ? w4.z : w4.w;
+        const int h = (int)((w >> (16 * (z & 1))) & 0xffffu);
+        atomicAdd(&acc[h * COLS + col], ((nb >> z) & 1u) ? -a : a);
       }
-      uint4* hr = reinterpret_cast<uint4*>(hrow + ((size_t)buf * kSpThreads + t) * ZMAX);
+    }
+  };
+
+  if (nfull > 0) {
+    // chunk k's first row for this thread's values; rows rs + RPP i follow at stride RPP ld
+    const TIn* lane0 = base + (gr0 + rs) * ld;
+    const int64_t cstep = (int64_t)kSpThreads * ld, istep = (int64_t)RPP * ld;
+    auto fetch = [&](int64_t k, TIn (&v)[VPT]) {
+      const TIn* p = lane0 + k * cstep;
 #pragma unroll
-      for (int u = 0; u < ZMAX / 8; ++u) hr[u] = make_uint4(pk[4 * u], pk[4 * u + 1], pk[4 * u + 2], pk[4 * u + 3]);
-      hneg[buf * kSpThreads + t] = nb;
+      for (int i = 0; i < VPT; ++i) v[i] = p[i * istep];
     };
-    auto fetch = [&](int64_t r0, TIn (&v)[VPT]) {
+    auto table = [&](int64_t k, uint4 (&tr)[ZW], uint32_t& tn) {
+      const int64_t j = gr0 + k * kSpThreads + t;
 #pragma unroll
-      for (int i = 0; i < VPT; ++i) {
-        const int64_t r = r0 + rs + RPP * i;
-        v[i] = base[(r < gr1 ? r : gr1 - 1) * ld];
-      }
+      for (int u = 0; u < ZW; ++u) tr[u] = rows_tab[(size_t)j * ZW + u];
+      tn = neg_tab[j];
     };
-    // chunk i + 1's values load into the register set chunk i does not use (two sets taken in
-    // turn, so no copy forces an early wait on the loads in flight); the last chunk's prefetch
-    // re-reads the final row and is discarded
-    auto step = [&](int64_t r0, int buf, TIn (&cur)[VPT], TIn (&nxt)[VPT]) {
-      fetch(r0 + kSpThreads, nxt);
-      draw(r0 + kSpThreads, buf ^ 1);
-      const uint16_t* hr = hrow + (size_t)buf * kSpThreads * ZMAX;
-      const uint32_t* hn = hneg + buf * kSpThreads;
+    auto stage = [&](int buf, const uint4 (&tr)[ZW], uint32_t tn) {
 #pragma unroll
-      for (int i = 0; i < VPT; ++i) {
-        const int q = rs + RPP * i;
-        const TAcc a = (TAcc)to_f64(cur[i]);
-        const uint32_t nb = hn[q];
-        // all zeta targets of the row in 16-byte reads first, then the atomics back to back
-        // (an LDS read between two atomics would wait for the earlier atomic to finish)
-        uint4 hv[ZMAX / 8];
-#pragma unroll
-        for (int u = 0; u < ZMAX / 8; ++u) hv[u] = reinterpret_cast<const uint4*>(hr + q * ZMAX)[u];
-#pragma unroll
-        for (int z = 0; z < ZMAX; ++z) {
-          const uint4 w4 = hv[z >> 3];
-          const uint32_t w = (z & 7) < 2 ? w4.x : (z & 7) < 4 ? w4.y : (z & 7) < 6 ? w4.z : w4.w;
-          const int h = (int)((w >> (16 * (z & 1))) & 0xffffu);
-          atomicAdd(&acc[h * COLS + col], ((nb >> z) & 1u) ? -a : a);
-        }
-      }
+      for (int u = 0; u < ZW; ++u) hrow[((size_t)buf * kSpThreads + t) * ZW + u] = tr[u];
+      hneg[buf * kSpThreads + t] = tn;
+    };
+    // chunk k + 1's values load into the register set chunk k does not use (two sets taken in
+    // turn); after the last full chunk the prefetch re-reads it and is discarded
+    auto step = [&](int64_t k, int buf, const TIn (&cur)[VPT], TIn (&nxt)[VPT]) {
+      const int64_t kn = k + 1 < nfull ? k + 1 : k;
+      uint4 tr[ZW];
+      uint32_t tn;
+      table(kn, tr, tn);
+      __builtin_amdgcn_sched_barrier(0);  // table loads issue before the value loads
+      fetch(kn, nxt);
+      accumulate(buf, cur);
+      stage(buf ^ 1, tr, tn);
       lds_barrier();
     };
-
     TIn va[VPT], vb[VPT];
-    fetch(gr0, va);
-    draw(gr0, 0);
+    {
+      uint4 tr[ZW];
+      uint32_t tn;
+      table(0, tr, tn);
+      fetch(0, va);
+      stage(0, tr, tn);
+    }
     lds_barrier();
-    for (int64_t r0 = gr0; r0 < gr1; r0 += 2 * kSpThreads) {
-      step(r0, 0, va, vb);
-      if (r0 + kSpThreads < gr1) step(r0 + kSpThreads, 1, vb, va);
+    for (int64_t k = 0; k < nfull; k += 2) {
+      step(k, 0, va, vb);
+      if (k + 1 < nfull) step(k + 1, 1, vb, va);
     }
   }
+  if (gr0 + nfull * kSpThreads < gr1) {
+    // the partial last chunk of the last group: rows past gr1 read row gr1 - 1 and add into the
+    // dump row
+    const int64_t r0 = gr0 + nfull * kSpThreads;
+    const int64_t j = r0 + t;
+    const bool in = j < gr1;
+    const int64_t jc = in ? j : gr1 - 1;
+    uint4 tr[ZW];
+#pragma unroll
+    for (int u = 0; u < ZW; ++u) {
+      const uint4 x = rows_tab[(size_t)jc * ZW + u];
+      tr[u] = in ? x : make_uint4(dump, dump, dump, dump);
+    }
+    const uint32_t tn = neg_tab[jc];
+#pragma unroll
+    for (int u = 0; u < ZW; ++u) hrow[(size_t)t * ZW + u] = tr[u];
+    hneg[t] = tn;
+    TIn v[VPT];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int64_t r = r0 + rs + RPP * i;
+      v[i] = base[(r < gr1 ? r : gr1 - 1) * ld];
+    }
+    lds_barrier();
+    accumulate(0, v);
+    lds_barrier();
+  }
+  __syncthreads();
   TAcc* out = partial + (size_t)g * s * N;
   for (int i = t; i < s * COLS; i += kSpThreads) {
     const int row = i / COLS, cc = tile * COLS + (i % COLS);
@@ -304,25 +373,31 @@ static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStrea
   return srht_cols(p.N, p.s) == 8 ? srht_dispatch_cols<TIn, TAcc, 8>(op, p, st) : srht_dispatch_cols<TIn, TAcc, 16>(op, p, st);
 }
 
-size_t sparse_lds_bytes(int s, int zeta, int acc) {
+static size_t sparse_lds_bytes_cols(int s, int zeta, int acc, int cols) {
   const int zmax = zeta <= 8 ? 8 : 32;
-  return (size_t)(s + 1) * sparse_cols(s, zeta, acc) * (acc == NSK_F64 ? 8 : 4) +
-         (size_t)2 * kSpThreads * zmax * 2 + (size_t)2 * kSpThreads * 4;
+  return (size_t)(s + 1) * cols * (acc == NSK_F64 ? 8 : 4) + (size_t)2 * kSpThreads * zmax * 2 +
+         (size_t)2 * kSpThreads * 4;
 }
+
+size_t sparse_lds_bytes(int s, int zeta, int acc) { return sparse_lds_bytes_cols(s, zeta, acc, sparse_cols(s, zeta, acc)); }
 
 template <typename TIn, typename TAcc>
 static hipError_t sparse_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
   const int acc = sizeof(TAcc) == 8 ? NSK_F64 : NSK_F32;
-  const int cols = sparse_cols(p.s, p.zeta, acc);
+  // FP64 values take twice the registers: 16-column tiles (16 values a thread, two sets)
+  // would spill, so FP64 input uses at most 8 columns
+  int cols = sparse_cols(p.s, p.zeta, acc);
+  if (sizeof(TIn) == 8 && cols > 8) cols = 8;
   dim3 grid((unsigned)xcd_grid((int64_t)((p.N + cols - 1) / cols) * p.groups));
   const int zmax = p.zeta <= 8 ? 8 : 32;
-  const size_t lds = sparse_lds_bytes(p.s, p.zeta, acc);
+  const size_t lds = sparse_lds_bytes_cols(p.s, p.zeta, acc, cols);
   TAcc* part = static_cast<TAcc*>(p.partial);
+  const uint4* rt = static_cast<const uint4*>(p.draws);
+  const uint32_t* nt = reinterpret_cast<const uint32_t*>(rt + (size_t)p.m * (zmax / 8));
 #define NSK_SPARSE(Z, C)                                                                               \
   {                                                                                                    \
     if (hipError_t e = set_lds_limit((const void*)sparse_kernel<TIn, TAcc, Z, C>, lds)) return e;      \
-    sparse_kernel<TIn, TAcc, Z, C><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.zeta, p.seed,   \
-                                                                   p.groups, part);                     \
+    sparse_kernel<TIn, TAcc, Z, C><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.groups, rt, nt, part); \
   }
   if (zmax == 8) {
     if (cols == 16) NSK_SPARSE(8, 16)
@@ -334,6 +409,20 @@ static hipError_t sparse_dispatch(const Operand& op, const SketchPlan& p, hipStr
     else NSK_SPARSE(32, 4)
   }
 #undef NSK_SPARSE
+  return hipGetLastError();
+}
+
+hipError_t launch_sparse_table(const SketchPlan& p, hipStream_t st) {
+  if (p.m == 0) return hipSuccess;
+  uint4* rt = static_cast<uint4*>(p.draws);
+  const unsigned grid = (unsigned)((p.m + 255) / 256);
+  if (p.zeta <= 8) {
+    sparse_table_kernel<8><<<grid, 256, 0, st>>>(p.seed, p.m, p.s, p.zeta, rt,
+                                                  reinterpret_cast<uint32_t*>(rt + (size_t)p.m));
+  } else {
+    sparse_table_kernel<32><<<grid, 256, 0, st>>>(p.seed, p.m, p.s, p.zeta, rt,
+                                                   reinterpret_cast<uint32_t*>(rt + (size_t)p.m * 4));
+  }
   return hipGetLastError();
 }
 
