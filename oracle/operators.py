@@ -12,10 +12,19 @@ Sketch kinds (Section 2):
 * ``gauss``  -- ``S = G_hat / sqrt(s)`` with ``G_hat`` the i.i.d. N(0,1) matrix G of Section 2
   rounded to the operand format (bf16 or e4m3); rounding happens before use, so
   ``G_hat`` itself is the sketch (FP64 holds bf16/e4m3 values exactly).
+* ``srdct``  -- the SRFT of Section 2 with the orthonormal DCT-II as trig transform, the
+  choice Section 4 makes for real data: ``S = sqrt(m_p / s) R C D`` on ``A`` zero-padded to
+  ``m_p = max(1024, 2**ceil(log2 m))`` rows, with the same ``D`` and the same row sampler as
+  the Hadamard kind (rows drawn from ``[0, m_p)``).  ``C[k, j] = c_k cos(pi k (2j+1) / (2 m_p))``
+  with ``c_0 = sqrt(1/m_p)`` and ``c_k = sqrt(2/m_p)`` otherwise, so entry ``(i, j)`` of S is
+  ``d_j w_i cos(pi r_i (2j+1) / (2 m_p))`` with ``w_i = sqrt(1/s)`` for ``r_i = 0`` and
+  ``sqrt(2/s)`` otherwise.  The cosine's argument is reduced exactly, in integers, modulo one
+  period before the cosine is taken.
 
-Pinned by: the special case ``s = m = m_p`` where the SRHT is orthogonal (SVD of ``SA``
-equals SVD of ``A``), unit column norms, ``S S^T`` structure, and the Gaussian embedding
-envelope of Theorem 2.1.
+Pinned by: the special case ``s = m = m_p`` where the SRHT and the DCT kind are orthogonal
+(SVD of ``SA`` equals SVD of ``A``), unit column norms, ``S S^T`` structure, the DCT kind
+against SciPy's orthonormal DCT-II of the signed, padded ``A`` (a library transform), and
+the Gaussian embedding envelope of Theorem 2.1.
 """
 from __future__ import annotations
 
@@ -41,6 +50,25 @@ def srht_columns(seed: int, m: int, s: int, j0: int, j1: int, rows=None, d=None)
     return had * d[j0:j1].astype(np.float64)[None, :] / math.sqrt(s)
 
 
+def dct_pool(m: int) -> int:
+    """Padded length ``m_p`` of the DCT kind: the next power of two, and at least 1024."""
+    return max(1024, draws.next_pow2(m))
+
+
+def srdct_columns(seed: int, m: int, s: int, j0: int, j1: int, rows=None, d=None) -> np.ndarray:
+    """Columns ``j0:j1`` of the subsampled randomized DCT-II sketching matrix."""
+    m_p = dct_pool(m)
+    if rows is None:
+        rows = draws.srht_rows(seed, m_p, s)
+    if d is None:
+        d = draws.signs(seed, m)
+    j = np.arange(j0, j1, dtype=np.int64)
+    num = (rows[:, None] * (2 * j[None, :] + 1)) % (4 * m_p)   # angle = pi num / (2 m_p)
+    cosv = np.cos(np.pi * num.astype(np.float64) / (2.0 * m_p))
+    w = np.where(rows == 0, math.sqrt(1.0 / s), math.sqrt(2.0 / s))
+    return cosv * w[:, None] * d[j0:j1].astype(np.float64)[None, :]
+
+
 def sparse_matrix(seed: int, m: int, s: int, zeta: int) -> sp.csc_matrix:
     """Sparse-sign sketching matrix as a SciPy CSC matrix (s x m)."""
     rows, sgn = draws.sparse(seed, m, s, zeta)
@@ -59,6 +87,8 @@ def explicit(kind: str, seed: int, m: int, s: int, zeta: int = 8, gauss_dtype: s
     """The whole S as a dense FP64 array (small cases only)."""
     if kind == "srht":
         return srht_columns(seed, m, s, 0, m)
+    if kind == "srdct":
+        return srdct_columns(seed, m, s, 0, m)
     if kind == "sparse":
         return sparse_matrix(seed, m, s, zeta).toarray()
     if kind == "gauss":
@@ -81,10 +111,15 @@ def sketch(a: np.ndarray, kind: str, s: int, seed: int, zeta: int = 8,
     if kind == "srht":
         rows = draws.srht_rows(seed, draws.next_pow2(m), s)
         d = draws.signs(seed, m)
+    if kind == "srdct":
+        rows = draws.srht_rows(seed, dct_pool(m), s)
+        d = draws.signs(seed, m)
     for j0 in range(0, m, block):
         j1 = min(m, j0 + block)
         if kind == "srht":
             cols = srht_columns(seed, m, s, j0, j1, rows=rows, d=d)
+        elif kind == "srdct":
+            cols = srdct_columns(seed, m, s, j0, j1, rows=rows, d=d)
         elif kind == "gauss":
             cols = gaussian_columns(seed, s, j0, j1, gauss_dtype)
         else:

@@ -33,6 +33,35 @@ def test_srht_entries_match_hadamard_library():
     assert np.array_equal(S2, H[r2][:, :m2] * draws.signs(seed, m2)[None, :] / math.sqrt(6))
 
 
+@pytest.mark.parametrize("m,s", [(13, 6), (1000, 100), (3000, 256), (2048, 2048)])
+def test_srdct_matches_scipy_orthonormal_dct(m, s):
+    """The DCT kind is sqrt(m_p/s) times rows R of SciPy's orthonormal DCT-II of the signed,
+    zero-padded A (m_p >= 1024; with s = m_p every row, including row 0, is taken)."""
+    from scipy.fft import dct
+    seed = 5
+    m_p = max(1024, draws.next_pow2(m))
+    a = np.random.default_rng(m).standard_normal((m, 6))
+    x = np.zeros((m_p, 6))
+    x[:m] = draws.signs(seed, m)[:, None] * a
+    ref = math.sqrt(m_p / s) * dct(x, type=2, norm="ortho", axis=0)[draws.srht_rows(seed, m_p, s)]
+    got = operators.sketch(a, "srdct", s, seed, block=700)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    if s == m_p:
+        assert 0 in draws.srht_rows(seed, m_p, s)
+
+
+def test_srdct_full_size_is_orthogonal_and_reduces_to_lapack_svd():
+    m = 1024
+    S = operators.explicit("srdct", 4, m, m)
+    assert np.abs(S @ S.T - np.eye(m)).max() < 1e-13
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((m, 20)) * np.logspace(0, -3, 20)[None, :]
+    vk, sk, sa, sig, v, _ = method.trailing_rsv(a, 2, "srdct", m, 8, return_all=True)
+    w, sw, full = metrics.trailing_exact(a, 2)
+    assert np.abs(sig - full).max() < 1e-13 * full[0]
+    assert metrics.sin_theta(w, vk) < 1e-13 * full[0] / (full[-3] - full[-2])
+
+
 @pytest.mark.parametrize("kind", ["srht", "sparse", "gauss"])
 def test_unit_column_norms_and_blocking(kind):
     m, s = 3000, 64
@@ -136,7 +165,7 @@ def test_planted_null_vector_plain_workload():
     assert sk[0] <= 1e-14 * sigma[0]
 
 
-@pytest.mark.parametrize("kind", ["srht", "sparse", "gauss"])
+@pytest.mark.parametrize("kind", ["srht", "sparse", "gauss", "srdct"])
 def test_planted_null_space_dimension_three(kind):
     rng = np.random.default_rng(8)
     n, k = 30, 3
@@ -149,7 +178,7 @@ def test_planted_null_space_dimension_three(kind):
     assert np.abs(sk).max() < 1e-13
 
 
-@pytest.mark.parametrize("kind", ["srht", "sparse", "gauss"])
+@pytest.mark.parametrize("kind", ["srht", "sparse", "gauss", "srdct"])
 def test_residual_ratio_below_ostrowski_bound(kind):
     """Proof of Theorem 2.3: rho <= sigma_max(S U_A) / sigma_min(S U_A) for the realised S."""
     M, _ = W.tls_matrix(m=3000, n=40, seed=4, dtype=np.float64)
