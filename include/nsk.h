@@ -22,7 +22,9 @@
  * - The realisation of S is a pure function of (kind, m, s, zeta, seed): S is regenerated
  *   from Philox4x32-10 counters on every call and never kept between calls.  Within a
  *   sparse-sign sketch the draws are expanded once into a per-call table in the workspace
- *   (20 bytes per row of A for zeta <= 8, 68 for zeta <= 32) that its column tiles share.
+ *   (20 bytes per row of A for zeta <= 8, 68 for zeta <= 32) that its column tiles share;
+ *   the DCT-II kind does the same with the signs of D (m_p / 8 bytes) and two rotations
+ *   per sampled row (32 bytes each).
  */
 #ifndef NSK_H
 #define NSK_H
@@ -51,8 +53,13 @@ typedef enum nsk_kind {
                             m_p = 2^ceil(log2 m) rows; entries +-1/sqrt(s)                  */
   NSK_SPARSE_SIGN = 1,   /* zeta distinct nonzeros +-1/sqrt(zeta) per column of S
                             (the CountSketch family mentioned in Section 2)                 */
-  NSK_GAUSSIAN = 2       /* S = G_hat/sqrt(s), G i.i.d. N(0,1) (Section 2) rounded to the
+  NSK_GAUSSIAN = 2,      /* S = G_hat/sqrt(s), G i.i.d. N(0,1) (Section 2) rounded to the
                             operand format of A (bf16 or e4m3) and applied on MFMA          */
+  NSK_SRDCT = 3          /* subsampled randomized DCT-II: the SRFT of Section 2 with the
+                            orthonormal DCT-II C of length m_p = max(1024, 2^ceil(log2 m)) as
+                            trig transform (the real transform of Section 4's experiments),
+                            S = sqrt(m_p/s) R C D on A zero-padded to m_p rows, with the
+                            NSK_SRHT kind's D and row sample R (rows drawn from [0, m_p))   */
 } nsk_kind;
 
 typedef enum nsk_dtype {
@@ -68,8 +75,8 @@ typedef struct nsk_desc {
                           0 selects 8                                                       */
   int64_t s;           /* sketch size; N < s <= m (Algorithm 1 requires s > n; s <= m)      */
   uint64_t seed;       /* Philox key of the realisation                                     */
-  int32_t acc;         /* NSK_SRHT / NSK_SPARSE_SIGN arithmetic: NSK_F64 (default, FP32 or
-                          FP64 loads with FP64 accumulation) or NSK_F32 (plain FP32)        */
+  int32_t acc;         /* NSK_SRHT / NSK_SRDCT / NSK_SPARSE_SIGN arithmetic: NSK_F64 (default,
+                          FP32 or FP64 loads with FP64 accumulation) or NSK_F32 (plain FP32) */
   int32_t max_sweeps;  /* Jacobi sweep cap, 0 selects 30                                     */
   int32_t row_groups;  /* number of row partitions of the sketch (partial sums); 0 = tuned */
   int32_t flags;       /* NSK_FLAG_*                                                         */
@@ -107,12 +114,13 @@ size_t nsk_workspace_bytes(int64_t m, int64_t N, int64_t k, const nsk_desc* d);
 /*
  * Line 2 of Algorithm 1: SA = S A.
  * blocks/nblocks (host array, 1..4 blocks): the m x N operand, N = sum of block columns.
- *   SRHT and sparse sign take NSK_F32 or NSK_F64 blocks; Gaussian takes NSK_BF16 or
- *   NSK_F8E4M3 blocks (all blocks of one dtype).
+ *   SRHT, DCT-II and sparse sign take NSK_F32 or NSK_F64 blocks; Gaussian takes NSK_BF16
+ *   or NSK_F8E4M3 blocks (all blocks of one dtype).
  * SA (device): s x N row-major FP64 output with row stride ldsa >= N.
  * Errors: NSK_EINVAL if m < N, s <= N, s > m, a block has cols < 1 or ld < cols, nblocks
- *   outside 1..4, zeta outside 1..min(s,32); NSK_EUNSUPPORTED for other dtype/kind pairs;
- *   NSK_EWORKSPACE if ws_bytes < nsk_workspace_bytes(m, N, 1, d).
+ *   outside 1..4, zeta outside 1..min(s,32); NSK_EUNSUPPORTED for other dtype/kind pairs
+ *   and for s > 2048 with NSK_SRHT or NSK_SRDCT; NSK_EWORKSPACE if
+ *   ws_bytes < nsk_workspace_bytes(m, N, 1, d).
  */
 int nsk_sketch(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_desc* d,
                double* SA, int64_t ldsa, void* ws, size_t ws_bytes, void* stream);
@@ -147,8 +155,9 @@ int nsk_residual(const nsk_operand* blocks, int32_t nblocks, int64_t m, const do
  * workgroup takes sketch tiles from a longest-first queue; the workgroup that completes
  * an instance's last tile reduces its partial sketches and runs its QR + Jacobi.
  * probs (host array): per-instance operand (single block), sizes, sketch size, seed, k
- *   and device output pointers.  base: kind (NSK_SRHT or NSK_SPARSE_SIGN), zeta, acc,
- *   max_sweeps; its s and seed are ignored.  Tile sizes come from the autotuner.
+ *   and device output pointers.  base: kind (NSK_SRHT; other kinds return
+ *   NSK_EUNSUPPORTED), acc, max_sweeps; its s and seed are ignored.  Tile sizes come from the
+ *   autotuner.
  */
 typedef struct nsk_problem {
   const void* A;        /* device, row-major m x n, NSK_F32 or NSK_F64                     */
@@ -207,7 +216,7 @@ int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const n
  * regenerated from the seed, the gradient is the rank-2 matrix p w^T + q v^T:
  * dA (device, m x n, row stride ldda >= n) = its first n columns, db (device, m) the last.
  * out_dtype: NSK_F32 or NSK_F64 for dA and db.  Built for NSK_SPARSE_SIGN and NSK_SRHT;
- * NSK_GAUSSIAN returns NSK_EUNSUPPORTED.  A degenerate gap (sigma_N = sigma_j) gives
+ * NSK_GAUSSIAN and NSK_SRDCT return NSK_EUNSUPPORTED.  A degenerate gap (sigma_N = sigma_j) gives
  * non-finite output: the TLS solution is then not differentiable.
  */
 int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state, const double* gx,

@@ -45,7 +45,7 @@ int dflt_sweeps(const nsk_desc* d) { return d->max_sweeps ? d->max_sweeps : 30; 
 int dflt_acc(const nsk_desc* d) { return d->acc == NSK_F32 ? NSK_F32 : NSK_F64; }
 
 // Row groups (number of partial sketches) for a single-instance sketch.
-int plan_groups(const nsk_desc* d, int64_t m, int64_t N) {
+int plan_groups(const nsk_desc* d, int64_t m, int64_t N, int dtype) {
   if (d->row_groups > 0) return d->row_groups;
   if (d->kind == NSK_SRHT) {
     // about two workgroups per CU in total (a 16-column tile fills most of a CU's LDS)
@@ -54,6 +54,13 @@ int plan_groups(const nsk_desc* d, int64_t m, int64_t N) {
     const int64_t ct = (N + cols - 1) / cols, nb = (m + 1023) / 1024;
     const int64_t target = cols == 16 ? 512 : 1024;
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, target / ct));
+  }
+  if (d->kind == NSK_SRDCT) {
+    // one or two workgroups per CU, as the LDS allows
+    const int cols = srdct_cols((int)N, (int)d->s, dflt_acc(d), dtype);
+    const int64_t ct = (N + cols - 1) / cols, nb = srdct_pool(m) / 1024;
+    const int64_t per_cu = srdct_lds_bytes((int)N, (int)d->s, dflt_acc(d), dtype) <= 80 * 1024 ? 2 : 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256 * per_cu / ct));
   }
   if (d->kind == NSK_SPARSE_SIGN) {
     // one workgroup per CU (the accumulator fills most of the LDS): about 256 workgroups
@@ -72,11 +79,15 @@ struct Layout {
 Layout layout(int64_t m, int64_t N, const nsk_desc* d) {
   Layout L{};
   const int64_t s = d->s;
-  const int groups = plan_groups(d, m, N);
+  // the workspace query knows no operand dtype: room for the larger partial count
+  const int groups = std::max(plan_groups(d, m, N, NSK_F32), plan_groups(d, m, N, NSK_F64));
   const bool fast = svd_fast_path((int)s, (int)N);
   size_t off = 0;
   L.rows = off;    off = align_up(off + (size_t)s * 4);
-  L.draws = off;   off = align_up(off + (d->kind == NSK_SPARSE_SIGN ? sparse_table_bytes(m, dflt_zeta(d)) : 0));
+  const size_t draws = d->kind == NSK_SPARSE_SIGN ? sparse_table_bytes(m, dflt_zeta(d))
+                     : d->kind == NSK_SRDCT     ? srdct_table_bytes(m, (int)d->s)
+                                                : 0;
+  L.draws = off;   off = align_up(off + draws);
   L.partial = off; off = align_up(off + (size_t)groups * s * N * 8);
   L.sa = off;      off = align_up(off + (size_t)s * N * 8);
   L.R = off;       off = align_up(off + svd_work_R_bytes((int)s, (int)N));
@@ -111,13 +122,13 @@ SvdPlan svd_plan(const nsk_desc* d, int64_t N, unsigned char* w, const Layout& L
 
 int check_desc(const nsk_desc* d, int64_t m, int64_t N) {
   if (!d) return NSK_EINVAL;
-  if (d->kind < NSK_SRHT || d->kind > NSK_GAUSSIAN) return NSK_EINVAL;
+  if (d->kind < NSK_SRHT || d->kind > NSK_SRDCT) return NSK_EINVAL;
   if (m < N || N < 1 || d->s <= N || d->s > m) return NSK_EINVAL;
   if (d->kind == NSK_SPARSE_SIGN) {
     const int z = dflt_zeta(d);
     if (z < 1 || z > 32 || z > d->s || d->s > 65535) return NSK_EINVAL;
   }
-  if (d->kind == NSK_SRHT && d->s > 2048) return NSK_EUNSUPPORTED;
+  if ((d->kind == NSK_SRHT || d->kind == NSK_SRDCT) && d->s > 2048) return NSK_EUNSUPPORTED;
   if (d->kind == NSK_SPARSE_SIGN && sparse_lds_bytes((int)d->s, dflt_zeta(d), dflt_acc(d)) > 160 * 1024)
     return NSK_EUNSUPPORTED;
   if (d->kind == NSK_GAUSSIAN && gauss_tiles_per_wave((int)d->s, (int)N) > 48) return NSK_EUNSUPPORTED;
@@ -181,9 +192,9 @@ void srht_rows_host(uint64_t seed, int64_t pool, int64_t s, std::vector<int64_t>
   std::sort(out.begin(), out.end());
 }
 
-int upload_rows(uint64_t seed, int64_t m, int64_t s, int* dst, hipStream_t st) {
+int upload_rows(uint64_t seed, int64_t pool, int64_t s, int* dst, hipStream_t st) {
   std::vector<int64_t> r;
-  srht_rows_host(seed, next_pow2(m), s, r);
+  srht_rows_host(seed, pool, s, r);
   std::vector<int> r32(r.begin(), r.end());
   if (hipMemcpyAsync(dst, r32.data(), r32.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
     return NSK_EDEVICE;
@@ -192,7 +203,7 @@ int upload_rows(uint64_t seed, int64_t m, int64_t s, int* dst, hipStream_t st) {
   return NSK_OK;
 }
 
-SketchPlan make_plan(const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws, const Layout& L) {
+SketchPlan make_plan(const nsk_desc* d, int64_t m, int64_t N, int dtype, unsigned char* ws, const Layout& L) {
   SketchPlan p{};
   p.kind = d->kind;
   p.m = m;
@@ -201,7 +212,7 @@ SketchPlan make_plan(const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws,
   p.zeta = dflt_zeta(d);
   p.seed = d->seed;
   p.acc = dflt_acc(d);
-  p.groups = plan_groups(d, m, N);
+  p.groups = plan_groups(d, m, N, dtype);
   p.col_tile = 0;
   p.rows = reinterpret_cast<const int*>(ws + L.rows);
   p.draws = ws + L.draws;
@@ -239,10 +250,15 @@ namespace {
 // Sketch + reduce; SA written column-major into the workspace and optionally row-major out.
 int run_sketch(const Operand& op, const nsk_desc* d, int64_t m, int64_t N, unsigned char* ws, const Layout& L,
                double* sa_rm, int64_t ld_rm, hipStream_t st, SketchPlan& p) {
-  p = make_plan(d, m, N, ws, L);
+  p = make_plan(d, m, N, op.dtype, ws, L);
   prof_begin(st);
-  if (d->kind == NSK_SRHT) {
-    const int rc = upload_rows(d->seed, m, d->s, reinterpret_cast<int*>(ws + L.rows), st);
+  if (d->kind == NSK_SRHT || d->kind == NSK_SRDCT) {
+    const int64_t pool = d->kind == NSK_SRHT ? next_pow2(m) : srdct_pool(m);
+    const int rc = upload_rows(d->seed, pool, d->s, reinterpret_cast<int*>(ws + L.rows), st);
+    if (rc) return rc;
+  }
+  if (d->kind == NSK_SRDCT) {
+    const int rc = dev(launch_srdct_signs(p, st));
     if (rc) return rc;
   }
   if (d->kind == NSK_SPARSE_SIGN) {
@@ -413,7 +429,7 @@ int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state,
   const int64_t N = n + 1;
   int rc = check_desc(d, m, N);
   if (rc) return rc;
-  if (d->kind == NSK_GAUSSIAN || !svd_fast_path((int)d->s, (int)N)) return NSK_EUNSUPPORTED;
+  if (d->kind == NSK_GAUSSIAN || d->kind == NSK_SRDCT || !svd_fast_path((int)d->s, (int)N)) return NSK_EUNSUPPORTED;
   if (!state || !gx || !dA || !db || !ws || ldda < n) return NSK_EINVAL;
   if (out_dtype != NSK_F32 && out_dtype != NSK_F64) return NSK_EINVAL;
   const Layout L = layout(m, N, d);
@@ -423,8 +439,9 @@ int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state,
   const unsigned char* S = static_cast<const unsigned char*>(state);
   size_t o[9];
   tls_state_layout(n, d->s, dflt_sweeps(d), o);
-  SketchPlan p = make_plan(d, m, N, w, L);
-  if (d->kind == NSK_SRHT && (rc = upload_rows(d->seed, m, d->s, reinterpret_cast<int*>(w + L.rows), st))) return rc;
+  SketchPlan p = make_plan(d, m, N, NSK_F64, w, L);
+  if (d->kind == NSK_SRHT && (rc = upload_rows(d->seed, next_pow2(m), d->s, reinterpret_cast<int*>(w + L.rows), st)))
+    return rc;
   TlsBack tb;
   tb.sa_rm = reinterpret_cast<const double*>(S + o[0]);
   tb.colnorm = reinterpret_cast<const double*>(S + o[1]);

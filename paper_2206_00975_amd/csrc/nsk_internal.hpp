@@ -103,6 +103,9 @@ __host__ __device__ inline int64_t next_pow2(int64_t m) {
   return p;
 }
 
+// Padded length of the DCT-II kind: a power of two holding at least one 1024-row block.
+__host__ __device__ inline int64_t srdct_pool(int64_t m) { return m <= 1024 ? 1024 : next_pow2(m); }
+
 // ---------------------------------------------------------------------------------------
 // Operand: up to four row-major column blocks of one element type.
 // ---------------------------------------------------------------------------------------
@@ -163,14 +166,22 @@ struct SketchPlan {
   int acc;            // NSK_F64 or NSK_F32
   int groups;         // row groups = number of partial sketches
   int col_tile;       // columns per workgroup
-  const int* rows;    // SRHT: sorted sampled rows (device)
-  void* draws;        // sparse sign: per-row draw table (device, sparse_table_bytes)
+  const int* rows;    // SRHT, DCT-II: sorted sampled rows (device)
+  void* draws;        // sparse sign: per-row draw table (sparse_table_bytes); DCT-II: sign
+                      // table (srdct_table_bytes); device
   void* partial;      // groups x s x N (acc type)
 };
 
 // sparse sign: the per-call table of every row's packed draws, and the pass that writes it
 size_t sparse_table_bytes(int64_t m, int zeta);
 hipError_t launch_sparse_table(const SketchPlan& p, hipStream_t st);
+
+// DCT-II: columns per tile (16 or 8), LDS bytes, the sign table and its pass, the sketch
+int srdct_cols(int N, int s, int acc, int dtype);
+size_t srdct_lds_bytes(int N, int s, int acc, int dtype);
+size_t srdct_table_bytes(int64_t m, int s);
+hipError_t launch_srdct_signs(const SketchPlan& p, hipStream_t st);
+hipError_t launch_srdct(const Operand& op, const SketchPlan& p, hipStream_t st);
 
 hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st);
 // SA (FP64, s x N) = scale * sum_g partial_g; row-major (ld_rm) and/or column-major (ld_cm)

@@ -477,6 +477,7 @@ hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st)
       return p.acc == NSK_F64 ? sparse_dispatch<double, double>(op, p, st) : sparse_dispatch<double, float>(op, p, st);
     return p.acc == NSK_F64 ? sparse_dispatch<float, double>(op, p, st) : sparse_dispatch<float, float>(op, p, st);
   }
+  if (p.kind == NSK_SRDCT) return launch_srdct(op, p, st);
   return gauss_dispatch(op, p, st);
 }
 
@@ -508,6 +509,9 @@ hipError_t launch_reduce(const Operand& op, const SketchPlan& p, double* sa_rm, 
     else f64part = p.acc == NSK_F64;
   } else if (p.kind == NSK_SPARSE_SIGN) {
     scale = 1.0 / sqrt((double)p.zeta);
+    f64part = p.acc == NSK_F64;
+  } else if (p.kind == NSK_SRDCT) {
+    scale = 1.0 / sqrt((double)p.s);
     f64part = p.acc == NSK_F64;
   } else {
     scale = 1.0 / sqrt((double)p.s);

@@ -90,6 +90,38 @@ def test_srht_sketch_parity(lib, name, m, n, s, dt):
     assert rel(SA32, ref) < 1e-4
 
 
+SRDCT_CASES = [
+    ("tiny_m", 40, 9, 16, np.float64),            # m_p = 1024: one block, 984 padding rows
+    ("padded", 1000, 13, 100, np.float32),
+    ("ragged", 5003, 37, 150, np.float32),        # 8 blocks
+    ("multi_block", 70_000, 21, 300, np.float32),  # 128 blocks
+    ("wide", 9000, 129, 1100, np.float64),        # s > 1024: 64 sampled rows a thread
+    ("tls_shape", 20_000, 201, 804, np.float32),  # the TLS workload's N and s
+]
+
+
+@pytest.mark.parametrize("name,m,n,s,dt", SRDCT_CASES)
+def test_srdct_sketch_parity(lib, name, m, n, s, dt):
+    a = np.random.default_rng(len(name) + m).standard_normal((m, n)).astype(dt)
+    SA = lib.sketch(t(a), "srdct", s, 41).cpu().numpy()
+    ref = operators.sketch(a.astype(np.float64), "srdct", s, 41)
+    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    SA32 = lib.sketch(t(a), "srdct", s, 41, acc="f32").cpu().numpy()
+    assert rel(SA32, ref) < 1e-4, rel(SA32, ref)
+
+
+def test_srdct_one_workgroup_per_column_tile(lib):
+    """One row group: a workgroup runs all 128 blocks, its per-sample rotation recurrence taken
+    exactly every 32 blocks."""
+    m, n, s = 131_000, 19, 256
+    a = np.random.default_rng(5).standard_normal((m, n)).astype(np.float32)
+    ref = operators.sketch(a.astype(np.float64), "srdct", s, 9)
+    SA = lib.sketch(t(a), "srdct", s, 9, row_groups=1).cpu().numpy()
+    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    SA32 = lib.sketch(t(a), "srdct", s, 9, acc="f32", row_groups=1).cpu().numpy()
+    assert rel(SA32, ref) < 1e-4, rel(SA32, ref)
+
+
 @pytest.mark.parametrize("m,n,s,zeta,dt", [(5003, 37, 150, 8, np.float32), (20_000, 201, 804, 8, np.float32),
                                            (3000, 30, 90, 3, np.float64), (4100, 17, 64, 16, np.float32)])
 def test_sparse_sketch_parity(lib, m, n, s, zeta, dt):
@@ -148,7 +180,8 @@ def test_plain_workload_trailing_vector(lib):
 
 
 @pytest.mark.parametrize("kind,dt,acc", [("sparse", np.float32, "f64"), ("srht", np.float32, "f64"),
-                                         ("sparse", np.float32, "f32"), ("srht", np.float64, "f64")])
+                                         ("sparse", np.float32, "f32"), ("srht", np.float64, "f64"),
+                                         ("srdct", np.float32, "f64"), ("srdct", np.float32, "f32")])
 def test_tls_trailing_vector_and_residual_ratio(lib, kind, dt, acc):
     M, _ = W.tls_matrix(m=30_000, n=60, dtype=dt)
     s = 4 * 61
@@ -189,7 +222,8 @@ def test_trailing_vectors_block_jacobi_shapes(lib, m, N, k, kind):
 
 
 @pytest.mark.parametrize("m,n,k,s,kind", [(64, 16, 16, 64, "srht"), (300, 1, 1, 8, "sparse"),
-                                          (1000, 8, 3, 1000, "srht"), (513, 5, 2, 10, "sparse")])
+                                          (1000, 8, 3, 1000, "srht"), (513, 5, 2, 10, "sparse"),
+                                          (1000, 8, 3, 1000, "srdct"), (64, 16, 16, 64, "srdct")])
 def test_edge_shapes(lib, m, n, k, s, kind):
     a = np.random.default_rng(m).standard_normal((m, n))
     Vk, sk, _ = lib.trailing_rsv(t(a), k, kind=kind, s=s, seed=2)
@@ -224,6 +258,9 @@ def test_deterministic_bitwise(lib):
     c = lib.sketch(Mt, "srht", 404, 5)
     d = lib.sketch(Mt, "srht", 404, 5)
     assert torch.equal(c, d)
+    e = lib.sketch(Mt, "srdct", 404, 5)
+    f = lib.sketch(Mt, "srdct", 404, 5)
+    assert torch.equal(e, f)
 
 
 def test_residual_entry_point(lib):

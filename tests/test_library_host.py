@@ -69,6 +69,9 @@ def test_host_sparse_bit_exact(lib, m, s, zeta):
 def test_workspace_query_validates(lib):
     d = nsk.make_desc("srht", s=200, seed=1)
     assert lib.nsk_workspace_bytes(2000, 50, 1, ctypes.byref(d)) > 0
+    dct = nsk.make_desc("srdct", s=200, seed=1)
+    # the DCT-II kind's sign table (m_p / 8 bytes) is part of its workspace
+    assert lib.nsk_workspace_bytes(2000, 50, 1, ctypes.byref(dct)) >= 2048 // 8
     bad = [
         (2000, 50, 0, nsk.make_desc("srht", s=200)),      # k < 1
         (2000, 50, 51, nsk.make_desc("srht", s=200)),     # k > N
@@ -78,6 +81,8 @@ def test_workspace_query_validates(lib):
         (5000, 50, 1, nsk.make_desc("sparse", s=200, zeta=33)),
         (5000, 50, 1, nsk.make_desc("sparse", s=200, zeta=0, acc=7)),
         (5000, 2000, 1, nsk.make_desc("srht", s=4000)),   # N > 1024 / s > 2048
+        (5000, 50, 1, nsk.make_desc("srdct", s=2100)),    # DCT-II kind: s > 2048
+        (5000, 50, 1, nsk.make_desc(4, s=200)),           # no such kind
     ]
     for m, n, k, desc in bad:
         assert lib.nsk_workspace_bytes(m, n, k, ctypes.byref(desc)) == 0
@@ -102,6 +107,9 @@ def test_entry_points_reject_bad_arguments_before_device_work(lib):
     mixed = (nsk.Operand * 2)(nsk.Operand(0x1000, nsk.F32, 0, 10, 10, None), nsk.Operand(0x1000, nsk.F64, 0, 1, 1, None))
     assert lib.nsk_sketch(mixed, 2, 2000, ctypes.byref(d), fake, 11, fake, 1 << 30, None) == 1
     assert lib.nsk_tls_backward(ctypes.byref(g), 2000, 10, fake, fake, fake, 10, fake, nsk.F32, fake, 1 << 30,
+                                None) == 5
+    dct = nsk.make_desc("srdct", s=200, seed=1)
+    assert lib.nsk_tls_backward(ctypes.byref(dct), 2000, 10, fake, fake, fake, 10, fake, nsk.F32, fake, 1 << 30,
                                 None) == 5
 
 
