@@ -140,6 +140,10 @@ def suite(nsk, W, torch, np):
                              lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
         "srht_fp32_plain": (L64.to(torch.float32), "srht", "f32",
                             lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
+        "srdct_fp32_f64acc": (L64.to(torch.float32), "srdct", "f64",
+                              lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
+        "srdct_fp32_plain": (L64.to(torch.float32), "srdct", "f32",
+                             lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
     }
     rec3 = {"workload": f"Loewner (AAA, tanh(50z)) {m} x {n}, s = {s}, k = 1", "forms": {}}
     w_oracle64, _, _, sig64, _, _ = method.trailing_rsv(L, k, "srht", s, seed, return_all=True)
@@ -235,6 +239,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--sketch-kind", default="sparse", choices=["sparse", "srht", "srdct"],
+                    help="sketch of the timed solves (the headline workload is sparse sign)")
     ap.add_argument("--suite", action="store_true",
                     help="measure the precision (Loewner), batched and gradient workloads instead; one JSON line each")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -274,12 +280,12 @@ def main():
     A, b = Mt[:, :n], Mt[:, n:]            # two column blocks, no concatenated copy
     print(f"[bench] input {m}x{N} FP32 resident ({Mt.numel() * 4 / 1e6:.0f} MB)", file=sys.stderr, flush=True)
 
-    def step(seed=7, acc="f64", s_=s, ws=None, state=None):
-        return nsk.tls_solve(A, b, kind="sparse", s=s_, seed=seed, acc=acc, residual=True, ws=ws, state=state)
+    def step(seed=7, acc="f64", s_=s, ws=None, state=None, kind=args.sketch_kind):
+        return nsk.tls_solve(A, b, kind=kind, s=s_, seed=seed, acc=acc, residual=True, ws=ws, state=state)
 
     x, state, info = step()
     torch.cuda.synchronize()
-    ws = nsk._ws(nsk.workspace_bytes(m, N, 1, nsk.make_desc("sparse", s, 7, 8)), dev)
+    ws = nsk._ws(nsk.workspace_bytes(m, N, 1, nsk.make_desc(args.sketch_kind, s, 7, 8)), dev)
     for _ in range(args.warmup):
         step(ws=ws, state=state)
     torch.cuda.synchronize()
@@ -305,7 +311,8 @@ def main():
     a_bytes = m * N * 4
     sketch_bytes = a_bytes + s * N * 8          # read A once, write SA
     sketch_gbs = sketch_bytes / (stage_ms["sketch"] * 1e-3) / 1e9
-    kernels = {"sketch": "sparse_kernel", "qr": "svd_qr_coop_kernel", "jacobi": "svd_jacobi_coop_kernel",
+    sketch_kernel = {"sparse": "sparse_kernel", "srht": "srht_kernel", "srdct": "srdct_kernel"}[args.sketch_kind]
+    kernels = {"sketch": sketch_kernel, "qr": "svd_qr_coop_kernel", "jacobi": "svd_jacobi_coop_kernel",
                "finish": "svd_finish_kernel", "post": "residual_kernel"}
     dom = max(kernels, key=lambda k: stage_ms[k])
     if dom in ("qr", "jacobi", "finish"):
@@ -322,8 +329,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernels[dom]),
                 "algorithmic_bytes_per_launch": per,
                 "ms_per_launch": stage_ms[dom]}
-    sketch_roof = {"kernel": "sparse_kernel", "bound": "hbm", "achieved": sketch_gbs, "peak": HBM_PEAK_GBS,
-                   "unit": "GB/s", "frac": sketch_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("sparse_kernel"),
+    sketch_roof = {"kernel": sketch_kernel, "bound": "hbm", "achieved": sketch_gbs, "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": sketch_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(sketch_kernel),
                    "algorithmic_bytes_per_launch": sketch_bytes,
                    "ms_per_launch": stage_ms["sketch"]}
     res_gbs = a_bytes / (stage_ms["post"] * 1e-3) / 1e9
@@ -340,31 +347,34 @@ def main():
     rho = inf.residual / opt
 
     forms = {}
-    if not args.no_forms:
-        for acc in ("f64", "f32"):
-            for c in (4, 6):
-                s_c = c * N
-                ws_c = nsk._ws(nsk.workspace_bytes(m, N, 1, nsk.make_desc("sparse", s_c, 7, 8, acc=acc)), dev)
-                st_c = nsk._ws(nsk.load().nsk_tls_state_bytes(n, s_c, 0), dev)
-                step(acc=acc, s_=s_c, ws=ws_c, state=st_c)
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                reps = 3
-                rhos = []
-                for r in range(reps):
-                    _, _, inf_c = step(seed=100 + r, acc=acc, s_=s_c, ws=ws_c, state=st_c)
-                    rhos.append(inf_c)
-                e1.record()
-                torch.cuda.synchronize()
-                rr = [nsk.read_info(i).residual / opt for i in rhos]
-                forms[f"{'fp64acc' if acc == 'f64' else 'plain_fp32'}_s{c}N"] = {
-                    "s": s_c, "solves_per_s": 1000.0 * reps / e0.elapsed_time(e1),
-                    "rho_median": float(np.median(rr))}
+    if not args.no_forms and args.sketch_kind == "sparse":
+        # sparse sign at s = 4N and 6N in both arithmetic forms; the DCT-II kind at s = 4N
+        cases = [("sparse", acc, c) for acc in ("f64", "f32") for c in (4, 6)] + \
+                [("srdct", acc, 4) for acc in ("f64", "f32")]
+        for kind, acc, c in cases:
+            s_c = c * N
+            ws_c = nsk._ws(nsk.workspace_bytes(m, N, 1, nsk.make_desc(kind, s_c, 7, 8, acc=acc)), dev)
+            st_c = nsk._ws(nsk.load().nsk_tls_state_bytes(n, s_c, 0), dev)
+            step(acc=acc, s_=s_c, ws=ws_c, state=st_c, kind=kind)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            reps = 3
+            rhos = []
+            for r in range(reps):
+                _, _, inf_c = step(seed=100 + r, acc=acc, s_=s_c, ws=ws_c, state=st_c, kind=kind)
+                rhos.append(inf_c)
+            e1.record()
+            torch.cuda.synchronize()
+            rr = [nsk.read_info(i).residual / opt for i in rhos]
+            prefix = "" if kind == "sparse" else f"{kind}_"
+            forms[f"{prefix}{'fp64acc' if acc == 'f64' else 'plain_fp32'}_s{c}N"] = {
+                "s": s_c, "solves_per_s": 1000.0 * reps / e0.elapsed_time(e1),
+                "rho_median": float(np.median(rr))}
         print(f"[bench] forms {forms}", file=sys.stderr, flush=True)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.sketch_kind == "sparse":
         print("[bench] timing the oracle on host cores", file=sys.stderr, flush=True)
         cpu = cpu_baseline(M, s, 7)
 
@@ -373,7 +383,9 @@ def main():
         "value": 1000.0 / ms_per_step, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32-in/f64-acc", "data": "synthetic",
-        "config": {"workload": "TLS [A|b] 1,000,000 x 201 FP32, sparse-sign sketch zeta=8, s=804, k=1",
+        "config": {"workload": (f"TLS [A|b] {m:,} x {N} FP32, "
+                                + {"sparse": "sparse-sign sketch zeta=8", "srht": "SRHT sketch",
+                                   "srdct": "DCT-II SRFT sketch"}[args.sketch_kind] + f", s={s}, k=1"),
                    "m": m, "N": N, "s": s, "k": 1},
         "sketch_gbs": sketch_gbs, "stage_ms": stage_ms, "rho": rho, "jacobi_sweeps": inf.sweeps,
         "roofline": roof, "sketch_roofline": sketch_roof, "residual_roofline": post_roof, "forms": forms,
