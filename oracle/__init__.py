@@ -16,6 +16,7 @@ What the oracle computes, plainly and slowly, with every floating-point step in 
                    ``SA = S A`` by plain matrix products (Section 2: Gaussian ``G/sqrt(s)``,
                    subsampled randomized trigonometric transform, sparse sign).
 * ``svd``       -- plain one-sided (Hestenes) Jacobi SVD of ``SA`` itself, no QR.
+* ``updates``   -- row updates and downdates of a sketch (Section 5, Algorithms 2 and 3).
 * ``method``    -- Algorithm 1 (trailing right singular vectors), total least squares
                    (Section 4) and the gradient of a TLS loss through the sketch.
 * ``metrics``   -- canonical-angle sines (Definition 3.1), residual ratios (Table 1),
