@@ -142,6 +142,33 @@ int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int6
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Row updates and downdates of a sketch (Section 5, Algorithms 2 and 3), in place:
+ *     SA += sum_t ops[t] S_r(:, rows[t]) a_t,
+ * where a_t is row t of the r x N operand `blocks` (NSK_F32 / NSK_F64 rows, or the Gaussian
+ * kind's NSK_BF16 / NSK_F8E4M3 with the same column exponents as the sketched matrix),
+ * ops[t] = +1 adds the row (update) and -1 removes it (downdate), and S_r is the updated
+ * sketching matrix of the sketch (d, m) that produced SA: its column j is column j of S for a
+ * row j < m of the sketched matrix, and g_j / sqrt(s) for a row appended at index j >= m, with
+ * g_j the j-th column of the Gaussian kind's G (Algorithm 2; Section 5.3 takes the same appended
+ * column for the non-Gaussian kinds).  For NSK_GAUSSIAN every column is G_hat(:, j) / sqrt(s),
+ * so an update equals sketching the changed matrix from scratch.  Keep m at the row count that
+ * was sketched across a sequence of updates; a removed original row j is downdated with its
+ * values A(j, :), an appended one with the values it was added with.
+ * A column update is nsk_sketch of the new columns into the matching columns of SA (SA pointer
+ * offset, same ldsa); a column downdate drops the column of SA.
+ * rows, ops (host, r entries): row indices >= 0 and signs +-1.  SA (device): s x N row-major
+ * FP64, row stride ldsa >= N.  ws (device): nsk_update_workspace_bytes(r, d) bytes.
+ * The call waits for its small host-to-device copies (the stream is synchronised once).
+ * Errors: as nsk_sketch for (m, N, d) and the operand; NSK_EINVAL for a negative row index, a
+ * sign other than +-1, r < 0 or r > 2^30; NSK_EWORKSPACE for a short workspace.  r = 0 does
+ * nothing.
+ */
+size_t nsk_update_workspace_bytes(int64_t r, const nsk_desc* d);
+int nsk_sketch_rows(const nsk_operand* blocks, int32_t nblocks, int64_t r, const int64_t* rows,
+                    const int8_t* ops, int64_t m, const nsk_desc* d, double* SA, int64_t ldsa,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Residual |A Vk|_F of Problem 2.1 with FP64 accumulation (one more read of A).
  * Vk (device): N x k row-major FP64.  out (device): one FP64 value.
  * NSK_EUNSUPPORTED if N * k > 16384 (V_k is staged in LDS); the same limit applies to

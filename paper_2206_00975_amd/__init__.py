@@ -96,6 +96,9 @@ _SIGS = {
     "nsk_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "nsk_philox": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                   ctypes.POINTER(ctypes.c_uint32)]),
+    "nsk_update_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, _P]),
+    "nsk_sketch_rows": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, ctypes.c_int64, _P, _P,
+                                       ctypes.c_int64, _P, ctypes.c_size_t, _P]),
     "nsk_draw_signs": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, _P]),
     "nsk_draw_srht_rows": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
     "nsk_draw_sparse": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P, _P]),
@@ -174,15 +177,39 @@ def _ws(nbytes, device):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def sketch(A, kind="srht", s=None, seed=0, zeta=8, acc="f64", row_groups=0):
-    """``SA = S A`` as an s x N FP64 tensor on A's device."""
+def sketch(A, kind="srht", s=None, seed=0, zeta=8, acc="f64", row_groups=0, out=None):
+    """``SA = S A`` as an s x N FP64 tensor on A's device.  ``out``: an s x N FP64 view with unit
+    column stride to write into, e.g. columns of a larger sketch (a column update)."""
     lib = load()
     ops, nb, m, N, dev, keep = _blocks(A)
     d = make_desc(kind, s, seed, zeta, acc, row_groups=row_groups)
     ws = _ws(lib.nsk_workspace_bytes(m, N, 1, ctypes.byref(d)), dev)
-    SA = torch.empty((s, N), dtype=torch.float64, device=dev)
-    _check("nsk_sketch", lib.nsk_sketch(ops, nb, m, ctypes.byref(d), SA.data_ptr(), N, ws.data_ptr(),
+    if out is None:
+        out = torch.empty((s, N), dtype=torch.float64, device=dev)
+    elif out.shape != (s, N) or out.dtype != torch.float64 or out.stride(1) != 1:
+        raise ValueError("out must be an s x N float64 view with unit column stride")
+    _check("nsk_sketch", lib.nsk_sketch(ops, nb, m, ctypes.byref(d), out.data_ptr(), out.stride(0), ws.data_ptr(),
                                         ws.numel(), _stream(dev)))
+    return out
+
+
+def sketch_rows(SA, values, rows, ops, m, kind="srht", seed=0, zeta=8):
+    """Row updates (+1) and downdates (-1) of the sketch ``SA`` (s x N FP64, from a sketch of an
+    m-row matrix) in place: ``SA += sum_t ops[t] S_r(:, rows[t]) values[t, :]`` (Section 5)."""
+    import numpy as np
+    lib = load()
+    blks, nb, r, N, dev, keep = _blocks(values)
+    d = make_desc(kind, SA.shape[0], seed, zeta)
+    idx = np.ascontiguousarray(rows, dtype=np.int64)
+    sg = np.ascontiguousarray(ops, dtype=np.int8)
+    if idx.size != r or sg.size != r:
+        raise ValueError("one row index and one sign per row of values")
+    if SA.dtype != torch.float64 or SA.stride(1) != 1 or SA.shape[1] != N:
+        raise ValueError("SA must be an s x N float64 tensor with unit column stride")
+    ws = _ws(lib.nsk_update_workspace_bytes(r, ctypes.byref(d)), dev)
+    _check("nsk_sketch_rows", lib.nsk_sketch_rows(blks, nb, r, idx.ctypes.data, sg.ctypes.data, m, ctypes.byref(d),
+                                                  SA.data_ptr(), SA.stride(0), ws.data_ptr(), ws.numel(),
+                                                  _stream(dev)))
     return SA
 
 

@@ -27,6 +27,8 @@ void batch_fill_inst(void* dst, const Operand& op, int64_t m, int N, int s, int 
                      double* sigma_k, nsk_info* info);
 void batch_fill_tile(void* dst, int inst, int ctile, int g);
 int tuned_rows_per_tile(int n, int64_t m, int dtype, int acc);
+hipError_t launch_row_update(const Operand& op, const SketchPlan& p, const int64_t* idx, const int8_t* ops, int r,
+                             double* SA, int64_t ldsa, hipStream_t st);
 }  // namespace nsk
 
 using namespace nsk;
@@ -340,6 +342,50 @@ int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int6
   }
   prof_mark(6, st);
   return rc;
+}
+
+size_t nsk_update_workspace_bytes(int64_t r, const nsk_desc* d) {
+  if (!d || r < 0 || d->s < 1) return 0;
+  const size_t rr = (size_t)std::max<int64_t>(r, 1);
+  return align_up((size_t)d->s * 4) + align_up(rr * 8) + align_up(rr);
+}
+
+int nsk_sketch_rows(const nsk_operand* blocks, int32_t nblocks, int64_t r, const int64_t* rows, const int8_t* ops,
+                    int64_t m, const nsk_desc* d, double* SA, int64_t ldsa, void* ws, size_t ws_bytes, void* stream) {
+  Operand op;
+  int64_t N;
+  int rc = build_operand(blocks, nblocks, d, op, N);
+  if (rc) return rc;
+  if ((rc = check_desc(d, m, N))) return rc;
+  if (r < 0 || r > (int64_t)1 << 30 || (r > 0 && (!rows || !ops)) || !SA || ldsa < N || !ws) return NSK_EINVAL;
+  for (int64_t t = 0; t < r; ++t)
+    if (rows[t] < 0 || (ops[t] != 1 && ops[t] != -1)) return NSK_EINVAL;
+  if (ws_bytes < nsk_update_workspace_bytes(r, d)) return NSK_EWORKSPACE;
+  if (r == 0) return NSK_OK;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  int* srows = reinterpret_cast<int*>(w);
+  int64_t* idx = reinterpret_cast<int64_t*>(w + align_up((size_t)d->s * 4));
+  int8_t* sg = reinterpret_cast<int8_t*>(w + align_up((size_t)d->s * 4) + align_up((size_t)r * 8));
+  if (hipMemcpyAsync(idx, rows, (size_t)r * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(sg, ops, (size_t)r, hipMemcpyHostToDevice, st) != hipSuccess)
+    return NSK_EDEVICE;
+  if (d->kind == NSK_SRHT || d->kind == NSK_SRDCT) {
+    // synchronises the stream, so the host arrays above have been consumed as well
+    const int64_t pool = d->kind == NSK_SRHT ? next_pow2(m) : srdct_pool(m);
+    if ((rc = upload_rows(d->seed, pool, d->s, srows, st))) return rc;
+  } else if (hipStreamSynchronize(st) != hipSuccess) {
+    return NSK_EDEVICE;
+  }
+  SketchPlan p{};
+  p.kind = d->kind;
+  p.m = m;
+  p.N = (int)N;
+  p.s = (int)d->s;
+  p.zeta = dflt_zeta(d);
+  p.seed = d->seed;
+  p.rows = srows;
+  return dev(launch_row_update(op, p, idx, sg, (int)r, SA, ldsa, st));
 }
 
 int nsk_residual(const nsk_operand* blocks, int32_t nblocks, int64_t m, const double* Vk, int64_t k, double* out,

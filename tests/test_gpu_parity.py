@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import workloads as W
-from oracle import draws, method, metrics, operators
+from oracle import draws, method, metrics, operators, updates
 from oracle.precision import round_bf16, round_e4m3
 
 pytestmark = pytest.mark.gpu
@@ -160,6 +160,58 @@ def test_gaussian_sketch_parity(lib, fmt):
         SA = lib.sketch([(q, t(-e))], "gauss", s, 12).cpu().numpy()
     ref = operators.sketch(stored, "gauss", s, 12, gauss_dtype=fmt)
     assert rel(SA, ref) < 1e-4, rel(SA, ref)
+
+
+# ---------------------------------------------------------------------------- sketch updates
+@pytest.mark.parametrize("kind,dt", [("srht", np.float64), ("srdct", np.float32), ("sparse", np.float32),
+                                     ("sparse", np.float64)])
+def test_row_downdate_and_update_match_oracle(lib, kind, dt):
+    m, n, s, seed = 6000, 23, 96, 21
+    rng = np.random.default_rng(len(kind) + m)
+    a = rng.standard_normal((m, n)).astype(dt)
+    SA = lib.sketch(t(a), kind, s, seed)
+    # Algorithm 3: removing rows equals the sketch of the matrix without them
+    gone = [0, 5, m - 1, 4097]
+    lib.sketch_rows(SA, t(a[gone]), gone, [-1] * len(gone), m, kind=kind, seed=seed)
+    a0 = a.astype(np.float64)
+    a0[gone] = 0.0
+    ref = operators.sketch(a0, kind, s, seed)
+    assert rel(SA.cpu().numpy(), ref) < 1e-12, rel(SA.cpu().numpy(), ref)
+    # Algorithm 2 / Section 5.3: appended rows add Gaussian columns; a re-added original row its own
+    before = SA.cpu().numpy()
+    new = rng.standard_normal((3, n)).astype(dt)
+    rows, ops = [m, m + 7, 5], [1, 1, 1]
+    lib.sketch_rows(SA, t(new), rows, ops, m, kind=kind, seed=seed)
+    ref = updates.update_rows(before, kind, seed, m, rows, new.astype(np.float64), ops)
+    assert rel(SA.cpu().numpy() - before, ref - before) < 1e-12
+
+
+def test_gaussian_row_update_matches_oracle(lib):
+    m, n, s, seed = 4000, 16, 64, 22
+    rng = np.random.default_rng(8)
+    at = t(rng.standard_normal((m + 2, n)), torch.float64).to(torch.bfloat16)
+    stored = at.to(torch.float64).cpu().numpy()
+    SA = lib.sketch(at[:m].contiguous(), "gauss", s, seed)
+    before = SA.cpu().numpy()
+    lib.sketch_rows(SA, at[m:].contiguous(), [m, m + 1], [1, 1], m, kind="gauss", seed=seed)
+    delta = SA.cpu().numpy() - before
+    ref = updates.update_rows(np.zeros_like(before), "gauss", seed, m, [m, m + 1], stored[m:], [1, 1],
+                              gauss_dtype="bf16")
+    # G_hat from FP32 Box-Muller on the device and FP64 on the host: rare one-step rounding flips
+    close = np.abs(delta - ref) <= 1e-12 * np.abs(ref).max()
+    assert close.mean() > 0.99, close.mean()
+    assert rel(delta, ref) < 1e-2
+
+
+@pytest.mark.parametrize("kind", ["srht", "srdct", "sparse"])
+def test_column_update_writes_into_sketch_columns(lib, kind):
+    m, n, s = 9000, 40, 164
+    a = np.random.default_rng(9).standard_normal((m, n)).astype(np.float32)
+    whole = lib.sketch(t(a), kind, s, 4).cpu().numpy()
+    SA = torch.zeros((s, n), dtype=torch.float64, device=DEV)
+    lib.sketch(t(a[:, :37]), kind, s, 4, out=SA[:, :37])
+    lib.sketch(t(a[:, 37:]), kind, s, 4, out=SA[:, 37:])
+    assert rel(SA.cpu().numpy(), whole) < 1e-13
 
 
 # ---------------------------------------------------------------------------- solves

@@ -111,6 +111,17 @@ def test_entry_points_reject_bad_arguments_before_device_work(lib):
     dct = nsk.make_desc("srdct", s=200, seed=1)
     assert lib.nsk_tls_backward(ctypes.byref(dct), 2000, 10, fake, fake, fake, 10, fake, nsk.F32, fake, 1 << 30,
                                 None) == 5
+    # row updates: index >= 0, sign +-1, workspace from nsk_update_workspace_bytes
+    idx = (ctypes.c_int64 * 2)(3, -1)
+    sg = (ctypes.c_int8 * 2)(1, -1)
+    assert lib.nsk_update_workspace_bytes(2, ctypes.byref(d)) > 0
+    assert lib.nsk_sketch_rows(op, 1, 2, idx, sg, 2000, ctypes.byref(d), fake, 50, fake, 1 << 20, None) == 1
+    idx2 = (ctypes.c_int64 * 2)(3, 4)
+    sg2 = (ctypes.c_int8 * 2)(1, 2)
+    assert lib.nsk_sketch_rows(op, 1, 2, idx2, sg2, 2000, ctypes.byref(d), fake, 50, fake, 1 << 20, None) == 1
+    sg3 = (ctypes.c_int8 * 2)(1, -1)
+    assert lib.nsk_sketch_rows(op, 1, 2, idx2, sg3, 2000, ctypes.byref(d), fake, 50, fake, 16, None) == 2
+    assert lib.nsk_sketch_rows(op, 1, 0, None, None, 2000, ctypes.byref(d), fake, 50, fake, 1 << 20, None) == 0
 
 
 def test_batched_plan_and_tuner_table(lib):
