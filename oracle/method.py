@@ -6,6 +6,9 @@
                        ``v`` of the sketched ``[A | b]`` gives ``x = -v(1:n) / v(n+1)``.
 * ``tls_grad``      -- gradient of ``L = |x - x_target|^2`` with respect to ``[A | b]`` through
                        the sketch (the paper has no gradient; derivation below).
+* ``null_space_eps`` -- the epsilon-tolerance version of Algorithm 1 (Section 2): every right
+                       singular vector of ``SA`` whose singular value is below ``eps`` (times the
+                       largest one when ``relative``); with ``eps = O(u)`` the numerical null space.
 
 Gradient.  With ``M~ = S M`` (s x N), ``M~ = U~ Sigma V^T`` and ``v`` its last right singular
 vector: ``g = 2 (x - x_target)``; ``dL/dv = -(1/v_N) [g; g^T x]``; first-order eigenvector
@@ -36,6 +39,18 @@ def trailing_rsv(a: np.ndarray, k: int, kind: str, s: int, seed: int, zeta: int 
     if return_all:
         return out + (sa, sigma, v, sweeps)
     return out
+
+
+def null_space_eps(a: np.ndarray, eps: float, kind: str, s: int, seed: int, relative: bool = True,
+                   zeta: int = 8):
+    """``(W, sigma, count)``: all N right singular vectors of ``SA`` in non-increasing order of
+    their singular values ``sigma``; the last ``count`` columns, those with ``sigma < eps``
+    (``eps * sigma[0]`` when ``relative``), span the computed null space."""
+    n = a.shape[1]
+    _, _, _, sigma, v, _ = trailing_rsv(a, n, kind, s, seed, zeta=zeta, return_all=True)
+    thr = eps * sigma[0] if relative else eps
+    count = int(np.sum(sigma < thr))
+    return v, sigma, count
 
 
 def tls_from_v(v: np.ndarray) -> np.ndarray:

@@ -178,6 +178,28 @@ def test_planted_null_space_dimension_three(kind):
     assert np.abs(sk).max() < 1e-13
 
 
+@pytest.mark.parametrize("kind", ["srht", "sparse", "srdct"])
+def test_epsilon_null_space_finds_planted_dimension(kind):
+    """Section 2's epsilon version: with eps = O(u) relative, an exact null space of dimension
+    3 gives exactly 3 vectors spanning it (the multiplicative perturbation keeps it); a
+    full-rank matrix gives none; an absolute eps between two singular values splits there."""
+    rng = np.random.default_rng(10)
+    n, d = 24, 3
+    u = np.linalg.qr(rng.standard_normal((2000, n)))[0]
+    v = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    sig = np.concatenate([np.linspace(3, 1, n - d), np.zeros(d)])
+    a = (u * sig) @ v.T
+    W, sigma, count = method.null_space_eps(a, 64 * U * n, kind, 4 * n, 5)
+    assert count == d
+    assert metrics.sin_theta(v[:, -d:], W[:, n - count:]) < 1e-12
+    assert np.all(np.diff(sigma) <= 0)
+    _, _, c0 = method.null_space_eps(u * np.linspace(3, 1, n) @ v.T, 64 * U * n, kind, 4 * n, 5)
+    assert c0 == 0
+    _, sg, c2 = method.null_space_eps(a, 0.5 * (sigma[n - d - 2] + sigma[n - d - 1]), kind, 4 * n, 5,
+                                      relative=False)
+    assert c2 == d + 1
+
+
 @pytest.mark.parametrize("kind", ["srht", "sparse", "gauss", "srdct"])
 def test_residual_ratio_below_ostrowski_bound(kind):
     """Proof of Theorem 2.3: rho <= sigma_max(S U_A) / sigma_min(S U_A) for the realised S."""
