@@ -142,6 +142,20 @@ int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int6
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Epsilon-tolerance version of Algorithm 1 (Section 2): the right singular vectors of SA whose
+ * singular values are below eps (relative = 0) or below eps * sigma_1(SA) (relative = 1); with
+ * eps = O(u) and relative = 1, the numerical null space.  V (device, N x N row-major FP64)
+ * receives all N right singular vectors with column j belonging to sigma (device, N FP64,
+ * non-increasing), each sign-normalised as in nsk_trailing_rsv; count (device, one int32)
+ * receives how many trailing columns of V lie below the threshold.  Workspace as
+ * nsk_workspace_bytes(m, N, N, d).  Errors: as nsk_trailing_rsv with k = N, and NSK_EINVAL for
+ * a negative or non-finite eps, relative outside {0, 1}, or a null count.
+ */
+int nsk_null_space(const nsk_operand* blocks, int32_t nblocks, int64_t m, double eps, int32_t relative,
+                   const nsk_desc* d, double* V, double* sigma, int32_t* count, nsk_info* info,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Row updates and downdates of a sketch (Section 5, Algorithms 2 and 3), in place:
  *     SA += sum_t ops[t] S_r(:, rows[t]) a_t,
  * where a_t is row t of the r x N operand `blocks` (NSK_F32 / NSK_F64 rows, or the Gaussian

@@ -96,6 +96,8 @@ _SIGS = {
     "nsk_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "nsk_philox": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                   ctypes.POINTER(ctypes.c_uint32)]),
+    "nsk_null_space": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P,
+                                      _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "nsk_update_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, _P]),
     "nsk_sketch_rows": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, ctypes.c_int64, _P, _P,
                                        ctypes.c_int64, _P, ctypes.c_size_t, _P]),
@@ -191,6 +193,23 @@ def sketch(A, kind="srht", s=None, seed=0, zeta=8, acc="f64", row_groups=0, out=
     _check("nsk_sketch", lib.nsk_sketch(ops, nb, m, ctypes.byref(d), out.data_ptr(), out.stride(0), ws.data_ptr(),
                                         ws.numel(), _stream(dev)))
     return out
+
+
+def null_space(A, eps, kind="srht", s=None, seed=0, zeta=8, acc="f64", relative=True):
+    """Epsilon-tolerance Algorithm 1: ``(V, sigma, count)`` with all N right singular vectors of
+    SA (columns, non-increasing ``sigma``); the last ``count`` columns have singular values below
+    ``eps`` (times the largest when ``relative``)."""
+    lib = load()
+    ops, nb, m, N, dev, keep = _blocks(A)
+    d = make_desc(kind, s, seed, zeta, acc)
+    ws = _ws(lib.nsk_workspace_bytes(m, N, N, ctypes.byref(d)), dev)
+    V = torch.empty((N, N), dtype=torch.float64, device=dev)
+    sigma = torch.empty(N, dtype=torch.float64, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check("nsk_null_space", lib.nsk_null_space(ops, nb, m, float(eps), int(bool(relative)), ctypes.byref(d),
+                                                V.data_ptr(), sigma.data_ptr(), count.data_ptr(), None,
+                                                ws.data_ptr(), ws.numel(), _stream(dev)))
+    return V, sigma, count
 
 
 def sketch_rows(SA, values, rows, ops, m, kind="srht", seed=0, zeta=8):

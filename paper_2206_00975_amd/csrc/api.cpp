@@ -29,6 +29,8 @@ void batch_fill_tile(void* dst, int inst, int ctile, int g);
 int tuned_rows_per_tile(int n, int64_t m, int dtype, int acc);
 hipError_t launch_row_update(const Operand& op, const SketchPlan& p, const int64_t* idx, const int8_t* ops, int r,
                              double* SA, int64_t ldsa, hipStream_t st);
+hipError_t launch_count_below(const double* sigma, int N, double eps, int relative, int32_t* count,
+                              hipStream_t st);
 }  // namespace nsk
 
 using namespace nsk;
@@ -342,6 +344,19 @@ int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int6
   }
   prof_mark(6, st);
   return rc;
+}
+
+int nsk_null_space(const nsk_operand* blocks, int32_t nblocks, int64_t m, double eps, int32_t relative,
+                   const nsk_desc* d, double* V, double* sigma, int32_t* count, nsk_info* info, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (!(eps >= 0.0) || !std::isfinite(eps) || !count || (relative != 0 && relative != 1)) return NSK_EINVAL;
+  Operand op;
+  int64_t N;
+  int rc = build_operand(blocks, nblocks, d, op, N);
+  if (rc) return rc;
+  // all N vectors, non-increasing singular values: the trailing `count` columns are the answer
+  if ((rc = nsk_trailing_rsv(blocks, nblocks, m, N, d, V, sigma, info, ws, ws_bytes, stream))) return rc;
+  return dev(launch_count_below(sigma, (int)N, eps, relative, count, (hipStream_t)stream));
 }
 
 size_t nsk_update_workspace_bytes(int64_t r, const nsk_desc* d) {

@@ -156,6 +156,29 @@ hipError_t launch_tls_extract(int N, const double* v, double* x, hipStream_t st)
   return hipGetLastError();
 }
 
+// ================================================================ epsilon null space
+// Section 2's epsilon version of Algorithm 1: the number of singular values (non-increasing,
+// sigma[0] the largest) below eps, or below eps * sigma[0] when `relative`.
+__global__ __launch_bounds__(256) void count_below_kernel(const double* __restrict__ sigma, int N, double eps,
+                                                          int relative, int32_t* __restrict__ count) {
+  __shared__ int part[4];
+  const double thr = relative ? eps * sigma[0] : eps;
+  int c = 0;
+  for (int b = 0; b < N; b += 256) {  // uniform trip count: every lane takes part in the ballot
+    const int i = b + (int)threadIdx.x;
+    c += __popcll(__ballot(i < N && sigma[i] < thr));
+  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) *count = part[0] + part[1] + part[2] + part[3];
+}
+
+hipError_t launch_count_below(const double* sigma, int N, double eps, int relative, int32_t* count,
+                              hipStream_t st) {
+  count_below_kernel<<<1, 256, 0, st>>>(sigma, N, eps, relative, count);
+  return hipGetLastError();
+}
+
 // ======================================================================== TLS backward
 // g_bar = dL/dv = -(1/v_N) [g; g.x];  w = V D V^T g_bar with D_c = 1 / (sigma_N^2 - sigma_c^2)
 // for every column c except the trailing one (D = 0 there): the first-order change of the

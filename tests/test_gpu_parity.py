@@ -162,6 +162,26 @@ def test_gaussian_sketch_parity(lib, fmt):
     assert rel(SA, ref) < 1e-4, rel(SA, ref)
 
 
+# ---------------------------------------------------------------------------- epsilon null space
+@pytest.mark.parametrize("kind,n,d", [("srht", 24, 3), ("sparse", 100, 5), ("srdct", 40, 1), ("sparse", 30, 0)])
+def test_epsilon_null_space(lib, kind, n, d):
+    rng = np.random.default_rng(n + d)
+    u = np.linalg.qr(rng.standard_normal((5000, n)))[0]
+    v = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    sig = np.concatenate([np.linspace(3, 1, n - d), np.zeros(d)])
+    a = (u * sig) @ v.T
+    eps = 64 * U * n
+    V, sigma, count = lib.null_space(t(a), eps, kind=kind, s=4 * n, seed=5)
+    torch.cuda.synchronize()
+    W, sg_ref, c_ref = method.null_space_eps(a, eps, kind, 4 * n, 5)
+    assert int(count.item()) == c_ref == d
+    assert np.abs(sigma.cpu().numpy() - sg_ref).max() <= 1e-13 * sg_ref[0]
+    V = V.cpu().numpy()
+    assert np.abs(V.T @ V - np.eye(n)).max() < 1e-12
+    if d:
+        assert metrics.sin_theta(v[:, -d:], V[:, n - d:]) < 1e-12
+
+
 # ---------------------------------------------------------------------------- sketch updates
 @pytest.mark.parametrize("kind,dt", [("srht", np.float64), ("srdct", np.float32), ("sparse", np.float32),
                                      ("sparse", np.float64)])
