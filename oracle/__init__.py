@@ -17,6 +17,7 @@ What the oracle computes, plainly and slowly, with every floating-point step in 
                    subsampled randomized trigonometric transform, sparse sign).
 * ``svd``       -- plain one-sided (Hestenes) Jacobi SVD of ``SA`` itself, no QR.
 * ``updates``   -- row updates and downdates of a sketch (Section 5, Algorithms 2 and 3).
+* ``aaa``       -- AAA rational approximation with a reused, updated sketch (Section 6).
 * ``method``    -- Algorithm 1 (trailing right singular vectors), total least squares
                    (Section 4) and the gradient of a TLS loss through the sketch.
 * ``metrics``   -- canonical-angle sines (Definition 3.1), residual ratios (Table 1),
