@@ -156,6 +156,28 @@ int nsk_null_space(const nsk_operand* blocks, int32_t nblocks, int64_t m, double
                    void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * AAA rational approximation with a reused sketch (Section 6), real sample points z (device,
+ * m distinct FP64) and values f (device, m FP64).  Support points are taken greedily where
+ * |f - r| is largest (the lowest index on ties; r is the mean of f before the first one), r the
+ * barycentric approximant sum_j w_j f_j / (z - z_j) / sum_j w_j / (z - z_j); the weights w are
+ * the trailing right singular vector of the s x k sketch of the Loewner matrix
+ * L[i, j] = (f_i - f_j) / (z_i - z_j) (non-support rows i, support columns j), kept up to date
+ * by one row downdate (Algorithm 3) and one column update per support point (Section 6.2).
+ * The loop stops when the largest error is at most tol * max|f| or after n_max support points.
+ * d: NSK_SRHT, NSK_SRDCT or NSK_SPARSE_SIGN (NSK_GAUSSIAN returns NSK_EUNSUPPORTED), with
+ * n_max < s <= m, n_max <= 320 and s <= 4096.
+ * support (host, n_max): sample indices in the order taken; n_support (host): their number;
+ * weights (device, n_max FP64): the first n_support entries are w, sign-normalised as in
+ * nsk_trailing_rsv; err_hist (host, n_max + 1, nullable): the largest error before each
+ * step, the last entry that of the returned approximant.  The call blocks: the host reads
+ * each step's largest error to decide whether to go on.  ws: nsk_aaa_workspace_bytes.
+ */
+size_t nsk_aaa_workspace_bytes(int64_t m, int32_t n_max, const nsk_desc* d);
+int nsk_aaa(const double* z, const double* f, int64_t m, int32_t n_max, double tol, const nsk_desc* d,
+            int64_t* support, double* weights, int32_t* n_support, double* err_hist, void* ws,
+            size_t ws_bytes, void* stream);
+
+/*
  * Row updates and downdates of a sketch (Section 5, Algorithms 2 and 3), in place:
  *     SA += sum_t ops[t] S_r(:, rows[t]) a_t,
  * where a_t is row t of the r x N operand `blocks` (NSK_F32 / NSK_F64 rows, or the Gaussian

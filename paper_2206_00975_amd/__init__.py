@@ -98,6 +98,9 @@ _SIGS = {
                                   ctypes.POINTER(ctypes.c_uint32)]),
     "nsk_null_space": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P,
                                       _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "nsk_aaa_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, _P]),
+    "nsk_aaa": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P, _P, _P,
+                               ctypes.c_size_t, _P]),
     "nsk_update_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, _P]),
     "nsk_sketch_rows": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, ctypes.c_int64, _P, _P,
                                        ctypes.c_int64, _P, ctypes.c_size_t, _P]),
@@ -210,6 +213,33 @@ def null_space(A, eps, kind="srht", s=None, seed=0, zeta=8, acc="f64", relative=
                                                 V.data_ptr(), sigma.data_ptr(), count.data_ptr(), None,
                                                 ws.data_ptr(), ws.numel(), _stream(dev)))
     return V, sigma, count
+
+
+def aaa(z, f, n_max, tol, kind="srht", s=None, seed=0, zeta=8, ws=None):
+    """AAA with a reused sketch (Section 6): ``(support indices, weights, errors)`` for real
+    sample points ``z`` and values ``f`` (FP64 device tensors); ``errors[i]`` is the largest
+    |f - r| before step i, the last one that of the returned approximant."""
+    import numpy as np
+    lib = load()
+    z = z.contiguous()
+    f = f.contiguous()
+    if z.dtype != torch.float64 or f.dtype != torch.float64 or z.shape != f.shape or z.dim() != 1:
+        raise ValueError("z and f must be FP64 vectors of one length")
+    m = z.shape[0]
+    s = s if s is not None else 2 * n_max
+    d = make_desc(kind, s, seed, zeta)
+    need = lib.nsk_aaa_workspace_bytes(m, n_max, ctypes.byref(d))
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, z.device)
+    sup = np.zeros(n_max, dtype=np.int64)
+    hist = np.zeros(n_max + 1, dtype=np.float64)
+    nsup = ctypes.c_int32(0)
+    w = torch.zeros(n_max, dtype=torch.float64, device=z.device)
+    _check("nsk_aaa", lib.nsk_aaa(z.data_ptr(), f.data_ptr(), m, n_max, float(tol), ctypes.byref(d), sup.ctypes.data,
+                                  w.data_ptr(), ctypes.byref(nsup), hist.ctypes.data, ws.data_ptr(), ws.numel(),
+                                  _stream(z.device)))
+    n = nsup.value
+    return [int(x) for x in sup[:n]], w[:n], [float(x) for x in hist[:n + 1]]
 
 
 def sketch_rows(SA, values, rows, ops, m, kind="srht", seed=0, zeta=8):

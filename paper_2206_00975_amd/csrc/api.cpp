@@ -359,6 +359,173 @@ int nsk_null_space(const nsk_operand* blocks, int32_t nblocks, int64_t m, double
   return dev(launch_count_below(sigma, (int)N, eps, relative, count, (hipStream_t)stream));
 }
 
+// ------------------------------------------------------------------------------ AAA
+}  // extern "C"
+
+namespace {
+
+struct AaaLayout {
+  Layout col;          // nsk workspace of an m x 1 sketch (the new Loewner column)
+  size_t col_base;
+  size_t sa_rm, sa_cm, R, log, sigma, order, colnorm, jres, sig1;
+  size_t mask, colv, row, idx, ops, sz, sf, part, pval, pidx, stats, pick, total;
+};
+
+int aaa_check(int64_t m, int32_t n_max, const nsk_desc* d) {
+  if (!d || n_max < 1 || n_max > kAaaMaxSupport) return NSK_EINVAL;
+  if (d->kind == NSK_GAUSSIAN) return NSK_EUNSUPPORTED;
+  int rc = check_desc(d, m, n_max);
+  if (rc) return rc;
+  if (!svd_fast_path((int)d->s, n_max)) return NSK_EUNSUPPORTED;
+  return NSK_OK;
+}
+
+AaaLayout aaa_layout(int64_t m, int32_t n_max, const nsk_desc* d) {
+  AaaLayout A{};
+  A.col = layout(m, 1, d);
+  size_t off = 0;
+  A.col_base = off;  off = align_up(off + A.col.total);
+  const size_t s = (size_t)d->s;
+  size_t rb = 0, lb = 0;  // the SVD's work for any N <= n_max
+  for (int N = 1; N <= n_max; ++N) {
+    rb = std::max(rb, svd_work_R_bytes((int)s, N));
+    lb = std::max(lb, svd_work_log_bytes((int)s, N, dflt_sweeps(d)));
+  }
+  A.sa_rm = off;   off = align_up(off + s * n_max * 8);
+  A.sa_cm = off;   off = align_up(off + s * n_max * 8);
+  A.R = off;       off = align_up(off + rb);
+  A.log = off;     off = align_up(off + lb);
+  A.sigma = off;   off = align_up(off + (size_t)n_max * 8);
+  A.order = off;   off = align_up(off + (size_t)n_max * 4);
+  A.colnorm = off; off = align_up(off + (size_t)n_max * 8);
+  A.jres = off;    off = align_up(off + 64);
+  A.sig1 = off;    off = align_up(off + 8);
+  A.mask = off;    off = align_up(off + (size_t)m);
+  A.colv = off;    off = align_up(off + (size_t)m * 8);
+  A.row = off;     off = align_up(off + (size_t)n_max * 8);
+  A.idx = off;     off = align_up(off + 8);
+  A.ops = off;     off = align_up(off + 1);
+  A.sz = off;      off = align_up(off + (size_t)n_max * 8);
+  A.sf = off;      off = align_up(off + (size_t)n_max * 8);
+  A.part = off;    off = align_up(off + (size_t)kAaaParts * 16);
+  A.pval = off;    off = align_up(off + (size_t)kAaaParts * 8);
+  A.pidx = off;    off = align_up(off + (size_t)kAaaParts * 8);
+  A.stats = off;   off = align_up(off + 16);
+  A.pick = off;    off = align_up(off + sizeof(AaaPick));
+  A.total = off;
+  return A;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nsk_aaa_workspace_bytes(int64_t m, int32_t n_max, const nsk_desc* d) {
+  if (aaa_check(m, n_max, d) != NSK_OK) return 0;
+  return aaa_layout(m, n_max, d).total;
+}
+
+int nsk_aaa(const double* z, const double* f, int64_t m, int32_t n_max, double tol, const nsk_desc* d,
+            int64_t* support, double* weights, int32_t* n_support, double* err_hist, void* ws, size_t ws_bytes,
+            void* stream) {
+  int rc = aaa_check(m, n_max, d);
+  if (rc) return rc;
+  if (!z || !f || !support || !weights || !n_support || !ws || !(tol >= 0.0)) return NSK_EINVAL;
+  const AaaLayout A = aaa_layout(m, n_max, d);
+  if (ws_bytes < A.total) return NSK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  unsigned char* wcol = w + A.col_base;
+  double* sa_rm = reinterpret_cast<double*>(w + A.sa_rm);
+  uint8_t* mask = w + A.mask;
+  double* colv = reinterpret_cast<double*>(w + A.colv);
+  double* row = reinterpret_cast<double*>(w + A.row);
+  int64_t* idx = reinterpret_cast<int64_t*>(w + A.idx);
+  int8_t* ops = reinterpret_cast<int8_t*>(w + A.ops);
+  double* sz = reinterpret_cast<double*>(w + A.sz);
+  double* sf = reinterpret_cast<double*>(w + A.sf);
+  double* stats = reinterpret_cast<double*>(w + A.stats);
+  AaaPick* pick = reinterpret_cast<AaaPick*>(w + A.pick);
+  if (hipMemsetAsync(mask, 0, (size_t)m, st) != hipSuccess) return NSK_EDEVICE;
+  if ((rc = dev(launch_aaa_stats(f, m, reinterpret_cast<double*>(w + A.part), stats, st)))) return rc;
+  double hstats[2];
+  if (hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return NSK_EDEVICE;
+  const double thr = tol * hstats[1];
+
+  // the column sketch: an m x 1 FP64 operand in the workspace
+  Operand cop{};
+  cop.nb = 1;
+  cop.dtype = NSK_F64;
+  cop.ptr[0] = colv;
+  cop.ld[0] = 1;
+  cop.col0[0] = 0;
+  cop.col0[1] = 1;
+  Operand rop{};
+  rop.nb = 1;
+  rop.dtype = NSK_F64;
+  rop.ptr[0] = row;
+  rop.col0[0] = 0;
+
+  int k = 0;
+  for (;; ++k) {
+    if ((rc = dev(launch_aaa_error(z, f, mask, m, sz, sf, weights, k, stats, reinterpret_cast<double*>(w + A.pval),
+                                   reinterpret_cast<int64_t*>(w + A.pidx), pick, st))))
+      return rc;
+    AaaPick hp;
+    if (hipMemcpyAsync(&hp, pick, sizeof(hp), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return NSK_EDEVICE;
+    if (err_hist) err_hist[k] = hp.err;
+    // no finite error at a non-support point (NaN in f or in r): nothing valid to join
+    if (!(hp.err >= 0.0) || hp.idx < 0 || hp.idx >= m) break;
+    if (hp.err <= thr || k == n_max) break;
+    const int64_t j = hp.idx;
+    if ((rc = dev(launch_aaa_join(z, f, m, j, k, sz, sf, mask, row, idx, ops, colv, st)))) return rc;
+    if (k > 0) {  // Algorithm 3: the new support point's row leaves the Loewner matrix
+      rop.ld[0] = k;
+      rop.col0[1] = k;
+      SketchPlan pr{};
+      pr.kind = d->kind;
+      pr.m = m;
+      pr.N = k;
+      pr.s = (int)d->s;
+      pr.zeta = dflt_zeta(d);
+      pr.seed = d->seed;
+      pr.rows = reinterpret_cast<const int*>(wcol + A.col.rows);  // uploaded by the previous column sketch
+      if ((rc = dev(launch_row_update(rop, pr, idx, ops, 1, sa_rm, n_max, st)))) return rc;
+    }
+    // column update: the sketch of the new Loewner column becomes column k of SA
+    SketchPlan pc;
+    if ((rc = run_sketch(cop, d, m, 1, wcol, A.col, sa_rm + k, n_max, st, pc))) return rc;
+    // weights: the trailing right singular vector of the s x (k + 1) sketch
+    const int N = k + 1;
+    if ((rc = dev(launch_aaa_transpose(sa_rm, n_max, (int)d->s, N, reinterpret_cast<double*>(w + A.sa_cm), st))))
+      return rc;
+    SvdPlan sp{};
+    sp.s = (int)d->s;
+    sp.N = N;
+    sp.k = 1;
+    sp.max_sweeps = dflt_sweeps(d);
+    sp.sa = reinterpret_cast<double*>(w + A.sa_cm);
+    sp.R = reinterpret_cast<double*>(w + A.R);
+    sp.V = nullptr;
+    sp.log = reinterpret_cast<double2*>(w + A.log);
+    sp.sigma = reinterpret_cast<double*>(w + A.sigma);
+    sp.order = reinterpret_cast<int*>(w + A.order);
+    sp.colnorm = reinterpret_cast<double*>(w + A.colnorm);
+    sp.jres = reinterpret_cast<JacobiResult*>(w + A.jres);
+    sp.Vk = weights;
+    sp.sigma_k = reinterpret_cast<double*>(w + A.sig1);
+    sp.info = nullptr;
+    if ((rc = dev(launch_svd(sp, st)))) return rc;
+    support[k] = j;
+  }
+  *n_support = k;
+  return NSK_OK;
+}
+
 size_t nsk_update_workspace_bytes(int64_t r, const nsk_desc* d) {
   if (!d || r < 0 || d->s < 1) return 0;
   const size_t rr = (size_t)std::max<int64_t>(r, 1);

@@ -230,6 +230,22 @@ struct TlsBack {
 hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const TlsBack& tb, const double* gx, double* work,
                                void* dA, int64_t ldda, void* db, int out_dtype, hipStream_t st);
 
+// AAA with a reused sketch (aaa.hip): reductions over at most kAaaParts blocks; at most
+// kAaaMaxSupport support points (the single-instance SVD's fast path)
+constexpr int kAaaParts = 1024;
+constexpr int kAaaMaxSupport = 320;
+struct AaaPick {
+  double err;    // largest |f - r| over the non-support points
+  int64_t idx;   // its sample index (the lowest on ties)
+};
+hipError_t launch_aaa_stats(const double* f, int64_t m, double* part, double* stats, hipStream_t st);
+hipError_t launch_aaa_error(const double* z, const double* f, const uint8_t* mask, int64_t m, const double* sz,
+                            const double* sf, const double* w, int k, const double* stats, double* pval,
+                            int64_t* pidx, AaaPick* out, hipStream_t st);
+hipError_t launch_aaa_join(const double* z, const double* f, int64_t m, int64_t j, int k, double* sz, double* sf,
+                           uint8_t* mask, double* row, int64_t* idx, int8_t* ops, double* col, hipStream_t st);
+hipError_t launch_aaa_transpose(const double* a, int64_t ld, int s, int N, double* cm, hipStream_t st);
+
 hipError_t launch_draw_signs(uint64_t seed, int64_t m, int8_t* d, hipStream_t st);
 hipError_t launch_draw_sparse(uint64_t seed, int64_t m, int s, int zeta, int32_t* rows,
                               int8_t* signs, hipStream_t st);

@@ -433,3 +433,28 @@ def test_batched_matches_single_instances(lib):
         assert_vectors(vk_ref, Vk.cpu().numpy(), vec_tol(sig, k))
         assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-9, atol=1e-13 * sig[0])
         assert lib.read_info(info).converged
+
+
+# ---------------------------------------------------------------------------- AAA with sketch reuse
+@pytest.mark.parametrize("kind", ["srht", "srdct", "sparse"])
+def test_aaa_sketch_reuse_matches_oracle(lib, kind):
+    """The GPU loop takes the oracle's support points while the errors are well above rounding
+    (the argmax is decided by margins far larger than the two SVDs' differences); both reach the
+    tolerance with the same or a neighbouring degree."""
+    from oracle import aaa
+    m, n_max, tol, s = 20_000, 40, 1e-10, 160
+    z = np.sort(np.random.default_rng(11).uniform(-1, 1, m))
+    f = np.tanh(50 * z)
+    sup, w, hist = lib.aaa(t(z), t(f), n_max, tol, kind=kind, s=s, seed=6)
+    sup_ref, w_ref, hist_ref = aaa.aaa(z, f, n_max, tol, kind=kind, s=s, seed=6)
+    sure = next((i for i, h in enumerate(hist_ref) if h < 1e-6), len(hist_ref))
+    assert sup[:sure] == sup_ref[:sure], (sup, sup_ref)
+    assert np.allclose(hist[:sure], hist_ref[:sure], rtol=1e-6)
+    assert hist[-1] <= tol and hist_ref[-1] <= tol
+    assert abs(len(sup) - len(sup_ref)) <= 2
+    if sup == sup_ref:
+        assert metrics.sin_theta(w_ref[:, None], w.cpu().numpy()[:, None]) < 1e-6
+    # the returned approximant's error at every sample point, recomputed on the host
+    from oracle.aaa import barycentric
+    r = barycentric(z, f, sup, w.cpu().numpy())
+    assert np.abs(f - r).max() <= 1.01 * hist[-1] + 1e-15
