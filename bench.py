@@ -113,8 +113,9 @@ def _timed(torch, fn, reps):
 
 
 def suite(nsk, W, torch, np):
-    """Precision forms on the AAA-shaped Loewner matrix, the 512-instance batch and the TLS
-    gradient at 2,000,000 x 256; one JSON line per workload (values measured live)."""
+    """Precision forms on the AAA-shaped Loewner matrix, the 512-instance batch, the TLS
+    gradient at 2,000,000 x 256, sketch maintenance and the AAA loop with sketch reuse; one JSON
+    line per workload (values measured live)."""
     from oracle import method, metrics
     dev = torch.device("cuda:0")
     nsk.load()
@@ -218,6 +219,64 @@ def suite(nsk, W, torch, np):
             "backward_write_gbs": gbytes / (ms_bw * 1e-3) / 1e9,
             "loss": float(((x - xt) ** 2).sum())}
     print(json.dumps(rec5), flush=True)
+    del A, b, Mt, ws, state, dA, db
+
+    # ---------------------------------------------------------------- sketch maintenance
+    print("[suite] sketch maintenance at 1,000,000 x 201", file=sys.stderr, flush=True)
+    M, _ = W.tls_matrix(m=1_000_000, n=200, seed=2)
+    Mt = torch.from_numpy(M).to(dev)
+    mm, NN, ss = Mt.shape[0], Mt.shape[1], 804
+    SA = nsk.sketch(Mt, "sparse", ss, 7)
+    ms_full, _ = _timed(torch, lambda: nsk.sketch(Mt, "sparse", ss, 7), 5)
+    ms_col, _ = _timed(torch, lambda: nsk.sketch(Mt[:, -1:].contiguous(), "sparse", ss, 7, out=SA[:, -1:]), 5)
+    rec6 = {"suite": "maintenance", "workload": "sketch of TLS [A|b] 1,000,000 x 201 FP32, sparse-sign s = 804",
+            "full_sketch_ms": ms_full, "column_update_ms": ms_col}
+    for r in (1, 64):
+        rows = list(range(0, r * 997, 997))
+        vals = Mt[rows].contiguous()
+        nsk.sketch_rows(SA, vals, rows, [-1] * r, mm, kind="sparse", seed=7)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            nsk.sketch_rows(SA, vals, rows, [1] * r, mm, kind="sparse", seed=7)
+        torch.cuda.synchronize()
+        rec6[f"row_update_{r}_ms"] = (time.perf_counter() - t0) * 100.0
+    print(json.dumps(rec6), flush=True)
+    del Mt, SA
+
+    # ---------------------------------------------------------------- AAA with sketch reuse
+    print("[suite] AAA with sketch reuse, 1,000,000 points", file=sys.stderr, flush=True)
+    ma, n_max, tol, sa_ = 1_000_000, 100, 1e-10, 200
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    z = torch.sort(torch.rand(ma, dtype=torch.float64, device=dev, generator=g) * 2 - 1).values
+    f = torch.tanh(50 * z)
+    rec7 = {"suite": "aaa", "workload": f"AAA, tanh(50 z) at {ma:,} uniform points of [-1, 1], s = {sa_}, "
+                                        f"tol = {tol:g} max|f|", "kinds": {}}
+    for kind in ("sparse", "srht", "srdct"):
+        nsk.aaa(z, f, n_max, tol, kind=kind, s=sa_, seed=3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sup, w, hist = nsk.aaa(z, f, n_max, tol, kind=kind, s=sa_, seed=3)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) * 1e3
+        rec7["kinds"][kind] = {"support_points": len(sup), "ms": dt, "ms_per_step": dt / max(1, len(sup)),
+                               "final_max_error": hist[-1]}
+        if kind == "sparse":
+            sup_sparse = sup
+    # the same support points with a fresh sketch of the whole Loewner matrix at every step
+    # (weights only: the loop above also evaluates the error at every point each step)
+    sidx = torch.tensor(sup_sparse, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, len(sup_sparse) + 1):
+        zs, fs = z[sidx[:k]], f[sidx[:k]]
+        L = (f[:, None] - fs[None, :]) / (z[:, None] - zs[None, :])
+        L[sidx[:k]] = 0.0
+        nsk.trailing_rsv(L.contiguous(), 1, kind="sparse", s=sa_, seed=3)
+    torch.cuda.synchronize()
+    rec7["fresh_sketch_weights_ms_sparse"] = (time.perf_counter() - t0) * 1e3
+    print(json.dumps(rec7), flush=True)
 
 
 def A_bytes(A):
