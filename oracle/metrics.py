@@ -11,6 +11,10 @@
                           the residual ratio for the realised S (proof of Theorem 2.3).
 * ``thm32_bound``      -- ``|R - R^{-*}|_2 / chi(alpha^2, (alpha + delta)^2)`` of Theorem 3.2
                           with ``S U = QR`` for the realised S.
+* ``thm34_bounds``     -- Theorem 3.4 for subspaces of different dimensions (l < k): the
+                          bounds on ``sin Theta([V_2, V_3], V~_3)`` and on
+                          ``sin Theta(V_3, [V~_2, V~_3])``, each infinite where its gap
+                          condition fails.
 * ``expected_rho``     -- first-order mean residual ratio for a Gaussian sketch,
                           ``sqrt(1 + (N - k) / (s - N + k - 1))`` (inverse-Wishart mean; a
                           derivation of this build, not a result printed in the paper).
@@ -100,6 +104,25 @@ def thm32_bound(S: np.ndarray, a: np.ndarray, sa_sigma: np.ndarray, k: int) -> f
             c = chi(alpha ** 2, top ** 2)
             best = min(best, num / c if c > 0 else math.inf)
     return best
+
+
+def thm34_bounds(S: np.ndarray, a: np.ndarray, sa_sigma: np.ndarray, k: int, l: int):
+    """Right-hand sides of Theorem 3.4 in the 2-norm for the realised S, ``l < k < n``.
+
+    First bound (on ``sin Theta([V_2, V_3], V~_3)``): alpha + delta = sigma_{n-k} (the smallest
+    of the leading n - k singular values of A), alpha = sigma~_{n-l+1} (the largest of the
+    trailing l of SA).  Second bound (on ``sin Theta(V_3, [V~_2, V~_3])``): alpha + delta =
+    sigma~_{n-k}, alpha = sigma_{n-l+1}.  Both share ``|R - R^{-*}|_2`` with ``S U = QR``.
+    """
+    u, sig, _ = np.linalg.svd(np.asarray(a, dtype=np.float64), full_matrices=False)
+    n = sig.size
+    _, r = np.linalg.qr(S @ u)
+    num = np.linalg.norm(r - np.linalg.inv(r).T, 2)
+    out = []
+    for top, alpha in ((sig[n - k - 1], sa_sigma[n - l]), (sa_sigma[n - k - 1], sig[n - l])):
+        c = chi(alpha ** 2, top ** 2) if top > alpha else 0.0
+        out.append(num / c if c > 0 else math.inf)
+    return out[0], out[1]
 
 
 def expected_rho(N: int, k: int, s: int) -> float:

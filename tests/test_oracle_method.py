@@ -231,6 +231,46 @@ def test_theorem_3_2_bound_holds(kind):
         assert err <= bound * (1 + 1e-6) + 1e-13
 
 
+@pytest.mark.parametrize("kind", ["gauss", "srht"])
+@pytest.mark.parametrize("spectrum", ["geometric", "cluster"])
+def test_theorem_3_4_bounds_hold(kind, spectrum):
+    """Figure 2 set-up: m = 1000, n = 100, coherent U = [I; 0], l = 1 and k = 2..n-1; singular
+    values geometric from 1 to 1e-10, or 80 ones followed by 20 values of 1e-10."""
+    m, n, l = 1000, 100, 1
+    rng = np.random.default_rng(12)
+    u = np.vstack([np.eye(n), np.zeros((m - n, n))])
+    v = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    sig = np.logspace(0, -10, n) if spectrum == "geometric" else np.r_[np.ones(80), np.full(20, 1e-10)]
+    a = (u * sig) @ v.T
+    s = 4 * n
+    S = operators.explicit(kind, 41, m, s, gauss_dtype="bf16")
+    _, vt_sa_sigma, vt = np.linalg.svd(S @ a, full_matrices=False)
+    Vt = vt.T                                   # right singular vectors of SA, non-increasing
+    checked = 0
+    for k in (2, 5, 20, 30, 60, 99):
+        b1, b2 = metrics.thm34_bounds(S, a, vt_sa_sigma, k, l)
+        e1 = metrics.sin_theta(v[:, n - k:], Vt[:, n - l:])
+        e2 = metrics.sin_theta(Vt[:, n - k:], v[:, n - l:])
+        assert e1 <= b1 * (1 + 1e-6) + 1e-9 and e2 <= b2 * (1 + 1e-6) + 1e-9, (k, e1, b1, e2, b2)
+        checked += np.isfinite(b1) + np.isfinite(b2)
+    assert checked >= 4
+
+
+def test_theorem_3_4_bound_vanishes_for_an_orthogonal_sketch():
+    """s = m = m_p: S U has orthonormal columns, so R is diagonal with entries +-1, R - R^{-*} = 0
+    and the subspaces agree to rounding."""
+    m, n = 256, 20
+    rng = np.random.default_rng(13)
+    u = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    v = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    a = (u * np.logspace(0, -6, n)) @ v.T
+    S = operators.explicit("srht", 3, m, m)
+    _, sa_sigma, vt = np.linalg.svd(S @ a, full_matrices=False)
+    b1, b2 = metrics.thm34_bounds(S, a, sa_sigma, 5, 2)
+    assert b1 < 1e-12 and b2 < 1e-12
+    assert metrics.sin_theta(v[:, n - 5:], vt.T[:, n - 2:]) < 1e-10
+
+
 def test_embedding_envelope_gaussian_and_coherent_failure():
     """Theorem 2.1 envelope for Gaussian S; coherent [I; 0] defeats an SRHT at s = 2n."""
     rng = np.random.default_rng(10)
