@@ -21,6 +21,12 @@ Sketch kinds (Section 2):
   ``sqrt(2/s)`` otherwise.  The cosine's argument is reduced exactly, in integers, modulo one
   period before the cosine is taken.
 
+* ``hrht``   -- hashed randomized Hadamard transform (the H-RHT of Section 2): the SRFT's row
+  sample R replaced by a 1-hashing matrix Phi (s x m_p, one entry +-1 per column at a uniformly
+  drawn row), ``S = Phi (H / sqrt(m_p)) D`` on ``A`` zero-padded to ``m_p = 2**ceil(log2 m)``
+  rows, with the Hadamard kind's D.  Phi is the sparse-sign kind's draw with zeta = 1 over the
+  m_p columns (Floyd with one draw is a uniform row; the sign bit as for sparse sign).
+
 Pinned by: the special case ``s = m = m_p`` where the SRHT and the DCT kind are orthogonal
 (SVD of ``SA`` equals SVD of ``A``), unit column norms, ``S S^T`` structure, the DCT kind
 against SciPy's orthonormal DCT-II of the signed, padded ``A`` (a library transform), and
@@ -69,6 +75,30 @@ def srdct_columns(seed: int, m: int, s: int, j0: int, j1: int, rows=None, d=None
     return cosv * w[:, None] * d[j0:j1].astype(np.float64)[None, :]
 
 
+def fwht(x: np.ndarray) -> np.ndarray:
+    """Unnormalised Walsh-Hadamard transform along axis 0 (length a power of two): the plain
+    radix-2 butterflies, entry (i, j) of the matrix being (-1)^popcount(i & j)."""
+    y = np.array(x, dtype=np.float64, copy=True)
+    n = y.shape[0]
+    h = 1
+    while h < n:
+        y = y.reshape(n // (2 * h), 2, h, *y.shape[1:])
+        a, b = y[:, 0].copy(), y[:, 1].copy()
+        y[:, 0], y[:, 1] = a + b, a - b
+        y = y.reshape(n, *y.shape[3:])
+        h *= 2
+    return y
+
+
+def hrht_matrix(seed: int, m: int, s: int) -> np.ndarray:
+    """The whole H-RHT sketching matrix (s x m, small cases only)."""
+    m_p = draws.next_pow2(m)
+    phi = sparse_matrix(seed, m_p, s, 1).toarray()
+    j = np.arange(m)
+    had = 1.0 - 2.0 * (np.bitwise_count(np.arange(m_p)[:, None] & j[None, :]) & 1)
+    return phi @ had * draws.signs(seed, m).astype(np.float64)[None, :] / math.sqrt(m_p)
+
+
 def sparse_matrix(seed: int, m: int, s: int, zeta: int) -> sp.csc_matrix:
     """Sparse-sign sketching matrix as a SciPy CSC matrix (s x m)."""
     rows, sgn = draws.sparse(seed, m, s, zeta)
@@ -89,6 +119,8 @@ def explicit(kind: str, seed: int, m: int, s: int, zeta: int = 8, gauss_dtype: s
         return srht_columns(seed, m, s, 0, m)
     if kind == "srdct":
         return srdct_columns(seed, m, s, 0, m)
+    if kind == "hrht":
+        return hrht_matrix(seed, m, s)
     if kind == "sparse":
         return sparse_matrix(seed, m, s, zeta).toarray()
     if kind == "gauss":
@@ -100,6 +132,11 @@ def sketch(a: np.ndarray, kind: str, s: int, seed: int, zeta: int = 8,
            gauss_dtype: str = "bf16", block: int = 8192) -> np.ndarray:
     """``SA`` in FP64 for an m x N matrix ``a`` (any real dtype; cast exactly to FP64)."""
     m, n = a.shape
+    if kind == "hrht":
+        m_p = draws.next_pow2(m)
+        x = np.zeros((m_p, n))
+        x[:m] = draws.signs(seed, m).astype(np.float64)[:, None] * np.asarray(a, dtype=np.float64)
+        return sparse_matrix(seed, m_p, s, 1) @ (fwht(x) / math.sqrt(m_p))
     if kind == "sparse":
         S = sparse_matrix(seed, m, s, zeta)
         out = np.zeros((s, n))

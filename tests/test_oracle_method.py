@@ -62,6 +62,42 @@ def test_srdct_full_size_is_orthogonal_and_reduces_to_lapack_svd():
     assert metrics.sin_theta(w, vk) < 1e-13 * full[0] / (full[-3] - full[-2])
 
 
+def test_fwht_matches_hadamard_library():
+    x = np.random.default_rng(1).standard_normal((64, 3))
+    assert np.allclose(operators.fwht(x), sl.hadamard(64) @ x, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("m,s", [(13, 6), (1000, 40), (4096, 300)])
+def test_hrht_is_a_hashed_hadamard_transform(m, s):
+    """S = Phi (H / sqrt(m_p)) D: scipy's Hadamard matrix, one +-1 per column of Phi, and the
+    fast form (butterflies, then the hashing as a sparse product) equals the explicit matrix."""
+    seed = 8
+    m_p = draws.next_pow2(m)
+    S = operators.explicit("hrht", seed, m, s)
+    rows, sgn = draws.sparse(seed, m_p, s, 1)
+    phi = np.zeros((s, m_p))
+    phi[rows[:, 0], np.arange(m_p)] = sgn[:, 0]
+    assert np.abs(phi).sum(axis=0).tolist() == [1.0] * m_p
+    ref = phi @ sl.hadamard(m_p)[:, :m] * draws.signs(seed, m)[None, :] / math.sqrt(m_p)
+    assert np.abs(S - ref).max() < 1e-14
+    a = np.random.default_rng(m).standard_normal((m, 5))
+    assert np.abs(operators.sketch(a, "hrht", s, seed) - S @ a).max() < 1e-12 * np.abs(S @ a).max()
+    # Phi and H / sqrt(m_p) D preserve norms in expectation: E[S^T S] = I
+    assert abs(np.linalg.norm(S) ** 2 / m - 1) < 4 / math.sqrt(s)
+
+
+def test_hrht_embeds_the_coherent_input_where_srht_fails():
+    """Section 3.1's coherent example: with U = [I; 0] the SRHT at s = 2n misses rows and is
+    not an embedding; hashing every transformed row (H-RHT) keeps sigma(S U) away from zero."""
+    m, n = 2048, 64
+    u = np.vstack([np.eye(n), np.zeros((m - n, n))])
+    for seed in (3, 4):
+        lo_h, hi_h = metrics.embedding_range(operators.explicit("hrht", seed, m, 2 * n), u)
+        lo_s, _ = metrics.embedding_range(operators.explicit("srht", seed, m, 2 * n), u)
+        assert lo_h > 0.2 and hi_h < 2.0, (lo_h, hi_h)
+        assert lo_s < 1e-8, lo_s
+
+
 @pytest.mark.parametrize("kind", ["srht", "sparse", "gauss"])
 def test_unit_column_norms_and_blocking(kind):
     m, s = 3000, 64
