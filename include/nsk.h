@@ -55,11 +55,16 @@ typedef enum nsk_kind {
                             (the CountSketch family mentioned in Section 2)                 */
   NSK_GAUSSIAN = 2,      /* S = G_hat/sqrt(s), G i.i.d. N(0,1) (Section 2) rounded to the
                             operand format of A (bf16 or e4m3) and applied on MFMA          */
-  NSK_SRDCT = 3          /* subsampled randomized DCT-II: the SRFT of Section 2 with the
+  NSK_SRDCT = 3,         /* subsampled randomized DCT-II: the SRFT of Section 2 with the
                             orthonormal DCT-II C of length m_p = max(1024, 2^ceil(log2 m)) as
                             trig transform (the real transform of Section 4's experiments),
                             S = sqrt(m_p/s) R C D on A zero-padded to m_p rows, with the
                             NSK_SRHT kind's D and row sample R (rows drawn from [0, m_p))   */
+  NSK_HRHT = 4           /* hashed randomized Hadamard transform (Section 2's H-RHT): the row
+                            sample replaced by a 1-hashing matrix Phi, S = Phi (H/sqrt(m_p)) D
+                            on A zero-padded to m_p = 2^ceil(log2 m) <= 2^21 rows; Phi is the
+                            sparse-sign draw with zeta = 1 over the m_p transformed rows.  FP64
+                            arithmetic only; the workspace holds the m_p x N transform      */
 } nsk_kind;
 
 typedef enum nsk_dtype {
@@ -119,7 +124,8 @@ size_t nsk_workspace_bytes(int64_t m, int64_t N, int64_t k, const nsk_desc* d);
  * SA (device): s x N row-major FP64 output with row stride ldsa >= N.
  * Errors: NSK_EINVAL if m < N, s <= N, s > m, a block has cols < 1 or ld < cols, nblocks
  *   outside 1..4, zeta outside 1..min(s,32); NSK_EUNSUPPORTED for other dtype/kind pairs
- *   and for s > 2048 with NSK_SRHT or NSK_SRDCT; NSK_EWORKSPACE if
+ *   and for s > 2048 with NSK_SRHT or NSK_SRDCT, NSK_HRHT with acc = NSK_F32 or m > 2^21;
+ *   NSK_EWORKSPACE if
  *   ws_bytes < nsk_workspace_bytes(m, N, 1, d).
  */
 int nsk_sketch(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_desc* d,
@@ -164,7 +170,7 @@ int nsk_null_space(const nsk_operand* blocks, int32_t nblocks, int64_t m, double
  * L[i, j] = (f_i - f_j) / (z_i - z_j) (non-support rows i, support columns j), kept up to date
  * by one row downdate (Algorithm 3) and one column update per support point (Section 6.2).
  * The loop stops when the largest error is at most tol * max|f| or after n_max support points.
- * d: NSK_SRHT, NSK_SRDCT or NSK_SPARSE_SIGN (NSK_GAUSSIAN returns NSK_EUNSUPPORTED), with
+ * d: NSK_SRHT, NSK_SRDCT or NSK_SPARSE_SIGN (other kinds return NSK_EUNSUPPORTED), with
  * n_max < s <= m, n_max <= 320 and s <= 4096.
  * support (host, n_max): sample indices in the order taken; n_support (host): their number;
  * weights (device, n_max FP64): the first n_support entries are w, sign-normalised as in
@@ -195,6 +201,7 @@ int nsk_aaa(const double* z, const double* f, int64_t m, int32_t n_max, double t
  * rows, ops (host, r entries): row indices >= 0 and signs +-1.  SA (device): s x N row-major
  * FP64, row stride ldsa >= N.  ws (device): nsk_update_workspace_bytes(r, d) bytes.
  * The call waits for its small host-to-device copies (the stream is synchronised once).
+ * NSK_HRHT returns NSK_EUNSUPPORTED (its columns are not regenerated one at a time).
  * Errors: as nsk_sketch for (m, N, d) and the operand; NSK_EINVAL for a negative row index, a
  * sign other than +-1, r < 0 or r > 2^30; NSK_EWORKSPACE for a short workspace.  r = 0 does
  * nothing.
@@ -279,7 +286,7 @@ int nsk_tls_solve(const nsk_operand* blocks, int32_t nblocks, int64_t m, const n
  * regenerated from the seed, the gradient is the rank-2 matrix p w^T + q v^T:
  * dA (device, m x n, row stride ldda >= n) = its first n columns, db (device, m) the last.
  * out_dtype: NSK_F32 or NSK_F64 for dA and db.  Built for NSK_SPARSE_SIGN and NSK_SRHT;
- * NSK_GAUSSIAN and NSK_SRDCT return NSK_EUNSUPPORTED.  A degenerate gap (sigma_N = sigma_j) gives
+ * NSK_GAUSSIAN, NSK_SRDCT and NSK_HRHT return NSK_EUNSUPPORTED.  A degenerate gap (sigma_N = sigma_j) gives
  * non-finite output: the TLS solution is then not differentiable.
  */
 int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state, const double* gx,

@@ -25,10 +25,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnsk.so")
 
-SRHT, SPARSE_SIGN, GAUSSIAN, SRDCT = 0, 1, 2, 3
+SRHT, SPARSE_SIGN, GAUSSIAN, SRDCT, HRHT = 0, 1, 2, 3, 4
 F64, F32, BF16, F8E4M3 = 0, 1, 2, 3
 FLAG_RESIDUAL = 1
-KINDS = {"srht": SRHT, "sparse": SPARSE_SIGN, "gauss": GAUSSIAN, "srdct": SRDCT}
+KINDS = {"srht": SRHT, "sparse": SPARSE_SIGN, "gauss": GAUSSIAN, "srdct": SRDCT, "hrht": HRHT}
 STATUS = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "Jacobi did not converge",
           4: "HIP runtime error", 5: "unsupported kind/dtype combination"}
 

@@ -48,6 +48,13 @@ int dflt_zeta(const nsk_desc* d) { return d->zeta ? d->zeta : 8; }
 int dflt_sweeps(const nsk_desc* d) { return d->max_sweeps ? d->max_sweeps : 30; }
 int dflt_acc(const nsk_desc* d) { return d->acc == NSK_F32 ? NSK_F32 : NSK_F64; }
 
+// H-RHT workspace: the hashing table of the m_p transformed rows, then the transform
+// (max(m_p, 1024) x N FP64)
+size_t hrht_table_bytes(int64_t m) { return align_up(sparse_table_bytes(next_pow2(m), 1)); }
+size_t hrht_draws_bytes(int64_t m, int64_t N) {
+  return hrht_table_bytes(m) + (size_t)std::max<int64_t>(next_pow2(m), 1024) * N * 8;
+}
+
 // Row groups (number of partial sketches) for a single-instance sketch.
 int plan_groups(const nsk_desc* d, int64_t m, int64_t N, int dtype) {
   if (d->row_groups > 0) return d->row_groups;
@@ -65,6 +72,12 @@ int plan_groups(const nsk_desc* d, int64_t m, int64_t N, int dtype) {
     const int64_t ct = (N + cols - 1) / cols, nb = srdct_pool(m) / 1024;
     const int64_t per_cu = srdct_lds_bytes((int)N, (int)d->s, dflt_acc(d), dtype) <= 80 * 1024 ? 2 : 1;
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256 * per_cu / ct));
+  }
+  if (d->kind == NSK_HRHT) {
+    // the hashing pass: the sparse-sign sketch (zeta = 1) of the m_p transformed rows
+    const int cols = sparse_cols((int)d->s, 1, NSK_F64);
+    const int64_t ct = (N + cols - 1) / cols, nb = (next_pow2(m) + 1023) / 1024;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256 / ct));
   }
   if (d->kind == NSK_SPARSE_SIGN) {
     // one workgroup per CU (the accumulator fills most of the LDS): about 256 workgroups
@@ -90,6 +103,7 @@ Layout layout(int64_t m, int64_t N, const nsk_desc* d) {
   L.rows = off;    off = align_up(off + (size_t)s * 4);
   const size_t draws = d->kind == NSK_SPARSE_SIGN ? sparse_table_bytes(m, dflt_zeta(d))
                      : d->kind == NSK_SRDCT     ? srdct_table_bytes(m, (int)d->s)
+                     : d->kind == NSK_HRHT      ? hrht_draws_bytes(m, N)
                                                 : 0;
   L.draws = off;   off = align_up(off + draws);
   L.partial = off; off = align_up(off + (size_t)groups * s * N * 8);
@@ -126,13 +140,17 @@ SvdPlan svd_plan(const nsk_desc* d, int64_t N, unsigned char* w, const Layout& L
 
 int check_desc(const nsk_desc* d, int64_t m, int64_t N) {
   if (!d) return NSK_EINVAL;
-  if (d->kind < NSK_SRHT || d->kind > NSK_SRDCT) return NSK_EINVAL;
+  if (d->kind < NSK_SRHT || d->kind > NSK_HRHT) return NSK_EINVAL;
   if (m < N || N < 1 || d->s <= N || d->s > m) return NSK_EINVAL;
   if (d->kind == NSK_SPARSE_SIGN) {
     const int z = dflt_zeta(d);
     if (z < 1 || z > 32 || z > d->s || d->s > 65535) return NSK_EINVAL;
   }
   if ((d->kind == NSK_SRHT || d->kind == NSK_SRDCT) && d->s > 2048) return NSK_EUNSUPPORTED;
+  if (d->kind == NSK_HRHT &&
+      (d->acc == NSK_F32 || next_pow2(m) > ((int64_t)1 << 21) || d->s > 65535 ||
+       sparse_lds_bytes((int)d->s, 1, NSK_F64) > 160 * 1024))
+    return NSK_EUNSUPPORTED;
   if (d->kind == NSK_SPARSE_SIGN && sparse_lds_bytes((int)d->s, dflt_zeta(d), dflt_acc(d)) > 160 * 1024)
     return NSK_EUNSUPPORTED;
   if (d->kind == NSK_GAUSSIAN && gauss_tiles_per_wave((int)d->s, (int)N) > 48) return NSK_EUNSUPPORTED;
@@ -265,6 +283,31 @@ int run_sketch(const Operand& op, const nsk_desc* d, int64_t m, int64_t N, unsig
     const int rc = dev(launch_srdct_signs(p, st));
     if (rc) return rc;
   }
+  if (d->kind == NSK_HRHT) {
+    // transform every row, then hash: the sparse-sign sketch with zeta = 1 of the transform
+    SketchPlan hp = p;
+    hp.kind = NSK_SPARSE_SIGN;
+    hp.m = next_pow2(m);
+    hp.zeta = 1;
+    hp.acc = NSK_F64;
+    double* Y = reinterpret_cast<double*>(ws + L.draws + hrht_table_bytes(m));
+    int rc = dev(launch_sparse_table(hp, st));
+    if (rc) return rc;
+    prof_mark(0, st);
+    if ((rc = dev(launch_rht_transform(op, m, (int)N, d->seed, Y, st)))) return rc;
+    Operand oy{};
+    oy.nb = 1;
+    oy.dtype = NSK_F64;
+    oy.ptr[0] = Y;
+    oy.ld[0] = N;
+    oy.col0[0] = 0;
+    oy.col0[1] = (int32_t)N;
+    if ((rc = dev(launch_sketch(oy, hp, st)))) return rc;
+    prof_mark(1, st);
+    rc = dev(launch_reduce(oy, hp, sa_rm, ld_rm, reinterpret_cast<double*>(ws + L.sa), d->s, st));
+    prof_mark(2, st);
+    return rc;
+  }
   if (d->kind == NSK_SPARSE_SIGN) {
     const int rc = dev(launch_sparse_table(p, st));
     if (rc) return rc;
@@ -373,7 +416,7 @@ struct AaaLayout {
 
 int aaa_check(int64_t m, int32_t n_max, const nsk_desc* d) {
   if (!d || n_max < 1 || n_max > kAaaMaxSupport) return NSK_EINVAL;
-  if (d->kind == NSK_GAUSSIAN) return NSK_EUNSUPPORTED;
+  if (d->kind == NSK_GAUSSIAN || d->kind == NSK_HRHT) return NSK_EUNSUPPORTED;
   int rc = check_desc(d, m, n_max);
   if (rc) return rc;
   if (!svd_fast_path((int)d->s, n_max)) return NSK_EUNSUPPORTED;
@@ -539,6 +582,7 @@ int nsk_sketch_rows(const nsk_operand* blocks, int32_t nblocks, int64_t r, const
   int rc = build_operand(blocks, nblocks, d, op, N);
   if (rc) return rc;
   if ((rc = check_desc(d, m, N))) return rc;
+  if (d->kind == NSK_HRHT) return NSK_EUNSUPPORTED;
   if (r < 0 || r > (int64_t)1 << 30 || (r > 0 && (!rows || !ops)) || !SA || ldsa < N || !ws) return NSK_EINVAL;
   for (int64_t t = 0; t < r; ++t)
     if (rows[t] < 0 || (ops[t] != 1 && ops[t] != -1)) return NSK_EINVAL;
@@ -657,7 +701,8 @@ int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state,
   const int64_t N = n + 1;
   int rc = check_desc(d, m, N);
   if (rc) return rc;
-  if (d->kind == NSK_GAUSSIAN || d->kind == NSK_SRDCT || !svd_fast_path((int)d->s, (int)N)) return NSK_EUNSUPPORTED;
+  if (d->kind == NSK_GAUSSIAN || d->kind == NSK_SRDCT || d->kind == NSK_HRHT || !svd_fast_path((int)d->s, (int)N))
+    return NSK_EUNSUPPORTED;
   if (!state || !gx || !dA || !db || !ws || ldda < n) return NSK_EINVAL;
   if (out_dtype != NSK_F32 && out_dtype != NSK_F64) return NSK_EINVAL;
   const Layout L = layout(m, N, d);

@@ -183,6 +183,9 @@ size_t srdct_table_bytes(int64_t m, int s);
 hipError_t launch_srdct_signs(const SketchPlan& p, hipStream_t st);
 hipError_t launch_srdct(const Operand& op, const SketchPlan& p, hipStream_t st);
 
+// H-RHT: the normalised m_p-point Hadamard transform of D A into Y (max(m_p, 1024) x N FP64)
+hipError_t launch_rht_transform(const Operand& op, int64_t m, int N, uint64_t seed, double* Y, hipStream_t st);
+
 hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st);
 // SA (FP64, s x N) = scale * sum_g partial_g; row-major (ld_rm) and/or column-major (ld_cm)
 hipError_t launch_reduce(const Operand& op, const SketchPlan& p, double* sa_rm, int64_t ld_rm,

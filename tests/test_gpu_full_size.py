@@ -65,6 +65,16 @@ def test_sparse_sketch_and_solve_full_size(lib, workload):
     assert abs(lib.read_info(info).residual - res_ref) <= 1e-10 * res_ref
 
 
+def test_hrht_sketch_columns_full_size(lib, workload):
+    """Columns of SA are sketched independently: three whole columns of the 1e6 x 201 H-RHT
+    sketch against the oracle's transform-and-hash of those columns."""
+    M, Mt = workload
+    SA = lib.sketch([Mt[:, :N_COLS], Mt[:, N_COLS:]], "hrht", S, SEED_SKETCH).cpu().numpy()
+    cols = [0, 117, N_COLS]
+    ref = operators.sketch(M[:, cols].astype(np.float64), "hrht", S, SEED_SKETCH)
+    assert rel(SA[:, cols], ref) < 1e-12, rel(SA[:, cols], ref)
+
+
 @pytest.mark.parametrize("kind", ["srht", "srdct"])
 def test_trig_sketch_sampled_rows_full_size(lib, workload, kind):
     M, Mt = workload

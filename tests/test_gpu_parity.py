@@ -110,6 +110,23 @@ def test_srdct_sketch_parity(lib, name, m, n, s, dt):
     assert rel(SA32, ref) < 1e-4, rel(SA32, ref)
 
 
+HRHT_CASES = [
+    ("tiny_m", 40, 9, 16, np.float64),            # m_p = 64: one block, the first 64 rows kept
+    ("ragged", 5003, 37, 150, np.float32),        # 8 blocks
+    ("multi_block", 70_000, 21, 300, np.float32),  # 128 blocks
+    ("wide", 9000, 129, 1100, np.float64),        # s > 1024
+    ("tls_shape", 20_000, 201, 804, np.float32),
+]
+
+
+@pytest.mark.parametrize("name,m,n,s,dt", HRHT_CASES)
+def test_hrht_sketch_parity(lib, name, m, n, s, dt):
+    a = np.random.default_rng(len(name) * 7 + m).standard_normal((m, n)).astype(dt)
+    SA = lib.sketch(t(a), "hrht", s, 43).cpu().numpy()
+    ref = operators.sketch(a.astype(np.float64), "hrht", s, 43)
+    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+
+
 def test_srdct_one_workgroup_per_column_tile(lib):
     """One row group: a workgroup runs all 128 blocks, its per-sample rotation recurrence taken
     exactly every 32 blocks."""
@@ -253,7 +270,8 @@ def test_plain_workload_trailing_vector(lib):
 
 @pytest.mark.parametrize("kind,dt,acc", [("sparse", np.float32, "f64"), ("srht", np.float32, "f64"),
                                          ("sparse", np.float32, "f32"), ("srht", np.float64, "f64"),
-                                         ("srdct", np.float32, "f64"), ("srdct", np.float32, "f32")])
+                                         ("srdct", np.float32, "f64"), ("srdct", np.float32, "f32"),
+                                         ("hrht", np.float32, "f64")])
 def test_tls_trailing_vector_and_residual_ratio(lib, kind, dt, acc):
     M, _ = W.tls_matrix(m=30_000, n=60, dtype=dt)
     s = 4 * 61

@@ -69,6 +69,9 @@ def test_host_sparse_bit_exact(lib, m, s, zeta):
 def test_workspace_query_validates(lib):
     d = nsk.make_desc("srht", s=200, seed=1)
     assert lib.nsk_workspace_bytes(2000, 50, 1, ctypes.byref(d)) > 0
+    hr = nsk.make_desc("hrht", s=200, seed=1)
+    # the H-RHT workspace holds the m_p x N transform
+    assert lib.nsk_workspace_bytes(2000, 50, 1, ctypes.byref(hr)) >= 2048 * 50 * 8
     dct = nsk.make_desc("srdct", s=200, seed=1)
     # the DCT-II kind's sign table (m_p / 8 bytes) is part of its workspace
     assert lib.nsk_workspace_bytes(2000, 50, 1, ctypes.byref(dct)) >= 2048 // 8
@@ -82,7 +85,9 @@ def test_workspace_query_validates(lib):
         (5000, 50, 1, nsk.make_desc("sparse", s=200, zeta=0, acc=7)),
         (5000, 2000, 1, nsk.make_desc("srht", s=4000)),   # N > 1024 / s > 2048
         (5000, 50, 1, nsk.make_desc("srdct", s=2100)),    # DCT-II kind: s > 2048
-        (5000, 50, 1, nsk.make_desc(4, s=200)),           # no such kind
+        (5000, 50, 1, nsk.make_desc(5, s=200)),           # no such kind
+        (5000, 50, 1, nsk.make_desc("hrht", s=200, acc="f32")),   # H-RHT: FP64 arithmetic only
+        (3_000_000, 50, 1, nsk.make_desc("hrht", s=200)),  # H-RHT: m_p <= 2^21
     ]
     for m, n, k, desc in bad:
         assert lib.nsk_workspace_bytes(m, n, k, ctypes.byref(desc)) == 0
