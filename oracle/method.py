@@ -6,6 +6,8 @@
                        ``v`` of the sketched ``[A | b]`` gives ``x = -v(1:n) / v(n+1)``.
 * ``tls_grad``      -- gradient of ``L = |x - x_target|^2`` with respect to ``[A | b]`` through
                        the sketch (the paper has no gradient; derivation below).
+* ``tls_solve_multi`` -- Section 4 with k right-hand sides: ``X = -V12 V22^{-1}`` from the
+                       trailing k right singular vectors of the sketched ``[A | B]``.
 * ``null_space_eps`` -- the epsilon-tolerance version of Algorithm 1 (Section 2): every right
                        singular vector of ``SA`` whose singular value is below ``eps`` (times the
                        largest one when ``relative``); with ``eps = O(u)`` the numerical null space.
@@ -51,6 +53,15 @@ def null_space_eps(a: np.ndarray, eps: float, kind: str, s: int, seed: int, rela
     thr = eps * sigma[0] if relative else eps
     count = int(np.sum(sigma < thr))
     return v, sigma, count
+
+
+def tls_solve_multi(mat: np.ndarray, nrhs: int, kind: str, s: int, seed: int, zeta: int = 8):
+    """``(X, Vk, sigma_k)`` for ``mat = [A | B]`` with ``B`` the last ``nrhs`` columns."""
+    N = mat.shape[1]
+    vk, sk = trailing_rsv(mat, nrhs, kind, s, seed, zeta=zeta)
+    n = N - nrhs
+    X = -np.linalg.solve(vk[n:].T, vk[:n].T).T
+    return X, vk, sk
 
 
 def tls_from_v(v: np.ndarray) -> np.ndarray:

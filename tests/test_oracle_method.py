@@ -369,6 +369,25 @@ def test_tls_full_size_sketch_equals_classical_tls():
     assert np.linalg.norm(x - x_ref) <= 1e-11 * np.linalg.norm(x_ref)
 
 
+def test_multi_rhs_tls_exact_and_classical():
+    """k right-hand sides (Section 4): a consistent B = A X recovers X exactly (the null space of
+    [A | B] is spanned by [X; -I]); with an orthogonal full-size sketch the result equals
+    classical TLS from LAPACK's SVD of [A | B]."""
+    rng = np.random.default_rng(14)
+    m, n, k = 1024, 30, 4
+    a = rng.standard_normal((m, n))
+    x = rng.standard_normal((n, k))
+    X, vk, sk = method.tls_solve_multi(np.hstack([a, a @ x]), k, "sparse", 4 * (n + k), 3)
+    assert np.abs(X - x).max() < 1e-10 and np.abs(sk).max() < 1e-12
+    b = a @ x + 1e-2 * rng.standard_normal((m, k))
+    M = np.hstack([a, b])
+    Xs, _, _ = method.tls_solve_multi(M, k, "srht", m, 5)
+    _, _, vt = np.linalg.svd(M)
+    V = vt[-k:].T
+    Xc = -V[:n] @ np.linalg.inv(V[n:])
+    assert np.abs(Xs - Xc).max() < 1e-10 * np.abs(Xc).max()
+
+
 def test_tls_gradient_central_differences():
     M, _ = W.tls_matrix(m=600, n=11, seed=12, dtype=np.float64)
     xt = W.tls_target(11)
