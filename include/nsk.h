@@ -134,7 +134,8 @@ int nsk_sketch(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_
 /*
  * Algorithm 1: trailing k right singular vectors of A through the sketch.
  * SA is reduced by Householder QR (FP64) to R (N x N); R is diagonalised by one-sided
- * Jacobi (FP64) with cyclic round-robin pair order and tolerance N*u; singular values
+ * Jacobi (FP64) with cyclic round-robin pair order and tolerance N*u (past N = 320 or
+ * s = 4096: one-sided Jacobi on SA itself across the GPU, no QR); singular values
  * are sorted non-increasing (Section 3 ordering) and W = V(:, N-k+1:N) is returned.
  * Vk (device): N x k row-major FP64; column j belongs to sigma_{N-k+1+j}; each column is
  *   sign-normalised so that its entry of largest magnitude (lowest index on ties) > 0.
@@ -146,6 +147,21 @@ int nsk_sketch(const nsk_operand* blocks, int32_t nblocks, int64_t m, const nsk_
 int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int64_t k,
                      const nsk_desc* d, double* Vk, double* sigma_k, nsk_info* info,
                      void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Total least squares with k = nrhs right-hand sides (Section 4): the trailing nrhs right
+ * singular vectors V_k of the sketched [A | B] (the operand's last nrhs columns are B, so
+ * N = n + nrhs) give X = -V12 V22^{-1}, V12 = V_k(1:n, :), V22 = V_k(n+1:N, :).
+ * X (device): n x nrhs row-major FP64.  Vk (device, N x nrhs) and sigma_k (device, nrhs, nullable)
+ * receive the trailing vectors and singular values as in nsk_trailing_rsv.  Workspace as
+ * nsk_workspace_bytes(m, N, nrhs, d).  Sizes past the register-blocked SVD (N > 320 or s > 4096)
+ * run the multi-workgroup Jacobi on SA.  Errors: as nsk_trailing_rsv with k = nrhs, and
+ * NSK_EINVAL for nrhs < 1, nrhs > 64 or nrhs >= N.  A singular V22 (no TLS solution) gives
+ * non-finite entries of X.
+ */
+int nsk_tls_solve_multi(const nsk_operand* blocks, int32_t nblocks, int64_t m, int64_t nrhs,
+                        const nsk_desc* d, double* X, double* Vk, double* sigma_k, nsk_info* info,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Epsilon-tolerance version of Algorithm 1 (Section 2): the right singular vectors of SA whose

@@ -96,6 +96,8 @@ _SIGS = {
     "nsk_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "nsk_philox": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                   ctypes.POINTER(ctypes.c_uint32)]),
+    "nsk_tls_solve_multi": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _P, _P, _P, _P, _P,
+                                           _P, ctypes.c_size_t, _P]),
     "nsk_null_space": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P,
                                       _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "nsk_aaa_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, _P]),
@@ -196,6 +198,24 @@ def sketch(A, kind="srht", s=None, seed=0, zeta=8, acc="f64", row_groups=0, out=
     _check("nsk_sketch", lib.nsk_sketch(ops, nb, m, ctypes.byref(d), out.data_ptr(), out.stride(0), ws.data_ptr(),
                                         ws.numel(), _stream(dev)))
     return out
+
+
+def tls_solve_multi(A, B, kind="srdct", s=None, seed=0, zeta=8, acc="f64", max_sweeps=0):
+    """TLS with k right-hand sides (Section 4): ``(X, Vk, sigma_k, info)``, X = -V12 V22^{-1}
+    (n x k) from the trailing k right singular vectors of the sketched [A | B]."""
+    lib = load()
+    ops, nb, m, N, dev, keep = _blocks([A, B])
+    k = B.shape[1] if B.dim() == 2 else 1
+    d = make_desc(kind, s, seed, zeta, acc, max_sweeps)
+    ws = _ws(lib.nsk_workspace_bytes(m, N, k, ctypes.byref(d)), dev)
+    X = torch.empty((N - k, k), dtype=torch.float64, device=dev)
+    Vk = torch.empty((N, k), dtype=torch.float64, device=dev)
+    sk = torch.empty(k, dtype=torch.float64, device=dev)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    _check("nsk_tls_solve_multi", lib.nsk_tls_solve_multi(ops, nb, m, k, ctypes.byref(d), X.data_ptr(), Vk.data_ptr(),
+                                                          sk.data_ptr(), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                          _stream(dev)))
+    return X, Vk, sk, info
 
 
 def null_space(A, eps, kind="srht", s=None, seed=0, zeta=8, acc="f64", relative=True):

@@ -31,6 +31,7 @@ hipError_t launch_row_update(const Operand& op, const SketchPlan& p, const int64
                              double* SA, int64_t ldsa, hipStream_t st);
 hipError_t launch_count_below(const double* sigma, int N, double eps, int relative, int32_t* count,
                               hipStream_t st);
+hipError_t launch_tls_extract_multi(const double* Vk, int n, int k, double* X, hipStream_t st);
 }  // namespace nsk
 
 using namespace nsk;
@@ -387,6 +388,18 @@ int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int6
   }
   prof_mark(6, st);
   return rc;
+}
+
+int nsk_tls_solve_multi(const nsk_operand* blocks, int32_t nblocks, int64_t m, int64_t nrhs, const nsk_desc* d,
+                        double* X, double* Vk, double* sigma_k, nsk_info* info, void* ws, size_t ws_bytes,
+                        void* stream) {
+  Operand op;
+  int64_t N;
+  int rc = build_operand(blocks, nblocks, d, op, N);
+  if (rc) return rc;
+  if (nrhs < 1 || nrhs > 64 || nrhs >= N || !X || !Vk) return NSK_EINVAL;
+  if ((rc = nsk_trailing_rsv(blocks, nblocks, m, nrhs, d, Vk, sigma_k, info, ws, ws_bytes, stream))) return rc;
+  return dev(launch_tls_extract_multi(Vk, (int)(N - nrhs), (int)nrhs, X, (hipStream_t)stream));
 }
 
 int nsk_null_space(const nsk_operand* blocks, int32_t nblocks, int64_t m, double eps, int32_t relative,

@@ -156,6 +156,63 @@ hipError_t launch_tls_extract(int N, const double* v, double* x, hipStream_t st)
   return hipGetLastError();
 }
 
+// ============================================================ multi-RHS TLS extraction
+// Section 4 with k right-hand sides: X = -V12 V22^{-1} from the trailing k right singular
+// vectors Vk (N x k row-major, N = n + k) of [A | B], V12 = Vk(0:n, :), V22 = Vk(n:N, :).
+// Row i of X solves x V22 = -V12(i, :), i.e. V22^T x^T = -V12(i, :)^T: one workgroup factors
+// M = V22^T = P^T L U with partial pivoting in LDS (k <= kTlsMaxRhs), then each thread solves
+// its rows.  A singular V22 (no TLS solution, Section 4) gives non-finite entries.
+constexpr int kTlsMaxRhs = 64;
+
+__global__ __launch_bounds__(256) void tls_extract_multi_kernel(const double* __restrict__ Vk, int n, int k,
+                                                                double* __restrict__ X) {
+  __shared__ double M[kTlsMaxRhs * kTlsMaxRhs];  // row-major k x k: M[r][c] = V22[c][r]
+  __shared__ int piv[kTlsMaxRhs];
+  for (int e = threadIdx.x; e < k * k; e += 256) {
+    const int r = e / k, c = e % k;
+    M[r * k + c] = Vk[(size_t)(n + c) * k + r];
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {  // elimination step j, pivot chosen by one thread
+    if (threadIdx.x == 0) {
+      int pr = j;
+      double best = fabs(M[j * k + j]);
+      for (int r = j + 1; r < k; ++r)
+        if (fabs(M[r * k + j]) > best) { best = fabs(M[r * k + j]); pr = r; }
+      piv[j] = pr;
+      if (pr != j)
+        for (int c = 0; c < k; ++c) { const double t = M[j * k + c]; M[j * k + c] = M[pr * k + c]; M[pr * k + c] = t; }
+    }
+    __syncthreads();
+    for (int r = j + 1 + (int)threadIdx.x; r < k; r += 256) {
+      const double l = M[r * k + j] / M[j * k + j];
+      M[r * k + j] = l;
+      for (int c = j + 1; c < k; ++c) M[r * k + c] -= l * M[j * k + c];
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double y[kTlsMaxRhs];
+    for (int c = 0; c < k; ++c) y[c] = -Vk[(size_t)i * k + c];
+    for (int j = 0; j < k; ++j) {  // the row swaps, then L (unit diagonal), then U
+      const int pr = piv[j];
+      if (pr != j) { const double t = y[j]; y[j] = y[pr]; y[pr] = t; }
+    }
+    for (int r = 1; r < k; ++r)
+      for (int c = 0; c < r; ++c) y[r] -= M[r * k + c] * y[c];
+    for (int r = k - 1; r >= 0; --r) {
+      for (int c = r + 1; c < k; ++c) y[r] -= M[r * k + c] * y[c];
+      y[r] /= M[r * k + r];
+    }
+    for (int c = 0; c < k; ++c) X[(size_t)i * k + c] = y[c];
+  }
+}
+
+hipError_t launch_tls_extract_multi(const double* Vk, int n, int k, double* X, hipStream_t st) {
+  tls_extract_multi_kernel<<<1, 256, 0, st>>>(Vk, n, k, X);
+  return hipGetLastError();
+}
+
 // ================================================================ epsilon null space
 // Section 2's epsilon version of Algorithm 1: the number of singular values (non-increasing,
 // sigma[0] the largest) below eps, or below eps * sigma[0] when `relative`.

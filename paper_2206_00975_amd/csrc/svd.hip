@@ -6,17 +6,19 @@
 // rotation log.  The Jacobi kernel is specialised on the rows per lane NR: NR <= 3 runs 8
 // waves (2 per SIMD, 256 VGPRs each); NR >= 4 holds two blocks of 4 x 13 or 5 x 10 doubles per
 // lane and runs 4 waves (1 per SIMD), whose accumulation registers absorb the overflow.
-// Larger problems use svd_instance (scalar Jacobi on global-memory R with V accumulated).
+// Larger problems run one-sided Jacobi on SA itself across the whole GPU (svd_big.hpp).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "nsk_internal.hpp"
 #include "svd_device.hpp"
 #include "qr_coop.hpp"
 #include "svd_pipeline.hpp"
+#include "svd_big.hpp"
 
 namespace nsk {
 
-constexpr int kSvdThreads = 1024;
 __host__ __device__ constexpr int jacobi_threads(int NR) { return NR <= 3 ? 512 : 256; }
 
 static SvdWork to_work(const SvdPlan& p) {
@@ -144,20 +146,17 @@ __global__ __launch_bounds__(kFinishThreads) void svd_finish_kernel(SvdWork w) {
   svd_stage_finish_nr<NR, replay_per_thread(kFinishThreads)>(w, smem);
 }
 
-__global__ __launch_bounds__(kSvdThreads) void svd_kernel(SvdPlan p) {
-  extern __shared__ unsigned char smem[];
-  svd_instance(p.sa, p.s, p.N, p.k, p.max_sweeps, p.R, p.V, p.sigma, p.order, p.Vk, p.sigma_k, p.info, smem);
-}
 
 
 bool svd_fast_path(int s, int N) { return N <= kFastMaxN && s <= kFastMaxS; }
 
 size_t svd_work_R_bytes(int s, int N) {
-  return svd_fast_path(s, N) ? svd_fast_R_bytes(N) : (size_t)N * N * 8;
+  return svd_fast_path(s, N) ? svd_fast_R_bytes(N) : 0;
 }
 
+// the fast path's rotation log; the large path's per-sweep counters
 size_t svd_work_log_bytes(int s, int N, int max_sweeps) {
-  return svd_fast_path(s, N) ? svd_fast_log_bytes(N, max_sweeps) : 0;
+  return svd_fast_path(s, N) ? svd_fast_log_bytes(N, max_sweeps) : svd_big_counter_bytes(max_sweeps);
 }
 
 hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
@@ -229,10 +228,26 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
     prof_mark(5, st);
     return hipGetLastError();
   }
-  const size_t lds = svd_lds_bytes(p.s, p.N);
-  if (hipError_t e = lds_attr((const void*)svd_kernel, lds)) return e;
-  svd_kernel<<<1, kSvdThreads, lds, st>>>(p);
-  for (int stage = 3; stage <= 5; ++stage) prof_mark(stage, st);
+  // large sizes: cooperative Jacobi on SA, then the one-workgroup finish
+  int dev = 0, cus = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  if (hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) return e;
+  const int pairs = (p.N + 1) / 2;
+  const int groups = std::max(1, std::min(cus, (pairs + kBigThreads / 64 - 1) / (kBigThreads / 64)));
+  double* sa = p.sa;
+  int s = p.s, N = p.N, sweeps = p.max_sweeps;
+  double* V = p.V;
+  unsigned long long* counters = reinterpret_cast<unsigned long long*>(p.log);
+  void* args[] = {&sa, &s, &N, &V, &sweeps, &counters};
+  prof_mark(3, st);
+  const void* fn = p.s <= 1024   ? reinterpret_cast<const void*>(svd_big_jacobi_kernel<16>)
+                   : p.s <= 2048 ? reinterpret_cast<const void*>(svd_big_jacobi_kernel<32>)
+                                 : reinterpret_cast<const void*>(svd_big_jacobi_kernel<0>);
+  if (hipError_t e = hipLaunchCooperativeKernel(fn, dim3(groups), dim3(kBigThreads), args, 0, st)) return e;
+  prof_mark(4, st);
+  svd_big_finish_kernel<<<1, 1024, (size_t)p.N * 8, st>>>(p.sa, p.s, p.N, p.k, p.V, p.max_sweeps, counters, p.sigma,
+                                                          p.order, p.Vk, p.sigma_k, p.info);
+  prof_mark(5, st);
   return hipGetLastError();
 }
 

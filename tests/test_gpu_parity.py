@@ -476,3 +476,48 @@ def test_aaa_sketch_reuse_matches_oracle(lib, kind):
     from oracle.aaa import barycentric
     r = barycentric(z, f, sup, w.cpu().numpy())
     assert np.abs(f - r).max() <= 1.01 * hist[-1] + 1e-15
+
+
+# ---------------------------------------------------------------------------- large N, several right-hand sides
+def test_large_path_trailing_vectors(lib):
+    """N = 400 is past the register-blocked SVD: the multi-workgroup Jacobi on SA."""
+    m, N, k, s = 8192, 400, 3, 800
+    a = W.planted_matrix(m, N, k=k, level=1e-4, seed=(8, N))[0].astype(np.float64)
+    Vk, sk, info = lib.trailing_rsv(t(a), k, kind="srht", s=s, seed=12)
+    torch.cuda.synchronize()
+    vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a, k, "srht", s, 12, return_all=True)
+    assert_vectors(vk_ref, Vk.cpu().numpy(), vec_tol(sig, k))
+    assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-10, atol=1e-14 * sig[0])
+    inf = lib.read_info(info)
+    assert inf.converged and abs(inf.sigma_max - sig[0]) <= 1e-12 * sig[0]
+
+
+def test_multi_rhs_tls_matches_oracle(lib):
+    m, n, k, s = 5000, 40, 3, 172
+    rng = np.random.default_rng(15)
+    a = rng.standard_normal((m, n))
+    b = a @ rng.standard_normal((n, k)) + 1e-3 * rng.standard_normal((m, k))
+    X, Vk, sk, _ = lib.tls_solve_multi(t(a), t(b), kind="sparse", s=s, seed=4)
+    torch.cuda.synchronize()
+    X_ref, vk_ref, sk_ref = method.tls_solve_multi(np.hstack([a, b]), k, "sparse", s, 4)
+    assert rel(X.cpu().numpy(), X_ref) < 1e-10, rel(X.cpu().numpy(), X_ref)
+
+
+def test_multi_rhs_tls_table1_shape(lib):
+    """Table 1's shape: n = 1000, k = 10, s = 2(n + k) = 2020, DCT-II sketch, m = 2^14; A with
+    singular values geometric from 1 to 1e-3, B in A's range plus noise.  The expected
+    vectors are LAPACK's SVD of the oracle's sketch (the oracle's own Jacobi, pinned to LAPACK,
+    would take minutes at N = 1010)."""
+    m, n, k, s = 1 << 14, 1000, 10, 2020
+    M = W.table1_tls_matrix(m, n, k, seed=16)
+    a, b = M[:, :n], M[:, n:]
+    X, Vk, sk, info = lib.tls_solve_multi(t(a), t(b), kind="srdct", s=s, seed=9)
+    torch.cuda.synchronize()
+    sa = operators.sketch(M, "srdct", s, 9)
+    _, sig, vt = np.linalg.svd(sa, full_matrices=False)
+    V = vt[-k:].T
+    assert_vectors(V, Vk.cpu().numpy(), vec_tol(sig, k))
+    X_ref = -np.linalg.solve(V[n:].T, V[:n].T).T
+    gap_amp = np.linalg.norm(np.linalg.inv(V[n:]), 2)          # X's sensitivity to the vectors
+    assert rel(X.cpu().numpy(), X_ref) <= 10 * vec_tol(sig, k) * gap_amp * (1 + np.linalg.norm(X_ref, 2))
+    assert lib.read_info(info).converged
