@@ -232,8 +232,8 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
   int dev = 0, cus = 0;
   if (hipError_t e = hipGetDevice(&dev)) return e;
   if (hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) return e;
-  const int pairs = (p.N + 1) / 2;
-  const int groups = std::max(1, std::min(cus, (pairs + kBigThreads / 64 - 1) / (kBigThreads / 64)));
+  const int nb = (p.N + kBigW - 1) / kBigW;
+  const int groups = std::max(1, std::min(cus, (nb + (nb & 1)) / 2));
   double* sa = p.sa;
   int s = p.s, N = p.N, sweeps = p.max_sweeps;
   double* V = p.V;

@@ -1,15 +1,19 @@
 // SVD of SA for the sizes past the register-blocked fast path (N > 320 or s > 4096):
 // one-sided Jacobi on SA itself (its columns, s long, are rotated in HBM) across the whole GPU.
 //
-// A cooperative grid of workgroups of four waves takes the N/2 disjoint column pairs of each
-// round of the cyclic round-robin (circle) ordering, one pair per wave, and every round ends in
-// a grid barrier, whose device-scope fences publish the rotated columns to the next round's
-// readers on other CUs.  A pair (p, q) rotates when |x_p . x_q| > N u |x_p| |x_q| (the
-// single-workgroup path's rule and rotation formulas), V (N x N, from the identity) is rotated
-// alongside, and a sweep with no rotation ends the loop for every workgroup at once (the
-// rotation count is read after the barrier).  No QR first: Jacobi on SA sees the same column
-// inner products as Jacobi on its R factor.  The finish (one workgroup) takes the column norms
-// as singular values, ranks them and writes the trailing k columns of V, sign-normalised.
+// Block round-robin: the columns form blocks of kBigW; in each round of the circle ordering of
+// the blocks, a workgroup of kBigW waves takes one pair of blocks and runs a full one-sided
+// Jacobi sweep over their 2 kBigW columns (the circle ordering again, one column pair per wave,
+// workgroup barriers between its rounds), so the block pair's columns stay in the XCD's L2
+// while it works on them and the whole matrix crosses HBM once per block round instead of once
+// per column round.  Block rounds end in a grid barrier, whose device-scope fences publish the
+// rotated columns to the next round's readers on other CUs.  A pair (p, q) rotates when
+// |x_p . x_q| > N u |x_p| |x_q| (rule and formulas as in the register-blocked Jacobi), V (N x N,
+// from the identity) is rotated alongside, and a sweep with no rotation -- every column pair
+// within tolerance -- ends the loop for every workgroup at once (the count is read after the
+// barrier).  No QR first: Jacobi on SA sees the same column inner products as Jacobi on its R
+// factor.  The finish (one workgroup) takes the column norms as singular values, ranks them and
+// writes the trailing k columns of V, sign-normalised.
 #pragma once
 
 #include <hip/hip_cooperative_groups.h>
@@ -20,7 +24,8 @@
 
 namespace nsk {
 
-constexpr int kBigThreads = 256;  // four waves, one column pair each per round
+constexpr int kBigW = 8;                // columns per block
+constexpr int kBigThreads = 64 * kBigW;  // one wave per column pair of a block pair's round
 
 // counters: [0, max_sweeps) rotations per sweep, [max_sweeps, 2 max_sweeps) largest relative
 // cosine bits per sweep, then sweeps performed and the converged flag
@@ -99,6 +104,61 @@ __device__ inline void big_pair(double* __restrict__ xp, double* __restrict__ xq
   }
 }
 
+// One column pair (p < q) by one wave: the sums, and the rotation of SA's columns and V's when
+// they are not orthogonal to tolerance.  The sums are wave-uniform after the reduction, so the
+// whole wave takes one branch.  SCH > 0: the pair stays in registers (s <= 64 SCH) from the sums
+// to the rotation.  off: the wave's largest relative cosine so far.  Returns 1 if it rotated.
+template <int SCH>
+__device__ inline int big_pair_step(double* __restrict__ sa, int s, int N, double* __restrict__ V, int p, int q,
+                                    int lane, double tol, double& off) {
+  double* xp = sa + (size_t)p * s;
+  double* xq = sa + (size_t)q * s;
+  double a, b, g;
+  double x[SCH > 0 ? SCH : 1], y[SCH > 0 ? SCH : 1];
+  if constexpr (SCH > 0) {
+#pragma unroll
+    for (int u = 0; u < SCH; ++u) {
+      const int e = lane + 64 * u;
+      x[u] = e < s ? xp[e] : 0.0;
+      y[u] = e < s ? xq[e] : 0.0;
+    }
+    a = b = g = 0.0;
+#pragma unroll
+    for (int u = 0; u < SCH; ++u) {
+      a = fma(x[u], x[u], a);
+      b = fma(y[u], y[u], b);
+      g = fma(x[u], y[u], g);
+    }
+  } else {
+    big_pair<0>(xp, xq, s, lane, true, a, b, g, false, 0.0, 0.0);
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  g = wave_sum(g);
+  const double nab = sqrt(a * b);
+  if (nab > 0) off = fmax(off, fabs(g) / nab);
+  if (!(fabs(g) > tol * nab)) return 0;
+  const double zeta = (b - a) / (2.0 * g);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double sn = c * t;
+  if constexpr (SCH > 0) {
+#pragma unroll
+    for (int u = 0; u < SCH; ++u) {
+      const int e = lane + 64 * u;
+      if (e < s) {
+        xp[e] = c * x[u] - sn * y[u];
+        xq[e] = sn * x[u] + c * y[u];
+      }
+    }
+  } else {
+    big_pair<0>(xp, xq, s, lane, false, a, b, g, true, c, sn);
+  }
+  double da, db, dg;
+  big_pair<16>(V + (size_t)p * N, V + (size_t)q * N, N, lane, false, da, db, dg, true, c, sn);  // N <= 1024
+  return 1;
+}
+
 // SCH: register chunks of 64 for a column of SA (s <= 64 SCH; 0 = any s, streamed)
 template <int SCH>
 __global__ __launch_bounds__(kBigThreads) void svd_big_jacobi_kernel(double* __restrict__ sa, int s, int N,
@@ -106,77 +166,36 @@ __global__ __launch_bounds__(kBigThreads) void svd_big_jacobi_kernel(double* __r
                                                                      unsigned long long* __restrict__ counters) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * (kBigThreads / 64) + (threadIdx.x >> 6);
-  const int W = gridDim.x * (kBigThreads / 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t gt = (int64_t)blockIdx.x * kBigThreads + threadIdx.x, GT = (int64_t)gridDim.x * kBigThreads;
   for (int64_t e = gt; e < (int64_t)N * N; e += GT) V[e] = (e / N == e % N) ? 1.0 : 0.0;
   for (int64_t i = gt; i < 2 * max_sweeps + 2; i += GT) counters[i] = 0;
   grid.sync();
-  const int n_even = N + (N & 1);
-  const int P = n_even / 2;
+  const int nb = (N + kBigW - 1) / kBigW;
+  const int nb_even = nb + (nb & 1);
+  const int P = nb_even / 2;  // block pairs per block round
   const double tol = (double)N * 0x1p-53;
   int sweeps = 0, conv = 0;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     int nrot = 0;
-    for (int r = 0; r < n_even - 1; ++r) {
-      for (int i = gw; i < P; i += W) {
-        int p = circle_col(i, r, n_even), q = circle_col(n_even - 1 - i, r, n_even);
-        if (p > q) { const int tmp = p; p = q; q = tmp; }
-        if (q >= N) continue;
-        double* xp = sa + (size_t)p * s;
-        double* xq = sa + (size_t)q * s;
-        // the sums are wave-uniform after the reduction, so the whole wave takes one branch;
-        // with SCH > 0 the pair stays in registers from the sums to the rotation
-        double a, b, g;
-        double x[SCH > 0 ? SCH : 1], y[SCH > 0 ? SCH : 1];
-        if constexpr (SCH > 0) {
-#pragma unroll
-          for (int u = 0; u < SCH; ++u) {
-            const int e = lane + 64 * u;
-            x[u] = e < s ? xp[e] : 0.0;
-            y[u] = e < s ? xq[e] : 0.0;
-          }
-          a = b = g = 0.0;
-#pragma unroll
-          for (int u = 0; u < SCH; ++u) {
-            a = fma(x[u], x[u], a);
-            b = fma(y[u], y[u], b);
-            g = fma(x[u], y[u], g);
-          }
-        } else {
-          big_pair<0>(xp, xq, s, lane, true, a, b, g, false, 0.0, 0.0);
+    double off = 0.0;  // one atomic per wave and sweep: the counters are not contended per pair
+    for (int r = 0; r < nb_even - 1; ++r) {
+      for (int bp = blockIdx.x; bp < P; bp += gridDim.x) {  // uniform over the workgroup
+        const int bI = circle_col(bp, r, nb_even), bJ = circle_col(nb_even - 1 - bp, r, nb_even);
+        for (int ir = 0; ir < 2 * kBigW - 1; ++ir) {
+          // positions 0..kBigW-1 are block bI's columns, kBigW..2 kBigW-1 block bJ's
+          const int pa = circle_col(wave, ir, 2 * kBigW), pb = circle_col(2 * kBigW - 1 - wave, ir, 2 * kBigW);
+          int p = pa < kBigW ? bI * kBigW + pa : bJ * kBigW + pa - kBigW;
+          int q = pb < kBigW ? bI * kBigW + pb : bJ * kBigW + pb - kBigW;
+          if (p > q) { const int tmp = p; p = q; q = tmp; }
+          if (q < N) nrot += big_pair_step<SCH>(sa, s, N, V, p, q, lane, tol, off);
+          __syncthreads();  // the next inner round's pairs read this one's columns
         }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        g = wave_sum(g);
-        const double nab = sqrt(a * b);
-        if (nab > 0 && lane == 0)
-          atomicMax(&counters[max_sweeps + sw], (unsigned long long)__double_as_longlong(fabs(g) / nab));
-        if (!(fabs(g) > tol * nab)) continue;
-        const double zeta = (b - a) / (2.0 * g);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double sn = c * t;
-        if constexpr (SCH > 0) {
-#pragma unroll
-          for (int u = 0; u < SCH; ++u) {
-            const int e = lane + 64 * u;
-            if (e < s) {
-              xp[e] = c * x[u] - sn * y[u];
-              xq[e] = sn * x[u] + c * y[u];
-            }
-          }
-        } else {
-          big_pair<0>(xp, xq, s, lane, false, a, b, g, true, c, sn);
-        }
-        double da, db, dg;
-        big_pair<16>(V + (size_t)p * N, V + (size_t)q * N, N, lane, false, da, db, dg, true, c, sn);  // N <= 1024
-        ++nrot;
       }
       grid.sync();
     }
     if (lane == 0 && nrot) atomicAdd(&counters[sw], (unsigned long long)nrot);
+    if (lane == 0 && off > 0) atomicMax(&counters[max_sweeps + sw], (unsigned long long)__double_as_longlong(off));
     grid.sync();
     sweeps = sw + 1;
     if (__hip_atomic_load(&counters[sw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
