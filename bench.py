@@ -114,8 +114,8 @@ def _timed(torch, fn, reps):
 
 def suite(nsk, W, torch, np):
     """Precision forms on the AAA-shaped Loewner matrix, the 512-instance batch, the TLS
-    gradient at 2,000,000 x 256, sketch maintenance and the AAA loop with sketch reuse; one JSON
-    line per workload (values measured live)."""
+    gradient at 2,000,000 x 256, sketch maintenance, the AAA loop with sketch reuse and TLS with
+    ten right-hand sides at Table 1's shape; one JSON line per workload (values measured live)."""
     from oracle import method, metrics
     dev = torch.device("cuda:0")
     nsk.load()
@@ -277,6 +277,40 @@ def suite(nsk, W, torch, np):
     torch.cuda.synchronize()
     rec7["fresh_sketch_weights_ms_sparse"] = (time.perf_counter() - t0) * 1e3
     print(json.dumps(rec7), flush=True)
+    del z, f, L
+
+    # ---------------------------------------------------------------- Table 1 shape: TLS, k = 10
+    print("[suite] TLS with 10 right-hand sides at Table 1's shape", file=sys.stderr, flush=True)
+    n1, k1, s1 = 1000, 10, 2020
+    rec8 = {"suite": "table1", "workload": "TLS [A|B], n = 1000, k = 10, s = 2020, DCT-II sketch, FP64; "
+                                           "A: singular values 1 -> 1e-3, B in range(A) plus noise", "m": {}}
+    for lm in (14, 16, 18):
+        m1 = 1 << lm
+        M1 = W.table1_tls_matrix(m1, n1, k1, seed=16)
+        Mt1 = torch.from_numpy(M1).to(dev)
+        a1, b1 = Mt1[:, :n1], Mt1[:, n1:]
+        nsk.tls_solve_multi(a1, b1, kind="srdct", s=s1, seed=9)
+        torch.cuda.synchronize()
+        nsk.profile_enable(2)
+        t0 = time.perf_counter()
+        for _ in range(2):
+            X, Vk, sk, info = nsk.tls_solve_multi(a1, b1, kind="srdct", s=s1, seed=9)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 2 * 1e3
+        stages, calls = nsk.profile_read()
+        nsk.profile_enable(0)
+        r = {"ms": dt, "stage_ms": {kk: v / max(calls, 1) for kk, v in stages.items()},
+             "jacobi_sweeps": nsk.read_info(info).sweeps}
+        if lm == 14:  # Table 1's accuracy columns against the exact TLS subspace (LAPACK)
+            _, _, vt = np.linalg.svd(M1, full_matrices=False)
+            Vo = vt[-k1:].T
+            Vg = Vk.cpu().numpy()
+            r["residual_ratio"] = float(np.linalg.norm(M1 @ Vg) / np.linalg.norm(M1 @ Vo))
+            r["sin_theta_vs_exact"] = float(np.linalg.norm(Vg - Vo @ (Vo.T @ Vg), 2))
+        rec8["m"][f"2^{lm}"] = r
+        print(f"[suite] table1 m=2^{lm} {r}", file=sys.stderr, flush=True)
+        del Mt1, a1, b1, M1
+    print(json.dumps(rec8), flush=True)
 
 
 def A_bytes(A):
