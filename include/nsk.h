@@ -64,7 +64,8 @@ typedef enum nsk_kind {
                             sample replaced by a 1-hashing matrix Phi, S = Phi (H/sqrt(m_p)) D
                             on A zero-padded to m_p = 2^ceil(log2 m) <= 2^21 rows; Phi is the
                             sparse-sign draw with zeta = 1 over the m_p transformed rows.  FP64
-                            arithmetic only; the workspace holds the m_p x N transform      */
+                            arithmetic only; the workspace holds the m_p x N transform;
+                            s + m_p / 1024 <= 10240                                          */
 } nsk_kind;
 
 typedef enum nsk_dtype {
@@ -124,7 +125,7 @@ size_t nsk_workspace_bytes(int64_t m, int64_t N, int64_t k, const nsk_desc* d);
  * SA (device): s x N row-major FP64 output with row stride ldsa >= N.
  * Errors: NSK_EINVAL if m < N, s <= N, s > m, a block has cols < 1 or ld < cols, nblocks
  *   outside 1..4, zeta outside 1..min(s,32); NSK_EUNSUPPORTED for other dtype/kind pairs
- *   and for s > 2048 with NSK_SRHT or NSK_SRDCT, NSK_HRHT with acc = NSK_F32 or m > 2^21;
+ *   and for s > 2048 with NSK_SRHT or NSK_SRDCT, NSK_HRHT with acc = NSK_F32, m > 2^21 or s + m_p/1024 > 10240;
  *   NSK_EWORKSPACE if
  *   ws_bytes < nsk_workspace_bytes(m, N, 1, d).
  */

@@ -49,9 +49,9 @@ int dflt_zeta(const nsk_desc* d) { return d->zeta ? d->zeta : 8; }
 int dflt_sweeps(const nsk_desc* d) { return d->max_sweeps ? d->max_sweeps : 30; }
 int dflt_acc(const nsk_desc* d) { return d->acc == NSK_F32 ? NSK_F32 : NSK_F64; }
 
-// H-RHT workspace: the hashing table of the m_p transformed rows, then the transform
+// H-RHT workspace: the hash word of each of the m_p transformed rows, then the transform
 // (max(m_p, 1024) x N FP64)
-size_t hrht_table_bytes(int64_t m) { return align_up(sparse_table_bytes(next_pow2(m), 1)); }
+size_t hrht_table_bytes(int64_t m) { return align_up((size_t)next_pow2(m) * 4); }
 size_t hrht_draws_bytes(int64_t m, int64_t N) {
   return hrht_table_bytes(m) + (size_t)std::max<int64_t>(next_pow2(m), 1024) * N * 8;
 }
@@ -75,10 +75,11 @@ int plan_groups(const nsk_desc* d, int64_t m, int64_t N, int dtype) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256 * per_cu / ct));
   }
   if (d->kind == NSK_HRHT) {
-    // the hashing pass: the sparse-sign sketch (zeta = 1) of the m_p transformed rows
-    const int cols = sparse_cols((int)d->s, 1, NSK_F64);
-    const int64_t ct = (N + cols - 1) / cols, nb = (next_pow2(m) + 1023) / 1024;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256 / ct));
+    // the transform-and-hash pass: one workgroup per CU (its LDS holds a block and the
+    // accumulator), each over a range of the 1024 in-block indices
+    const int cols = std::max(1, rht_hash_cols(m, (int)d->s));
+    const int64_t ct = (N + cols - 1) / cols;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, 256 / ct));
   }
   if (d->kind == NSK_SPARSE_SIGN) {
     // one workgroup per CU (the accumulator fills most of the LDS): about 256 workgroups
@@ -148,9 +149,7 @@ int check_desc(const nsk_desc* d, int64_t m, int64_t N) {
     if (z < 1 || z > 32 || z > d->s || d->s > 65535) return NSK_EINVAL;
   }
   if ((d->kind == NSK_SRHT || d->kind == NSK_SRDCT) && d->s > 2048) return NSK_EUNSUPPORTED;
-  if (d->kind == NSK_HRHT &&
-      (d->acc == NSK_F32 || next_pow2(m) > ((int64_t)1 << 21) || d->s > 65535 ||
-       sparse_lds_bytes((int)d->s, 1, NSK_F64) > 160 * 1024))
+  if (d->kind == NSK_HRHT && (d->acc == NSK_F32 || next_pow2(m) > ((int64_t)1 << 21) || rht_hash_cols(m, (int)d->s) == 0))
     return NSK_EUNSUPPORTED;
   if (d->kind == NSK_SPARSE_SIGN && sparse_lds_bytes((int)d->s, dflt_zeta(d), dflt_acc(d)) > 160 * 1024)
     return NSK_EUNSUPPORTED;
@@ -285,27 +284,18 @@ int run_sketch(const Operand& op, const nsk_desc* d, int64_t m, int64_t N, unsig
     if (rc) return rc;
   }
   if (d->kind == NSK_HRHT) {
-    // transform every row, then hash: the sparse-sign sketch with zeta = 1 of the transform
+    // transform every row, hash it into the partial sketches, reduce them (scale 1: the
+    // hashing matrix has entries +-1)
+    uint32_t* hash = reinterpret_cast<uint32_t*>(ws + L.draws);
+    double* Y = reinterpret_cast<double*>(ws + L.draws + hrht_table_bytes(m));
+    int rc = dev(launch_rht(op, p, hash, Y, st));  // marks the end of stage 0 after the table
+    if (rc) return rc;
+    prof_mark(1, st);
     SketchPlan hp = p;
     hp.kind = NSK_SPARSE_SIGN;
-    hp.m = next_pow2(m);
     hp.zeta = 1;
     hp.acc = NSK_F64;
-    double* Y = reinterpret_cast<double*>(ws + L.draws + hrht_table_bytes(m));
-    int rc = dev(launch_sparse_table(hp, st));
-    if (rc) return rc;
-    prof_mark(0, st);
-    if ((rc = dev(launch_rht_transform(op, m, (int)N, d->seed, Y, st)))) return rc;
-    Operand oy{};
-    oy.nb = 1;
-    oy.dtype = NSK_F64;
-    oy.ptr[0] = Y;
-    oy.ld[0] = N;
-    oy.col0[0] = 0;
-    oy.col0[1] = (int32_t)N;
-    if ((rc = dev(launch_sketch(oy, hp, st)))) return rc;
-    prof_mark(1, st);
-    rc = dev(launch_reduce(oy, hp, sa_rm, ld_rm, reinterpret_cast<double*>(ws + L.sa), d->s, st));
+    rc = dev(launch_reduce(op, hp, sa_rm, ld_rm, reinterpret_cast<double*>(ws + L.sa), d->s, st));
     prof_mark(2, st);
     return rc;
   }

@@ -183,8 +183,20 @@ size_t srdct_table_bytes(int64_t m, int s);
 hipError_t launch_srdct_signs(const SketchPlan& p, hipStream_t st);
 hipError_t launch_srdct(const Operand& op, const SketchPlan& p, hipStream_t st);
 
-// H-RHT: the normalised m_p-point Hadamard transform of D A into Y (max(m_p, 1024) x N FP64)
-hipError_t launch_rht_transform(const Operand& op, int64_t m, int N, uint64_t seed, double* Y, hipStream_t st);
+// H-RHT: columns per tile of the transform-and-hash pass, the widest of 8, 4, 2 whose LDS (the
+// B x cols block of one in-block index, B = max(m_p, 1024) / 1024, and the s x cols accumulator)
+// fits in 160 KB; 0 if none does.
+inline int rht_hash_cols(int64_t m, int s) {
+  const int64_t mp = next_pow2(m);
+  const int64_t B = (mp < 1024 ? 1024 : mp) / 1024;
+  if (B == 1024 && (1024 * 8 + 64 + (int64_t)s * 8) * 8 <= 160 * 1024) return 8;  // register kernel
+  for (int c = 8; c >= 2; c >>= 1)
+    if ((B + s) * c * 8 <= 160 * 1024) return c;
+  return 0;
+}
+// the hash table (m_p words), the transform (Y: max(m_p, 1024) x N FP64) and the partial sketches
+// (p.groups x s x N FP64) of the H-RHT sketch
+hipError_t launch_rht(const Operand& op, const SketchPlan& p, uint32_t* hash, double* Y, hipStream_t st);
 
 hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st);
 // SA (FP64, s x N) = scale * sum_g partial_g; row-major (ld_rm) and/or column-major (ld_cm)
