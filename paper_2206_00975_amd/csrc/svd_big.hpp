@@ -24,7 +24,7 @@
 
 namespace nsk {
 
-constexpr int kBigW = 8;                // columns per block
+constexpr int kBigW = 4;                // columns per block (256 threads: room for both pairs)
 constexpr int kBigThreads = 64 * kBigW;  // one wave per column pair of a block pair's round
 
 // counters: [0, max_sweeps) rotations per sweep, [max_sweeps, 2 max_sweeps) largest relative
@@ -107,20 +107,31 @@ __device__ inline void big_pair(double* __restrict__ xp, double* __restrict__ xq
 // One column pair (p < q) by one wave: the sums, and the rotation of SA's columns and V's when
 // they are not orthogonal to tolerance.  The sums are wave-uniform after the reduction, so the
 // whole wave takes one branch.  SCH > 0: the pair stays in registers (s <= 64 SCH) from the sums
-// to the rotation.  off: the wave's largest relative cosine so far.  Returns 1 if it rotated.
+// to the rotation, and V's pair (N <= 1024) is loaded with it, so a round costs one load latency.
+// off: the wave's largest relative cosine so far.  Returns 1 if it rotated.
 template <int SCH>
 __device__ inline int big_pair_step(double* __restrict__ sa, int s, int N, double* __restrict__ V, int p, int q,
                                     int lane, double tol, double& off) {
   double* xp = sa + (size_t)p * s;
   double* xq = sa + (size_t)q * s;
+  double* vp = V + (size_t)p * N;
+  double* vq = V + (size_t)q * N;
   double a, b, g;
   double x[SCH > 0 ? SCH : 1], y[SCH > 0 ? SCH : 1];
+  constexpr int VCH = SCH > 0 ? 16 : 1;  // N <= 1024
+  double vx[VCH], vy[VCH];
   if constexpr (SCH > 0) {
 #pragma unroll
     for (int u = 0; u < SCH; ++u) {
       const int e = lane + 64 * u;
       x[u] = e < s ? xp[e] : 0.0;
       y[u] = e < s ? xq[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < VCH; ++u) {
+      const int e = lane + 64 * u;
+      vx[u] = e < N ? vp[e] : 0.0;
+      vy[u] = e < N ? vq[e] : 0.0;
     }
     a = b = g = 0.0;
 #pragma unroll
@@ -151,11 +162,19 @@ __device__ inline int big_pair_step(double* __restrict__ sa, int s, int N, doubl
         xq[e] = sn * x[u] + c * y[u];
       }
     }
+#pragma unroll
+    for (int u = 0; u < VCH; ++u) {
+      const int e = lane + 64 * u;
+      if (e < N) {
+        vp[e] = c * vx[u] - sn * vy[u];
+        vq[e] = sn * vx[u] + c * vy[u];
+      }
+    }
   } else {
     big_pair<0>(xp, xq, s, lane, false, a, b, g, true, c, sn);
+    double da, db, dg;
+    big_pair<16>(vp, vq, N, lane, false, da, db, dg, true, c, sn);  // N <= 1024
   }
-  double da, db, dg;
-  big_pair<16>(V + (size_t)p * N, V + (size_t)q * N, N, lane, false, da, db, dg, true, c, sn);  // N <= 1024
   return 1;
 }
 
