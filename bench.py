@@ -95,9 +95,16 @@ def cpu_baseline(M, s, seed, n_rep=3):
             break
     dt = (time.perf_counter() - t0) / done
     n_rep = done
+    # beside it, the deterministic method: LAPACK's SVD of the whole matrix (one call)
+    t1 = time.perf_counter()
+    np.linalg.svd(M64, full_matrices=False)
+    t_lapack = time.perf_counter() - t1
     return {"value": 1.0 / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_rep} full-size solve(s) of the same workload (m={M.shape[0]}, N={M.shape[1]}, "
-                      f"s={s}), FP64, {dt:.2f} s each"}
+                      f"s={s}), FP64, {dt:.2f} s each",
+            "lapack_svd_of_A": {"value": 1.0 / t_lapack, "unit": "solves/s",
+                                "sample": f"one numpy.linalg.svd of the FP64 {M.shape[0]} x {M.shape[1]} "
+                                          f"matrix, {t_lapack:.2f} s"}}
 
 
 def _timed(torch, fn, reps):
@@ -112,205 +119,216 @@ def _timed(torch, fn, reps):
     return e0.elapsed_time(e1) / reps, out
 
 
-def suite(nsk, W, torch, np):
+SUITE_PARTS = ("precision", "batched", "gradient", "maintenance", "aaa", "table1")
+
+
+def suite(nsk, W, torch, np, only=None):
     """Precision forms on the AAA-shaped Loewner matrix, the 512-instance batch, the TLS
     gradient at 2,000,000 x 256, sketch maintenance, the AAA loop with sketch reuse and TLS with
-    ten right-hand sides at Table 1's shape; one JSON line per workload (values measured live)."""
+    ten right-hand sides at Table 1's shape; one JSON line per workload (values measured live).
+    only: the subset of SUITE_PARTS to run (all when None)."""
     from oracle import method, metrics
     dev = torch.device("cuda:0")
     nsk.load()
+    want = lambda part: only is None or part in only
 
     # ---------------------------------------------------------------- precision forms
-    print("[suite] Loewner matrix (greedy AAA, FP64 host)", file=sys.stderr, flush=True)
-    L, _, _, _ = W.loewner_aaa()
-    m, n = L.shape
-    s, k, seed = 2 * n, 1, 3
-    l2 = float(np.linalg.norm(L, 2))
-    _, _, vt = np.linalg.svd(L, full_matrices=False)
-    w_exact = vt[-1][:, None]
-    L64 = torch.from_numpy(L).to(dev)
-    e = np.floor(np.log2(448.0 / np.abs(L).max(axis=0))).astype(np.int8)
-    fp8 = (L64 * torch.from_numpy(2.0 ** e.astype(np.float64)).to(dev)[None, :]).to(torch.float8_e4m3fn)
-    forms = {
-        "gaussian_bf16": (L64.to(torch.bfloat16), "gauss", "f64",
-                          lambda: L64.to(torch.bfloat16).to(torch.float64).cpu().numpy(), "bf16", 2 * s * m * n, 2500.0),
-        "gaussian_e4m3": ([(fp8, torch.from_numpy(-e).to(dev))], "gauss", "f64",
-                          lambda: fp8.to(torch.float64).cpu().numpy() * 2.0 ** (-e.astype(np.float64))[None, :],
-                          "e4m3", 2 * s * m * n, 5000.0),
-        "srht_fp32_f64acc": (L64.to(torch.float32), "srht", "f64",
-                             lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
-        "srht_fp32_plain": (L64.to(torch.float32), "srht", "f32",
-                            lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
-        "srdct_fp32_f64acc": (L64.to(torch.float32), "srdct", "f64",
-                              lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
-        "srdct_fp32_plain": (L64.to(torch.float32), "srdct", "f32",
-                             lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
-    }
-    rec3 = {"workload": f"Loewner (AAA, tanh(50z)) {m} x {n}, s = {s}, k = 1", "forms": {}}
-    w_oracle64, _, _, sig64, _, _ = method.trailing_rsv(L, k, "srht", s, seed, return_all=True)
-    rec3["oracle_fp64_exact_L"] = {"residual_over_norm": float(np.linalg.norm(L @ w_oracle64)) / l2,
-                                   "sin_theta_vs_svd_of_L": metrics.sin_theta(w_exact, w_oracle64)}
-    for name, (A, kind, acc, stored_fn, gdt, flops, peak) in forms.items():
-        ms_sk, _ = _timed(torch, lambda: nsk.sketch(A, kind, s, seed, acc=acc), 20)
-        ms_solve, (Vk, sk, _) = _timed(torch, lambda: nsk.trailing_rsv(A, k, kind=kind, s=s, seed=seed, acc=acc), 10)
-        w = Vk.cpu().numpy()
-        stored = stored_fn()
-        w_ref, _, _, sig, _, _ = method.trailing_rsv(stored, k, kind, s, seed, gauss_dtype=gdt, return_all=True)
-        r = {"sketch_us": ms_sk * 1e3, "solve_us": ms_solve * 1e3,
-             "sin_theta_vs_oracle_same_input": metrics.sin_theta(w_ref, w),
-             "sin_theta_vs_fp64_oracle": metrics.sin_theta(w_oracle64, w),
-             "residual_over_norm": float(np.linalg.norm(L @ w)) / l2,
-             "sketch_input_gbs": A_bytes(A) / (ms_sk * 1e-3) / 1e9}
-        if flops:
-            r["mfma_tflops"] = flops / (ms_sk * 1e-3) / 1e12
-            r["mfma_frac_of_dense_peak"] = r["mfma_tflops"] / peak
-        rec3["forms"][name] = r
-        print(f"[suite] {name} {r}", file=sys.stderr, flush=True)
-    print(json.dumps({"suite": "precision", **rec3}), flush=True)
-    del L64, fp8
+    if want("precision"):
+        print("[suite] Loewner matrix (greedy AAA, FP64 host)", file=sys.stderr, flush=True)
+        L, _, _, _ = W.loewner_aaa()
+        m, n = L.shape
+        s, k, seed = 2 * n, 1, 3
+        l2 = float(np.linalg.norm(L, 2))
+        _, _, vt = np.linalg.svd(L, full_matrices=False)
+        w_exact = vt[-1][:, None]
+        L64 = torch.from_numpy(L).to(dev)
+        e = np.floor(np.log2(448.0 / np.abs(L).max(axis=0))).astype(np.int8)
+        fp8 = (L64 * torch.from_numpy(2.0 ** e.astype(np.float64)).to(dev)[None, :]).to(torch.float8_e4m3fn)
+        forms = {
+            "gaussian_bf16": (L64.to(torch.bfloat16), "gauss", "f64",
+                              lambda: L64.to(torch.bfloat16).to(torch.float64).cpu().numpy(), "bf16", 2 * s * m * n, 2500.0),
+            "gaussian_e4m3": ([(fp8, torch.from_numpy(-e).to(dev))], "gauss", "f64",
+                              lambda: fp8.to(torch.float64).cpu().numpy() * 2.0 ** (-e.astype(np.float64))[None, :],
+                              "e4m3", 2 * s * m * n, 5000.0),
+            "srht_fp32_f64acc": (L64.to(torch.float32), "srht", "f64",
+                                 lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
+            "srht_fp32_plain": (L64.to(torch.float32), "srht", "f32",
+                                lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
+            "srdct_fp32_f64acc": (L64.to(torch.float32), "srdct", "f64",
+                                  lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
+            "srdct_fp32_plain": (L64.to(torch.float32), "srdct", "f32",
+                                 lambda: L64.to(torch.float32).to(torch.float64).cpu().numpy(), "bf16", None, None),
+        }
+        rec3 = {"workload": f"Loewner (AAA, tanh(50z)) {m} x {n}, s = {s}, k = 1", "forms": {}}
+        w_oracle64, _, _, sig64, _, _ = method.trailing_rsv(L, k, "srht", s, seed, return_all=True)
+        rec3["oracle_fp64_exact_L"] = {"residual_over_norm": float(np.linalg.norm(L @ w_oracle64)) / l2,
+                                       "sin_theta_vs_svd_of_L": metrics.sin_theta(w_exact, w_oracle64)}
+        for name, (A, kind, acc, stored_fn, gdt, flops, peak) in forms.items():
+            ms_sk, _ = _timed(torch, lambda: nsk.sketch(A, kind, s, seed, acc=acc), 20)
+            ms_solve, (Vk, sk, _) = _timed(torch, lambda: nsk.trailing_rsv(A, k, kind=kind, s=s, seed=seed, acc=acc), 10)
+            w = Vk.cpu().numpy()
+            stored = stored_fn()
+            w_ref, _, _, sig, _, _ = method.trailing_rsv(stored, k, kind, s, seed, gauss_dtype=gdt, return_all=True)
+            r = {"sketch_us": ms_sk * 1e3, "solve_us": ms_solve * 1e3,
+                 "sin_theta_vs_oracle_same_input": metrics.sin_theta(w_ref, w),
+                 "sin_theta_vs_fp64_oracle": metrics.sin_theta(w_oracle64, w),
+                 "residual_over_norm": float(np.linalg.norm(L @ w)) / l2,
+                 "sketch_input_gbs": A_bytes(A) / (ms_sk * 1e-3) / 1e9}
+            if flops:
+                r["mfma_tflops"] = flops / (ms_sk * 1e-3) / 1e12
+                r["mfma_frac_of_dense_peak"] = r["mfma_tflops"] / peak
+            rec3["forms"][name] = r
+            print(f"[suite] {name} {r}", file=sys.stderr, flush=True)
+        print(json.dumps({"suite": "precision", **rec3}), flush=True)
+        del L64, fp8
 
     # ---------------------------------------------------------------- batched
-    print("[suite] batched instances (device generation)", file=sys.stderr, flush=True)
-    shapes = W.batched_sizes(512)
-    As, Vps = [], []
-    for i, (mi, ni) in enumerate(shapes):
-        a, vp = W.planted_matrix_torch(mi, ni, i, dev)
-        As.append(a)
-        Vps.append(vp)
-    ks = [4] * len(As)
-    ss = [4 * ni for _, ni in shapes]
-    seeds = [4000 + i for i in range(len(As))]
-    nsk.trailing_rsv_batched(As, ks, ss, seeds, autotune=True)
-    ms_b, outs = _timed(torch, lambda: nsk.trailing_rsv_batched(As, ks, ss, seeds), 3)
-    total_bytes = sum(mi * ni * 4 for mi, ni in shapes)
-    ang = [metrics.sin_theta(vp.cpu().numpy(), o[0].cpu().numpy()) for vp, o in zip(Vps[:64], outs[:64])]
-    rec4 = {"suite": "batched", "workload": "512 planted instances, m in [5000, 200000], n in [16, 256], "
-                                             "FP32, SRHT s = 4n, k = 4",
-            "ms": ms_b, "instances_per_s": 512 / (ms_b * 1e-3), "input_gb": total_bytes / 1e9,
-            "input_gbs": total_bytes / (ms_b * 1e-3) / 1e9,
-            "planted_subspace_sin_theta_median_first64": float(np.median(ang))}
-    print(json.dumps(rec4), flush=True)
-    del As, outs
+    if want("batched"):
+        print("[suite] batched instances (device generation)", file=sys.stderr, flush=True)
+        shapes = W.batched_sizes(512)
+        As, Vps = [], []
+        for i, (mi, ni) in enumerate(shapes):
+            a, vp = W.planted_matrix_torch(mi, ni, i, dev)
+            As.append(a)
+            Vps.append(vp)
+        ks = [4] * len(As)
+        ss = [4 * ni for _, ni in shapes]
+        seeds = [4000 + i for i in range(len(As))]
+        nsk.trailing_rsv_batched(As, ks, ss, seeds, autotune=True)
+        ms_b, outs = _timed(torch, lambda: nsk.trailing_rsv_batched(As, ks, ss, seeds), 3)
+        total_bytes = sum(mi * ni * 4 for mi, ni in shapes)
+        ang = [metrics.sin_theta(vp.cpu().numpy(), o[0].cpu().numpy()) for vp, o in zip(Vps[:64], outs[:64])]
+        rec4 = {"suite": "batched", "workload": "512 planted instances, m in [5000, 200000], n in [16, 256], "
+                                                 "FP32, SRHT s = 4n, k = 4",
+                "ms": ms_b, "instances_per_s": 512 / (ms_b * 1e-3), "input_gb": total_bytes / 1e9,
+                "input_gbs": total_bytes / (ms_b * 1e-3) / 1e9,
+                "planted_subspace_sin_theta_median_first64": float(np.median(ang))}
+        print(json.dumps(rec4), flush=True)
+        del As, outs
 
     # ---------------------------------------------------------------- gradient
-    print("[suite] TLS gradient workload (host generation)", file=sys.stderr, flush=True)
-    mg, ng, sg = 2_000_000, 256, 1024
-    M, _ = W.tls_matrix(m=mg, n=ng, seed=5)
-    xt = torch.from_numpy(W.tls_target(ng)).to(dev)
-    Mt = torch.from_numpy(M).to(dev)
-    del M
-    A, b = Mt[:, :ng], Mt[:, ng:]
-    ws = nsk._ws(nsk.workspace_bytes(mg, ng + 1, 1, nsk.make_desc("sparse", sg, 5, 8)), dev)
-    state = nsk._ws(nsk.load().nsk_tls_state_bytes(ng, sg, 0), dev)
-    ms_f, (x, _, _) = _timed(torch, lambda: nsk.tls_solve(A, b, kind="sparse", s=sg, seed=5, ws=ws, state=state), 5)
-    nsk.profile_enable(3)
-    for _ in range(3):
-        nsk.tls_solve(A, b, kind="sparse", s=sg, seed=5, ws=ws, state=state)
-    torch.cuda.synchronize()
-    stages, calls = nsk.profile_read()
-    nsk.profile_enable(0)
-    gx = 2.0 * (x - xt)
-    ms_bw, (dA, db) = _timed(torch, lambda: nsk.tls_backward(state, mg, ng, gx, kind="sparse", s=sg, seed=5), 5)
-    gbytes = mg * (ng + 1) * 4
-    rec5 = {"suite": "gradient", "workload": "TLS [A|b] 2,000,000 x 257 FP32, sparse-sign s = 1024, "
-                                             "loss |x - x_target|^2",
-            "forward_ms": ms_f, "forward_stage_ms": {k: v / max(calls, 1) for k, v in stages.items()},
-            "backward_ms": ms_bw, "forward_read_gbs": gbytes / (ms_f * 1e-3) / 1e9,
-            "backward_write_gbs": gbytes / (ms_bw * 1e-3) / 1e9,
-            "loss": float(((x - xt) ** 2).sum())}
-    print(json.dumps(rec5), flush=True)
-    del A, b, Mt, ws, state, dA, db
-
-    # ---------------------------------------------------------------- sketch maintenance
-    print("[suite] sketch maintenance at 1,000,000 x 201", file=sys.stderr, flush=True)
-    M, _ = W.tls_matrix(m=1_000_000, n=200, seed=2)
-    Mt = torch.from_numpy(M).to(dev)
-    mm, NN, ss = Mt.shape[0], Mt.shape[1], 804
-    SA = nsk.sketch(Mt, "sparse", ss, 7)
-    ms_full, _ = _timed(torch, lambda: nsk.sketch(Mt, "sparse", ss, 7), 5)
-    ms_col, _ = _timed(torch, lambda: nsk.sketch(Mt[:, -1:].contiguous(), "sparse", ss, 7, out=SA[:, -1:]), 5)
-    rec6 = {"suite": "maintenance", "workload": "sketch of TLS [A|b] 1,000,000 x 201 FP32, sparse-sign s = 804",
-            "full_sketch_ms": ms_full, "column_update_ms": ms_col}
-    for r in (1, 64):
-        rows = list(range(0, r * 997, 997))
-        vals = Mt[rows].contiguous()
-        nsk.sketch_rows(SA, vals, rows, [-1] * r, mm, kind="sparse", seed=7)
+    if want("gradient"):
+        print("[suite] TLS gradient workload (host generation)", file=sys.stderr, flush=True)
+        mg, ng, sg = 2_000_000, 256, 1024
+        M, _ = W.tls_matrix(m=mg, n=ng, seed=5)
+        xt = torch.from_numpy(W.tls_target(ng)).to(dev)
+        Mt = torch.from_numpy(M).to(dev)
+        del M
+        A, b = Mt[:, :ng], Mt[:, ng:]
+        ws = nsk._ws(nsk.workspace_bytes(mg, ng + 1, 1, nsk.make_desc("sparse", sg, 5, 8)), dev)
+        state = nsk._ws(nsk.load().nsk_tls_state_bytes(ng, sg, 0), dev)
+        ms_f, (x, _, _) = _timed(torch, lambda: nsk.tls_solve(A, b, kind="sparse", s=sg, seed=5, ws=ws, state=state), 5)
+        nsk.profile_enable(3)
+        for _ in range(3):
+            nsk.tls_solve(A, b, kind="sparse", s=sg, seed=5, ws=ws, state=state)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(10):
-            nsk.sketch_rows(SA, vals, rows, [1] * r, mm, kind="sparse", seed=7)
-        torch.cuda.synchronize()
-        rec6[f"row_update_{r}_ms"] = (time.perf_counter() - t0) * 100.0
-    print(json.dumps(rec6), flush=True)
-    del Mt, SA
-
-    # ---------------------------------------------------------------- AAA with sketch reuse
-    print("[suite] AAA with sketch reuse, 1,000,000 points", file=sys.stderr, flush=True)
-    ma, n_max, tol, sa_ = 1_000_000, 100, 1e-10, 200
-    g = torch.Generator(device=dev)
-    g.manual_seed(1)
-    z = torch.sort(torch.rand(ma, dtype=torch.float64, device=dev, generator=g) * 2 - 1).values
-    f = torch.tanh(50 * z)
-    rec7 = {"suite": "aaa", "workload": f"AAA, tanh(50 z) at {ma:,} uniform points of [-1, 1], s = {sa_}, "
-                                        f"tol = {tol:g} max|f|", "kinds": {}}
-    for kind in ("sparse", "srht", "srdct"):
-        nsk.aaa(z, f, n_max, tol, kind=kind, s=sa_, seed=3)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sup, w, hist = nsk.aaa(z, f, n_max, tol, kind=kind, s=sa_, seed=3)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) * 1e3
-        rec7["kinds"][kind] = {"support_points": len(sup), "ms": dt, "ms_per_step": dt / max(1, len(sup)),
-                               "final_max_error": hist[-1]}
-        if kind == "sparse":
-            sup_sparse = sup
-    # the same support points with a fresh sketch of the whole Loewner matrix at every step
-    # (weights only: the loop above also evaluates the error at every point each step)
-    sidx = torch.tensor(sup_sparse, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(1, len(sup_sparse) + 1):
-        zs, fs = z[sidx[:k]], f[sidx[:k]]
-        L = (f[:, None] - fs[None, :]) / (z[:, None] - zs[None, :])
-        L[sidx[:k]] = 0.0
-        nsk.trailing_rsv(L.contiguous(), 1, kind="sparse", s=sa_, seed=3)
-    torch.cuda.synchronize()
-    rec7["fresh_sketch_weights_ms_sparse"] = (time.perf_counter() - t0) * 1e3
-    print(json.dumps(rec7), flush=True)
-    del z, f, L
-
-    # ---------------------------------------------------------------- Table 1 shape: TLS, k = 10
-    print("[suite] TLS with 10 right-hand sides at Table 1's shape", file=sys.stderr, flush=True)
-    n1, k1, s1 = 1000, 10, 2020
-    rec8 = {"suite": "table1", "workload": "TLS [A|B], n = 1000, k = 10, s = 2020, DCT-II sketch, FP64; "
-                                           "A: singular values 1 -> 1e-3, B in range(A) plus noise", "m": {}}
-    for lm in (14, 16, 18):
-        m1 = 1 << lm
-        M1 = W.table1_tls_matrix(m1, n1, k1, seed=16)
-        Mt1 = torch.from_numpy(M1).to(dev)
-        a1, b1 = Mt1[:, :n1], Mt1[:, n1:]
-        nsk.tls_solve_multi(a1, b1, kind="srdct", s=s1, seed=9)
-        torch.cuda.synchronize()
-        nsk.profile_enable(2)
-        t0 = time.perf_counter()
-        for _ in range(2):
-            X, Vk, sk, info = nsk.tls_solve_multi(a1, b1, kind="srdct", s=s1, seed=9)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 2 * 1e3
         stages, calls = nsk.profile_read()
         nsk.profile_enable(0)
-        r = {"ms": dt, "stage_ms": {kk: v / max(calls, 1) for kk, v in stages.items()},
-             "jacobi_sweeps": nsk.read_info(info).sweeps}
-        if lm == 14:  # Table 1's accuracy columns against the exact TLS subspace (LAPACK)
-            _, _, vt = np.linalg.svd(M1, full_matrices=False)
-            Vo = vt[-k1:].T
-            Vg = Vk.cpu().numpy()
-            r["residual_ratio"] = float(np.linalg.norm(M1 @ Vg) / np.linalg.norm(M1 @ Vo))
-            r["sin_theta_vs_exact"] = float(np.linalg.norm(Vg - Vo @ (Vo.T @ Vg), 2))
-        rec8["m"][f"2^{lm}"] = r
-        print(f"[suite] table1 m=2^{lm} {r}", file=sys.stderr, flush=True)
-        del Mt1, a1, b1, M1
-    print(json.dumps(rec8), flush=True)
+        gx = 2.0 * (x - xt)
+        ms_bw, (dA, db) = _timed(torch, lambda: nsk.tls_backward(state, mg, ng, gx, kind="sparse", s=sg, seed=5), 5)
+        gbytes = mg * (ng + 1) * 4
+        rec5 = {"suite": "gradient", "workload": "TLS [A|b] 2,000,000 x 257 FP32, sparse-sign s = 1024, "
+                                                 "loss |x - x_target|^2",
+                "forward_ms": ms_f, "forward_stage_ms": {k: v / max(calls, 1) for k, v in stages.items()},
+                "backward_ms": ms_bw, "forward_read_gbs": gbytes / (ms_f * 1e-3) / 1e9,
+                "backward_write_gbs": gbytes / (ms_bw * 1e-3) / 1e9,
+                "loss": float(((x - xt) ** 2).sum())}
+        print(json.dumps(rec5), flush=True)
+        del A, b, Mt, ws, state, dA, db
+
+    # ---------------------------------------------------------------- sketch maintenance
+    if want("maintenance"):
+        print("[suite] sketch maintenance at 1,000,000 x 201", file=sys.stderr, flush=True)
+        M, _ = W.tls_matrix(m=1_000_000, n=200, seed=2)
+        Mt = torch.from_numpy(M).to(dev)
+        mm, NN, ss = Mt.shape[0], Mt.shape[1], 804
+        SA = nsk.sketch(Mt, "sparse", ss, 7)
+        ms_full, _ = _timed(torch, lambda: nsk.sketch(Mt, "sparse", ss, 7), 5)
+        ms_col, _ = _timed(torch, lambda: nsk.sketch(Mt[:, -1:].contiguous(), "sparse", ss, 7, out=SA[:, -1:]), 5)
+        rec6 = {"suite": "maintenance", "workload": "sketch of TLS [A|b] 1,000,000 x 201 FP32, sparse-sign s = 804",
+                "full_sketch_ms": ms_full, "column_update_ms": ms_col}
+        for r in (1, 64):
+            rows = list(range(0, r * 997, 997))
+            vals = Mt[rows].contiguous()
+            nsk.sketch_rows(SA, vals, rows, [-1] * r, mm, kind="sparse", seed=7)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                nsk.sketch_rows(SA, vals, rows, [1] * r, mm, kind="sparse", seed=7)
+            torch.cuda.synchronize()
+            rec6[f"row_update_{r}_ms"] = (time.perf_counter() - t0) * 100.0
+        print(json.dumps(rec6), flush=True)
+        del Mt, SA
+
+    # ---------------------------------------------------------------- AAA with sketch reuse
+    if want("aaa"):
+        print("[suite] AAA with sketch reuse, 1,000,000 points", file=sys.stderr, flush=True)
+        ma, n_max, tol, sa_ = 1_000_000, 100, 1e-10, 200
+        g = torch.Generator(device=dev)
+        g.manual_seed(1)
+        z = torch.sort(torch.rand(ma, dtype=torch.float64, device=dev, generator=g) * 2 - 1).values
+        f = torch.tanh(50 * z)
+        rec7 = {"suite": "aaa", "workload": f"AAA, tanh(50 z) at {ma:,} uniform points of [-1, 1], s = {sa_}, "
+                                            f"tol = {tol:g} max|f|", "kinds": {}}
+        for kind in ("sparse", "srht", "srdct"):
+            nsk.aaa(z, f, n_max, tol, kind=kind, s=sa_, seed=3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sup, w, hist = nsk.aaa(z, f, n_max, tol, kind=kind, s=sa_, seed=3)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3
+            rec7["kinds"][kind] = {"support_points": len(sup), "ms": dt, "ms_per_step": dt / max(1, len(sup)),
+                                   "final_max_error": hist[-1]}
+            if kind == "sparse":
+                sup_sparse = sup
+        # the same support points with a fresh sketch of the whole Loewner matrix at every step
+        # (weights only: the loop above also evaluates the error at every point each step)
+        sidx = torch.tensor(sup_sparse, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, len(sup_sparse) + 1):
+            zs, fs = z[sidx[:k]], f[sidx[:k]]
+            L = (f[:, None] - fs[None, :]) / (z[:, None] - zs[None, :])
+            L[sidx[:k]] = 0.0
+            nsk.trailing_rsv(L.contiguous(), 1, kind="sparse", s=sa_, seed=3)
+        torch.cuda.synchronize()
+        rec7["fresh_sketch_weights_ms_sparse"] = (time.perf_counter() - t0) * 1e3
+        print(json.dumps(rec7), flush=True)
+        del z, f, L
+
+    # ---------------------------------------------------------------- Table 1 shape: TLS, k = 10
+    if want("table1"):
+        print("[suite] TLS with 10 right-hand sides at Table 1's shape", file=sys.stderr, flush=True)
+        n1, k1, s1 = 1000, 10, 2020
+        rec8 = {"suite": "table1", "workload": "TLS [A|B], n = 1000, k = 10, s = 2020, DCT-II sketch, FP64; "
+                                               "A: singular values 1 -> 1e-3, B in range(A) plus noise", "m": {}}
+        for lm in (14, 16, 18):
+            m1 = 1 << lm
+            M1 = W.table1_tls_matrix(m1, n1, k1, seed=16)
+            Mt1 = torch.from_numpy(M1).to(dev)
+            a1, b1 = Mt1[:, :n1], Mt1[:, n1:]
+            nsk.tls_solve_multi(a1, b1, kind="srdct", s=s1, seed=9)
+            torch.cuda.synchronize()
+            nsk.profile_enable(2)
+            t0 = time.perf_counter()
+            for _ in range(2):
+                X, Vk, sk, info = nsk.tls_solve_multi(a1, b1, kind="srdct", s=s1, seed=9)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 2 * 1e3
+            stages, calls = nsk.profile_read()
+            nsk.profile_enable(0)
+            r = {"ms": dt, "stage_ms": {kk: v / max(calls, 1) for kk, v in stages.items()},
+                 "jacobi_sweeps": nsk.read_info(info).sweeps}
+            if lm == 14:  # Table 1's accuracy columns against the exact TLS subspace (LAPACK)
+                _, _, vt = np.linalg.svd(M1, full_matrices=False)
+                Vo = vt[-k1:].T
+                Vg = Vk.cpu().numpy()
+                r["residual_ratio"] = float(np.linalg.norm(M1 @ Vg) / np.linalg.norm(M1 @ Vo))
+                r["sin_theta_vs_exact"] = float(np.linalg.norm(Vg - Vo @ (Vo.T @ Vg), 2))
+            rec8["m"][f"2^{lm}"] = r
+            print(f"[suite] table1 m=2^{lm} {r}", file=sys.stderr, flush=True)
+            del Mt1, a1, b1, M1
+        print(json.dumps(rec8), flush=True)
 
 
 def A_bytes(A):
@@ -336,6 +354,8 @@ def main():
                     help="sketch of the timed solves (the headline workload is sparse sign)")
     ap.add_argument("--suite", action="store_true",
                     help="measure the precision (Loewner), batched and gradient workloads instead; one JSON line each")
+    ap.add_argument("--only", default=None,
+                    help="with --suite: comma-separated subset of " + ",".join(SUITE_PARTS))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 1 GiB and exit (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -360,7 +380,14 @@ def main():
     import workloads as W
 
     if args.suite:
-        suite(nsk, W, torch, np)
+        only = None
+        if args.only:
+            only = set(args.only.split(","))
+            bad = only - set(SUITE_PARTS)
+            if bad:
+                print(f"unknown suite part(s): {sorted(bad)}; choose from {SUITE_PARTS}", file=sys.stderr)
+                sys.exit(2)
+        suite(nsk, W, torch, np, only)
         return
 
     nsk.load()
