@@ -6,8 +6,8 @@
 // Jacobi sweep over their 2 kBigW columns (the circle ordering again, one column pair per wave,
 // workgroup barriers between its rounds), so the block pair's columns stay in the XCD's L2
 // while it works on them and the whole matrix crosses HBM once per block round instead of once
-// per column round.  Block rounds end in a grid barrier, whose device-scope fences publish the
-// rotated columns to the next round's readers on other CUs.  A pair (p, q) rotates when
+// per column round.  Block rounds end in a grid barrier (one cache write-back per workgroup),
+// which publishes the rotated columns to the next round's readers on other CUs.  A pair (p, q) rotates when
 // |x_p . x_q| > N u |x_p| |x_q| (rule and formulas as in the register-blocked Jacobi), V (N x N,
 // from the identity) is rotated alongside, and a sweep with no rotation -- every column pair
 // within tolerance -- ends the loop for every workgroup at once (the count is read after the
@@ -28,8 +28,14 @@ constexpr int kBigW = 4;                // columns per block (256 threads: room 
 constexpr int kBigThreads = 64 * kBigW;  // one wave per column pair of a block pair's round
 
 // counters: [0, max_sweeps) rotations per sweep, [max_sweeps, 2 max_sweeps) largest relative
-// cosine bits per sweep, then sweeps performed and the converged flag
-__host__ __device__ inline size_t svd_big_counter_bytes(int max_sweeps) { return (size_t)(2 * max_sweeps + 2) * 8; }
+// cosine bits per sweep, then sweeps performed and the converged flag; then, 64-byte aligned,
+// the grid barrier's words
+__host__ __device__ inline size_t svd_big_bar_offset(int max_sweeps) {
+  return ((size_t)(2 * max_sweeps + 2) * 8 + 63) & ~(size_t)63;
+}
+__host__ __device__ inline size_t svd_big_counter_bytes(int max_sweeps) {
+  return svd_big_bar_offset(max_sweeps) + (size_t)kAgentBarWords * 4;
+}
 
 // x <- c x - sn y, y <- sn x + c y over n entries of two columns, lane-strided; CH > 0: the
 // pair is held in registers (n <= 64 CH), all loads issued before the first use
@@ -188,7 +194,9 @@ __global__ __launch_bounds__(kBigThreads) void svd_big_jacobi_kernel(double* __r
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t gt = (int64_t)blockIdx.x * kBigThreads + threadIdx.x, GT = (int64_t)gridDim.x * kBigThreads;
   for (int64_t e = gt; e < (int64_t)N * N; e += GT) V[e] = (e / N == e % N) ? 1.0 : 0.0;
-  for (int64_t i = gt; i < 2 * max_sweeps + 2; i += GT) counters[i] = 0;
+  for (int64_t i = gt; i < (int64_t)(svd_big_counter_bytes(max_sweeps) / 8); i += GT) counters[i] = 0;
+  unsigned* bar = reinterpret_cast<unsigned*>(reinterpret_cast<unsigned char*>(counters) + svd_big_bar_offset(max_sweeps));
+  unsigned epoch = 0;
   grid.sync();
   const int nb = (N + kBigW - 1) / kBigW;
   const int nb_even = nb + (nb & 1);
@@ -211,11 +219,11 @@ __global__ __launch_bounds__(kBigThreads) void svd_big_jacobi_kernel(double* __r
           __syncthreads();  // the next inner round's pairs read this one's columns
         }
       }
-      grid.sync();
+      agent_barrier(bar, gridDim.x, epoch);
     }
     if (lane == 0 && nrot) atomicAdd(&counters[sw], (unsigned long long)nrot);
     if (lane == 0 && off > 0) atomicMax(&counters[max_sweeps + sw], (unsigned long long)__double_as_longlong(off));
-    grid.sync();
+    agent_barrier(bar, gridDim.x, epoch);
     sweeps = sw + 1;
     if (__hip_atomic_load(&counters[sw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
       conv = 1;

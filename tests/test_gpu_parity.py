@@ -492,6 +492,24 @@ def test_large_path_trailing_vectors(lib):
     assert inf.converged and abs(inf.sigma_max - sig[0]) <= 1e-12 * sig[0]
 
 
+def test_large_path_streamed_columns(lib):
+    """s = 2200 is past the register chunks of the multi-workgroup Jacobi (s <= 2048): the
+    column pairs of SA are streamed from memory, V's pair still held in registers.  The
+    expected vectors are LAPACK's SVD of the oracle's sketch (the oracle's Jacobi, pinned to
+    LAPACK, takes about 40 s at this size)."""
+    m, N, k, s = 9000, 330, 3, 2200
+    a = W.planted_matrix(m, N, k=k, level=1e-4, seed=(9, N))[0].astype(np.float64)
+    Vk, sk, info = lib.trailing_rsv(t(a), k, kind="sparse", s=s, seed=13)
+    torch.cuda.synchronize()
+    sa = operators.sketch(a, "sparse", s, 13)
+    _, sig, vt = np.linalg.svd(sa, full_matrices=False)
+    vk_ref, sk_ref = vt[-k:].T, sig[-k:]
+    assert_vectors(vk_ref, Vk.cpu().numpy(), vec_tol(sig, k))
+    assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-10, atol=1e-14 * sig[0])
+    inf = lib.read_info(info)
+    assert inf.converged and abs(inf.sigma_max - sig[0]) <= 1e-12 * sig[0]
+
+
 def test_multi_rhs_tls_matches_oracle(lib):
     m, n, k, s = 5000, 40, 3, 172
     rng = np.random.default_rng(15)
