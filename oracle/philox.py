@@ -1,8 +1,9 @@
 """Philox4x32-10, written from the published description (Salmon, Moraes, Dror, Shaw,
 "Parallel random numbers: as easy as 1, 2, 3", SC'11).
 
-Pinned by: bit equality with rocRAND's independent ``philox4x32_10_engine`` (a library
-routine compiled from its source header in the tests), plus uniformity statistics.
+Pinned by: the generator's published known-answer vectors (a fixture in the tests), bit
+equality with rocRAND's independent ``philox4x32_10_engine`` (a library routine compiled from
+its source header in the tests), plus uniformity statistics.
 
 A block maps a 128-bit counter ``(c0, c1, c2, c3)`` and a 64-bit key ``(k0, k1)`` to four
 32-bit words.  One round multiplies ``c0`` and ``c2`` by the two Philox multipliers, keeps

@@ -68,6 +68,17 @@ def test_philox_matches_rocrand(rocrand_exe):
         assert [int(x) for x in w] == ref
 
 
+def test_philox_known_answer_vectors():
+    """The generator's published known-answer vectors (zero, all-ones and pi-digit inputs)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        c0, c1, c2, c3, k0, k1, *want = (int(x, 16) for x in r)
+        got = philox4x32(c0, c1, c2, c3, k0, k1)
+        assert [int(w) for w in got] == want, (r, [hex(int(w)) for w in got])
+
+
 def test_philox_vectorised_equals_scalar():
     idx = np.arange(0, 5000, 37, dtype=np.uint64)
     v = np.stack(block(99, idx, 3, 2))
