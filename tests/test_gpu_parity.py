@@ -510,6 +510,22 @@ def test_large_path_streamed_columns(lib):
     assert inf.converged and abs(inf.sigma_max - sig[0]) <= 1e-12 * sig[0]
 
 
+def test_large_path_maximum_width(lib):
+    """The largest accepted shape of the SVD: N = 1024 columns with s = 2048 (the Hadamard
+    kind's largest sketch), planted k = 2.  Expected vectors: LAPACK's SVD of the oracle's
+    sketch."""
+    m, N, k, s = 4096, 1024, 2, 2048
+    a = W.planted_matrix(m, N, k=k, level=1e-4, seed=(10, N))[0].astype(np.float64)
+    Vk, sk, info = lib.trailing_rsv(t(a), k, kind="srht", s=s, seed=14)
+    torch.cuda.synchronize()
+    sa = operators.sketch(a, "srht", s, 14)
+    _, sig, vt = np.linalg.svd(sa, full_matrices=False)
+    assert_vectors(vt[-k:].T, Vk.cpu().numpy(), vec_tol(sig, k))
+    assert np.allclose(sk.cpu().numpy(), sig[-k:], rtol=1e-10, atol=1e-14 * sig[0])
+    inf = lib.read_info(info)
+    assert inf.converged and abs(inf.sigma_max - sig[0]) <= 1e-12 * sig[0]
+
+
 def test_multi_rhs_tls_matches_oracle(lib):
     m, n, k, s = 5000, 40, 3, 172
     rng = np.random.default_rng(15)
