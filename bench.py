@@ -361,7 +361,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the sketch shards by rows across GPUs by design, but this build runs on one).", file=sys.stderr)
+              "(the sketch shards by rows across GPUs by design; the library runs on one GPU).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

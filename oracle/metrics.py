@@ -16,8 +16,8 @@
                           ``sin Theta(V_3, [V~_2, V~_3])``, each infinite where its gap
                           condition fails.
 * ``expected_rho``     -- first-order mean residual ratio for a Gaussian sketch,
-                          ``sqrt(1 + (N - k) / (s - N + k - 1))`` (inverse-Wishart mean; a
-                          derivation of this build, not a result printed in the paper).
+                          ``sqrt(1 + (N - k) / (s - N + k - 1))`` (inverse-Wishart mean;
+                          derived from the sketch's distribution, not printed in the paper).
 
 Pinned by: closed forms (orthogonal rotations of known angle), Table 1's printed residual
 ratios, and the inequalities themselves on realised sketches.
