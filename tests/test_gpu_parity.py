@@ -2,10 +2,10 @@
 
 Tolerances: sketches with FP64 accumulation agree with the oracle's FP64 product to
 rounding (1e-12 relative); plain-FP32 and narrow-operand sketches to the FP32 bound (1e-4
-relative, the spec FP32 tolerance).  Trailing vectors agree to
+relative: FP32 accumulation over the sketch's terms).  Trailing vectors agree to
 max(1e-10, sqrt(N) u kappa_gap) with kappa_gap = sigma_1 / (sigma_{N-k} - sigma_{N-k+1})
-of the oracle's SA (the conditioning floor of the vector), and residual
-ratios to 1e-10 (FP64 arithmetic) or 1e-4 (FP32 arithmetic).
+of the oracle's SA (the conditioning floor of a singular subspace under perturbations of
+size u sigma_1), and residual ratios to 1e-10 (FP64 arithmetic) or 1e-4 (FP32 arithmetic).
 """
 import math
 
