@@ -431,7 +431,7 @@ def test_autograd_function(lib):
     loss = ((x - t(xt)) ** 2).sum()
     loss.backward()
     grad, _, lref = method.tls_grad(M, xt, "sparse", s, 10)
-    assert abs(float(loss) - lref) <= 1e-10 * lref
+    assert abs(float(loss.detach()) - lref) <= 1e-10 * lref
     g = np.hstack([A.grad.cpu().numpy(), b.grad.cpu().numpy()[:, None]])
     assert rel(g, grad) < 1e-10
 
