@@ -482,15 +482,42 @@ hipError_t launch_sketch(const Operand& op, const SketchPlan& p, hipStream_t st)
 }
 
 // ================================================================================ reduce
+// Sum of the groups' partials for each entry of SA, in a fixed order.  A workgroup of
+// kRedThreads takes 256 / SL consecutive entries; slice sl of an entry adds groups sl,
+// sl + SL, ... into four accumulators taken in turn (so that its loads are independent), the
+// four are added pairwise and the SL slices are added in slice order through LDS.  Several
+// slices per entry keep the loads in flight when s N is small and the groups many.
+constexpr int kRedThreads = 256;
+
 template <typename TP>
-__global__ void reduce_kernel(Operand op, const TP* __restrict__ partial, int groups, int s, int N,
-                              double scale, int kind, double* __restrict__ sa_rm, int64_t ld_rm,
-                              double* __restrict__ sa_cm, int64_t ld_cm) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)s * N) return;
+__global__ __launch_bounds__(kRedThreads) void reduce_kernel(Operand op, const TP* __restrict__ partial, int groups,
+                                                             int s, int N, int SL, double scale, int kind,
+                                                             double* __restrict__ sa_rm, int64_t ld_rm,
+                                                             double* __restrict__ sa_cm, int64_t ld_cm) {
+  __shared__ double part[kRedThreads];
+  const int out = kRedThreads / SL;
+  const int o = threadIdx.x % out, sl = threadIdx.x / out;
+  const int64_t total = (int64_t)s * N;
+  const int64_t idx = (int64_t)blockIdx.x * out + o;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  if (idx < total) {
+    const TP* p = partial + idx;
+    const size_t stride = (size_t)SL * total;
+    int g = sl;
+    for (; g + 3 * SL < groups; g += 4 * SL) {
+      a0 += (double)p[(size_t)g * total];
+      a1 += (double)p[(size_t)g * total + stride];
+      a2 += (double)p[(size_t)g * total + 2 * stride];
+      a3 += (double)p[(size_t)g * total + 3 * stride];
+    }
+    for (; g < groups; g += SL) a0 += (double)p[(size_t)g * total];
+  }
+  part[threadIdx.x] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (sl != 0 || idx >= total) return;
+  double acc = part[o];
+  for (int k = 1; k < SL; ++k) acc += part[k * out + o];
   const int i = (int)(idx / N), c = (int)(idx % N);
-  double acc = 0;
-  for (int g = 0; g < groups; ++g) acc += (double)partial[(size_t)g * s * N + idx];
   double sc = scale;
   if (kind == NSK_GAUSSIAN && op.dtype == NSK_F8E4M3) sc = ldexp(sc, column_exp(op, c));
   acc *= sc;
@@ -518,14 +545,17 @@ hipError_t launch_reduce(const Operand& op, const SketchPlan& p, double* sa_rm, 
     f64part = false;
   }
   const int64_t total = (int64_t)p.s * p.N;
-  const int threads = 256;
-  const unsigned blocks = (unsigned)((total + threads - 1) / threads);
+  // slices per entry: about eight groups each, at most 16
+  int sl = 1;
+  while (sl < 16 && groups >= 16 * sl) sl *= 2;
+  const int out = kRedThreads / sl;
+  const unsigned blocks = (unsigned)((total + out - 1) / out);
   if (f64part)
-    reduce_kernel<double><<<blocks, threads, 0, st>>>(op, (const double*)p.partial, groups, p.s, p.N, scale,
-                                                      p.kind, sa_rm, ld_rm, sa_cm, ld_cm);
+    reduce_kernel<double><<<blocks, kRedThreads, 0, st>>>(op, (const double*)p.partial, groups, p.s, p.N, sl, scale,
+                                                          p.kind, sa_rm, ld_rm, sa_cm, ld_cm);
   else
-    reduce_kernel<float><<<blocks, threads, 0, st>>>(op, (const float*)p.partial, groups, p.s, p.N, scale,
-                                                     p.kind, sa_rm, ld_rm, sa_cm, ld_cm);
+    reduce_kernel<float><<<blocks, kRedThreads, 0, st>>>(op, (const float*)p.partial, groups, p.s, p.N, sl, scale,
+                                                         p.kind, sa_rm, ld_rm, sa_cm, ld_cm);
   return hipGetLastError();
 }
 
