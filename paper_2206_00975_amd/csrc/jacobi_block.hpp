@@ -154,30 +154,60 @@ __device__ inline void jacobi_intra_block(double* __restrict__ R, int ld, int bl
   for (int b = 0; b < BQ; ++b)
 #pragma unroll
     for (int r = 0; r < NR; ++r) X[b][r] = b < B ? p[(size_t)b * ld + lane + 64 * r] : 0.0;
-  for (int q = 0; q < BQ - 1; ++q) {
-    double sab[3];
+  // The squared norms are reduced once, then carried as in the block rounds: lanes of pair pi
+  // hold alpha = |x_pi|^2 and beta = |x_{BQ-1-pi}|^2, updated by each rotation and moved with
+  // the circle shift; only the inner products are reduced per step.
+  double alpha, beta;
+  {
+    constexpr int SHB = 6 - ceil_log2(B);
+    double v[16];
 #pragma unroll
-    for (int which = 0; which < 3; ++which) {
+    for (int b = 0; b < B; ++b) {
+      v[b] = 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[b] += X[b][r] * X[b][r];
+    }
+    const double nrm = reduce_t<B>(v, lane);  // lane l: position l >> SHB
+    const int pq = pi < H ? pi : 0;
+    alpha = __shfl(nrm, pq << SHB, 64);
+    beta = BQ - 1 - pq < B ? __shfl(nrm, (BQ - 1 - pq) << SHB, 64) : 0.0;  // the padding column is zero
+  }
+  const int up = lane + (1 << SH) < 64 ? lane + (1 << SH) : lane;  // a lane of pair pi + 1
+  const int down = lane >= (1 << SH) ? lane - (1 << SH) : lane;    // a lane of pair pi - 1
+  for (int q = 0; q < BQ - 1; ++q) {
+    double g;
+    {
       double v[16];
 #pragma unroll
       for (int i = 0; i < H; ++i) {
         v[i] = 0;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const double a = X[i][r], b = X[BQ - 1 - i][r];
-          v[i] += which == 0 ? a * a : which == 1 ? b * b : a * b;
-        }
+        for (int r = 0; r < NR; ++r) v[i] += X[i][r] * X[BQ - 1 - i][r];
       }
-      sab[which] = reduce_t<H>(v, lane);
+      g = reduce_t<H>(v, lane);
     }
     double c, s, t;
     bool act;
-    jacobi_params(sab[0], sab[1], sab[2], cx.tol, c, s, t, act);
+    jacobi_params(alpha, beta, g, cx.tol, c, s, t, act);
     if (lead) {
-      const double ab = sab[0] * sab[1];
-      if (ab > 0) cx.offmax = fmax(cx.offmax, sab[2] * sab[2] * rcp_nr(ab));
+      const double ab = alpha * beta;
+      if (ab > 0) cx.offmax = fmax(cx.offmax, g * g * rcp_nr(ab));
       if (act) cx.rotations++;
       lg[pi] = make_double2(c, s);
+    }
+    if (act) {
+      alpha = fmax(alpha - t * g, 0.0);
+      beta = fmax(beta + t * g, 0.0);
+    }
+    if constexpr (H > 1) {
+      // after the shift position b takes b + 1 (1 <= b < BQ - 1) and BQ - 1 takes 1: pair 0 keeps
+      // alpha and takes pair 1's alpha as beta; pair i >= 1 takes pair i - 1's beta, and pair
+      // i + 1's alpha (i < H - 1) or its own beta (i = H - 1) as alpha
+      const double a_up = __shfl(alpha, up, 64), b_down = __shfl(beta, down, 64);
+      const double na = pi == 0 ? alpha : pi + 1 < H ? a_up : beta;
+      const double nbv = pi == 0 ? a_up : b_down;
+      alpha = na;
+      beta = nbv;
     }
 #pragma unroll
     for (int i = 0; i < H; ++i) rot_cols<NR>(X[i], X[BQ - 1 - i], bcast_d(c, i << SH), bcast_d(s, i << SH));
