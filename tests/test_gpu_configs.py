@@ -1,0 +1,223 @@
+"""Parity with the FP64 oracle of the instantiations the workload configurations select.
+
+* Batched Algorithm 1 with instances past 128 columns: sketch tiles with s > 512 and the
+  one-workgroup Jacobi at three and four rows per lane, next to narrow instances; and one
+  batch run after the autotuner has chosen tile heights.
+* The TLS workload in FP32 at s = 1024 (Section 4): the forward sketch (8-column tiles), the
+  solve, the gradient written in FP32 and the autograd function on FP32 tensors.
+* The Gaussian sketch at the AAA-shaped Loewner matrix's shape (99,900 x 100, s = 200) in
+  BF16 and E4M3.
+* Sampled rows of the gradient at the full 2,000,000 x 257 FP32 size.
+
+Sketches are compared column by column: the largest relative error over the columns of SA,
+so that a few wrong entries of a small-norm column cannot hide behind the others.
+Tolerances: FP64 accumulation 1e-12 (rounding of sums of a few thousand terms); FP32
+results 1e-6 relative (one FP32 rounding, 2^-24, of an FP64-accurate value, with margin);
+plain-FP32 accumulation and narrow operands 1e-4; trailing vectors max(1e-10, sqrt(N) u
+kappa_gap) as in the other parity tests.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import draws, method, metrics, operators
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+DEV = "cuda:0"
+
+
+def t(x, dtype=None):
+    return torch.tensor(np.ascontiguousarray(x), device=DEV, dtype=dtype)
+
+
+def colrel(a, b):
+    """Largest relative 2-norm error over the columns."""
+    num = np.linalg.norm(a - b, axis=0)
+    den = np.maximum(np.linalg.norm(b, axis=0), 1e-300)
+    return float(np.max(num / den))
+
+
+def rowrel(a, b):
+    num = np.linalg.norm(a - b, axis=1)
+    den = np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+    return float(np.max(num / den))
+
+
+def vec_tol(sigma, k, u=U):
+    N = sigma.size
+    kappa = sigma[0] / max(sigma[N - k - 1] - sigma[N - k], 1e-300)
+    return max(1e-10, math.sqrt(N) * u * kappa)
+
+
+def assert_vectors(ref, got, tol):
+    gram = got.T @ got
+    assert np.abs(gram - np.eye(gram.shape[0])).max() < 1e-9, gram
+    err = metrics.sin_theta(ref, got)
+    assert err <= tol, (err, tol)
+
+
+# ---------------------------------------------------------------------------- batched
+# n > 128: the batched kernel's s > 512 sketch tiles and its Jacobi at 3 and 4 rows per lane
+# (n = 129..192 and 193..256); narrow instances alongside, as in the 512-instance workload.
+WIDE_SHAPES = [(12_000, 256), (9000, 200), (6000, 129), (5000, 16), (8000, 60), (7000, 140)]
+
+
+@pytest.fixture(scope="module")
+def wide_batch():
+    As = [W.planted_matrix(m, n, seed=(4, 300 + i))[0] for i, (m, n) in enumerate(WIDE_SHAPES)]
+    ks = [4] * len(As)
+    ss = [4 * n for _, n in WIDE_SHAPES]
+    seeds = [2000 + i for i in range(len(As))]
+    refs = []
+    for a, k, s, seed in zip(As, ks, ss, seeds):
+        vk, sk, sa, sig, V, _ = method.trailing_rsv(a.astype(np.float64), k, "srht", s, seed, return_all=True)
+        refs.append((vk, sk, sig))
+    return As, ks, ss, seeds, refs
+
+
+def _check_batch(lib, outs, wide_batch):
+    As, ks, ss, seeds, refs = wide_batch
+    for i, ((Vk, sk, info), (vk_ref, sk_ref, sig), k) in enumerate(zip(outs, refs, ks)):
+        assert_vectors(vk_ref, Vk.cpu().numpy(), vec_tol(sig, k))
+        assert np.allclose(sk.cpu().numpy(), sk_ref, rtol=1e-9, atol=1e-13 * sig[0]), i
+        assert lib.read_info(info).converged, i
+
+
+def test_batched_wide_instances(lib, wide_batch):
+    As, ks, ss, seeds, _ = wide_batch
+    outs = lib.trailing_rsv_batched([t(a) for a in As], ks, ss, seeds)
+    torch.cuda.synchronize()
+    _check_batch(lib, outs, wide_batch)
+
+
+def test_batched_after_autotune(lib, wide_batch):
+    """The autotuner times tile heights on the caller's instances, then the batch runs with the
+    chosen ones; the results still match the oracle."""
+    As, ks, ss, seeds, _ = wide_batch
+    try:
+        outs = lib.trailing_rsv_batched([t(a) for a in As], ks, ss, seeds, autotune=True)
+        torch.cuda.synchronize()
+        _check_batch(lib, outs, wide_batch)
+        # the batch used the tuned table: every n bucket of the batch has an entry in range
+        for _, n in WIDE_SHAPES:
+            assert 1 <= lib.tune_lookup(n) <= 64
+    finally:
+        lib.tune_clear()
+
+
+# ---------------------------------------------------------------------------- FP32 TLS at s = 1024
+M5, N5, S5 = 5000, 256, 1024
+
+
+@pytest.fixture(scope="module")
+def tls32():
+    M, _ = W.tls_matrix(m=M5, n=N5, seed=5, dtype=np.float32)
+    xt = W.tls_target(N5)
+    grad, x_ref, loss = method.tls_grad(M.astype(np.float64), xt, "sparse", S5, 5)
+    return M, xt, grad, x_ref, loss
+
+
+def test_sparse_sketch_fp32_s1024(lib):
+    """s = 1024 with FP32 input selects 8-column tiles of the sparse-sign kernel."""
+    a = np.random.default_rng(17).standard_normal((20_000, 257)).astype(np.float32)
+    ref = operators.sketch(a.astype(np.float64), "sparse", S5, 77)
+    SA = lib.sketch(t(a), "sparse", S5, 77).cpu().numpy()
+    assert colrel(SA, ref) < 1e-12, colrel(SA, ref)
+    SA32 = lib.sketch(t(a), "sparse", S5, 77, acc="f32").cpu().numpy()
+    assert colrel(SA32, ref) < 1e-4, colrel(SA32, ref)
+
+
+def test_tls_fp32_solve_and_gradient(lib, tls32):
+    M, xt, grad, x_ref, _ = tls32
+    Mt = t(M)
+    A, b = Mt[:, :N5].contiguous(), Mt[:, N5].contiguous()
+    x, state, _ = lib.tls_solve(A, b, kind="sparse", s=S5, seed=5)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(x.cpu().numpy() - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    gx = 2.0 * (x - t(xt))
+    dA, db = lib.tls_backward(state, M5, N5, gx, kind="sparse", s=S5, seed=5, out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    assert dA.dtype == torch.float32 and db.dtype == torch.float32
+    g = np.hstack([dA.cpu().numpy().astype(np.float64), db.cpu().numpy().astype(np.float64)[:, None]])
+    assert colrel(g, grad) < 1e-6, colrel(g, grad)
+    assert rowrel(g, grad) < 1e-6, rowrel(g, grad)
+
+
+def test_tls_autograd_fp32_tensors(lib, tls32):
+    M, xt, grad, _, loss_ref = tls32
+    A = t(M[:, :N5]).requires_grad_(True)
+    b = t(M[:, N5]).requires_grad_(True)
+    x = lib.TLSSketch.apply(A, b, S5, 5, "sparse", 8)
+    loss = ((x - t(xt)) ** 2).sum()
+    loss.backward()
+    assert A.grad.dtype == torch.float32 and b.grad.dtype == torch.float32
+    assert abs(float(loss.detach()) - loss_ref) <= 1e-8 * loss_ref
+    g = np.hstack([A.grad.cpu().numpy().astype(np.float64), b.grad.cpu().numpy().astype(np.float64)[:, None]])
+    assert colrel(g, grad) < 1e-6, colrel(g, grad)
+
+
+# ---------------------------------------------------------------------------- Gaussian, Loewner shape
+@pytest.fixture(scope="module")
+def loewner():
+    L, _, _, _ = W.loewner_aaa()
+    return L
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "e4m3"])
+def test_gaussian_sketch_loewner_shape(lib, loewner, fmt):
+    L = loewner
+    m, n = L.shape
+    s = 2 * n
+    L64 = t(L)
+    if fmt == "bf16":
+        at = L64.to(torch.bfloat16)
+        stored = at.to(torch.float64).cpu().numpy()
+        SA = lib.sketch(at, "gauss", s, 3).cpu().numpy()
+    else:
+        e = np.floor(np.log2(448.0 / np.abs(L).max(axis=0))).astype(np.int8)
+        q = (L64 * t(2.0 ** e.astype(np.float64))[None, :]).to(torch.float8_e4m3fn)
+        stored = q.to(torch.float64).cpu().numpy() * 2.0 ** (-e[None, :].astype(np.float64))
+        SA = lib.sketch([(q, t(-e))], "gauss", s, 3).cpu().numpy()
+    ref = operators.sketch(stored, "gauss", s, 3, gauss_dtype=fmt)
+    assert colrel(SA, ref) < 1e-4, colrel(SA, ref)
+
+
+# ---------------------------------------------------------------------------- full-size gradient rows
+MG, NG, SG = 2_000_000, 256, 1024
+
+
+def test_tls_gradient_rows_full_size(lib):
+    """The 2,000,000 x 257 FP32 gradient workload: the oracle's v, w and SA at full size, and
+    the rank-2 gradient p w^T + q v^T (p = S^T (SA v), q = S^T (SA w), the oracle's sparse S)
+    at sampled rows, against the FP32 dA, db written by the backward kernel."""
+    M, _ = W.tls_matrix(m=MG, n=NG, seed=5)
+    xt = W.tls_target(NG)
+    Mt = torch.from_numpy(M).to(DEV)
+    A, b = Mt[:, :NG], Mt[:, NG:]
+    x, state, _ = lib.tls_solve(A, b, kind="sparse", s=SG, seed=5)
+    gx = 2.0 * (x - t(xt))
+    dA, db = lib.tls_backward(state, MG, NG, gx, kind="sparse", s=SG, seed=5, out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    idx = np.concatenate([[0, 1, 2, MG // 2, MG - 2, MG - 1],
+                          np.random.default_rng(3).choice(MG, 200, replace=False)])
+    g_gpu = np.hstack([dA[idx].cpu().numpy().astype(np.float64), db[idx].cpu().numpy().astype(np.float64)[:, None]])
+    x_gpu = x.cpu().numpy()
+    del dA, db, A, b, Mt
+    # oracle: the solve at full size and the gradient's factors, then the sampled rows only
+    x_ref, v, sigma, V, sa = method.tls_solve(M.astype(np.float64), "sparse", SG, 5)
+    del M
+    g = 2.0 * (x_ref - xt)
+    gbar = -np.concatenate([g, [g @ x_ref]]) / v[-1]
+    coef = (V.T @ gbar)[:-1] / (sigma[-1] ** 2 - sigma[:-1] ** 2)
+    w = V[:, :-1] @ coef
+    rows, sg = draws.sparse(5, MG, SG, 8)
+    rows, sg = rows[idx], sg[idx].astype(np.float64) / math.sqrt(8)
+    p = (sg * (sa @ v)[rows]).sum(axis=1)
+    q = (sg * (sa @ w)[rows]).sum(axis=1)
+    g_ref = np.outer(p, w) + np.outer(q, v)
+    assert np.linalg.norm(x_gpu - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+    assert rowrel(g_gpu, g_ref) < 1e-5, rowrel(g_gpu, g_ref)
