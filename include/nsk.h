@@ -11,11 +11,17 @@
  * ---------------------------------------
  * - Matrices are row-major.  A matrix operand is a list of column blocks (nsk_operand),
  *   so [A | b] of Section 4 is passed as two blocks without a concatenated copy.
- * - Device pointers are HIP device memory owned by the caller.  The library allocates
- *   nothing in the calls below: scratch comes from the caller's workspace, sized by the
- *   matching *_workspace_bytes query.  Host pointers are marked "host".
+ * - Device pointers are HIP device memory owned by the caller.  The library allocates no
+ *   device memory in the calls below: scratch comes from the caller's workspace, sized by the
+ *   matching *_workspace_bytes query.  Host pointers are marked "host".  The host-built
+ *   records that nsk_trailing_rsv_batched and nsk_sketch_rows copy to the device go through
+ *   a few library-owned pinned host buffers (allocated on first use, grown when a larger
+ *   batch arrives, kept until the process ends); a call reuses such a buffer only after the
+ *   copy that last used it has completed.
  * - `stream` is a hipStream_t passed as void*.  Device entry points only enqueue work on
- *   it and return; outputs (including nsk_info) are valid after the stream has drained.
+ *   it and return (nsk_aaa and the autotuner excepted, as documented there): every random
+ *   draw, the SRFT row sample included, is made on the device; outputs (including nsk_info)
+ *   are valid after the stream has drained.
  * - Every entry point returns an nsk_status; no exceptions cross the ABI.  Argument
  *   errors are detected on the host before anything is enqueued.  NaN and Inf inputs are
  *   not checked: they propagate to the outputs.
@@ -125,7 +131,8 @@ size_t nsk_workspace_bytes(int64_t m, int64_t N, int64_t k, const nsk_desc* d);
  * SA (device): s x N row-major FP64 output with row stride ldsa >= N.
  * Errors: NSK_EINVAL if m < N, s <= N, s > m, a block has cols < 1 or ld < cols, nblocks
  *   outside 1..4, zeta outside 1..min(s,32); NSK_EUNSUPPORTED for other dtype/kind pairs
- *   and for s > 2048 with NSK_SRHT or NSK_SRDCT, NSK_HRHT with acc = NSK_F32, m > 2^21 or s + m_p/1024 > 10240;
+ *   and for s > 2048 or m > 2^31 with NSK_SRHT or NSK_SRDCT, NSK_HRHT with acc = NSK_F32, m > 2^21 or
+ *   s + m_p/1024 > 10240;
  *   NSK_EWORKSPACE if
  *   ws_bytes < nsk_workspace_bytes(m, N, 1, d).
  */
@@ -215,9 +222,9 @@ int nsk_aaa(const double* z, const double* f, int64_t m, int32_t n_max, double t
  * values A(j, :), an appended one with the values it was added with.
  * A column update is nsk_sketch of the new columns into the matching columns of SA (SA pointer
  * offset, same ldsa); a column downdate drops the column of SA.
- * rows, ops (host, r entries): row indices >= 0 and signs +-1.  SA (device): s x N row-major
- * FP64, row stride ldsa >= N.  ws (device): nsk_update_workspace_bytes(r, d) bytes.
- * The call waits for its small host-to-device copies (the stream is synchronised once).
+ * rows, ops (host, r entries): row indices >= 0 and signs +-1, copied into a pinned staging
+ * buffer before the call returns (the caller may reuse them at once).  SA (device): s x N
+ * row-major FP64, row stride ldsa >= N.  ws (device): nsk_update_workspace_bytes(r, d) bytes.
  * NSK_HRHT returns NSK_EUNSUPPORTED (its columns are not regenerated one at a time).
  * Errors: as nsk_sketch for (m, N, d) and the operand; NSK_EINVAL for a negative row index, a
  * sign other than +-1, r < 0 or r > 2^30; NSK_EWORKSPACE for a short workspace.  r = 0 does
@@ -242,9 +249,11 @@ int nsk_residual(const nsk_operand* blocks, int32_t nblocks, int64_t m, const do
  * workgroup takes sketch tiles from a longest-first queue; the workgroup that completes
  * an instance's last tile reduces its partial sketches and runs its QR + Jacobi.
  * probs (host array): per-instance operand (single block), sizes, sketch size, seed, k
- *   and device output pointers.  base: kind (NSK_SRHT; other kinds return
- *   NSK_EUNSUPPORTED), acc, max_sweeps; its s and seed are ignored.  Tile sizes come from the
- *   autotuner.
+ *   and device output pointers; read before the call returns.  base: kind (NSK_SRHT; other
+ *   kinds return NSK_EUNSUPPORTED), acc, max_sweeps; its s and seed are ignored.  Tile sizes
+ *   come from the autotuner.  Each instance's row sample is drawn on the device.
+ * Errors: NSK_EINVAL for an instance with n outside 1..256, s outside n+1..min(m, 1024),
+ *   k outside 1..n, ld < n or a null pointer, or mixed dtypes; NSK_EUNSUPPORTED for m > 2^31.
  */
 typedef struct nsk_problem {
   const void* A;        /* device, row-major m x n, NSK_F32 or NSK_F64                     */
@@ -337,6 +346,10 @@ int nsk_draw_srht_rows(uint64_t seed, int64_t m, int64_t s, int64_t* rows);  /* 
 int nsk_draw_sparse(uint64_t seed, int64_t m, int64_t s, int32_t zeta, int32_t* rows,
                     int8_t* signs);                                      /* host, m x zeta */
 int nsk_draw_signs_device(uint64_t seed, int64_t m, int8_t* d, void* stream);
+/* rows (device): the s sorted sampled rows of [0, 2^ceil(log2 m)) that nsk_draw_srht_rows
+ * returns, drawn by the parallel resolution of Floyd's rule the sketches use (s <= 2048,
+ * m <= 2^31). */
+int nsk_draw_srht_rows_device(uint64_t seed, int64_t m, int64_t s, int32_t* rows, void* stream);
 int nsk_draw_sparse_device(uint64_t seed, int64_t m, int64_t s, int32_t zeta, int32_t* rows,
                            int8_t* signs, void* stream);
 /* G (device): s x (j1 - j0) row-major FP32, entries G_hat[i, j0 + c] rounded to dtype

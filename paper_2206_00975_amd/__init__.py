@@ -110,6 +110,7 @@ _SIGS = {
     "nsk_draw_srht_rows": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
     "nsk_draw_sparse": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P, _P]),
     "nsk_draw_signs_device": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, _P, _P]),
+    "nsk_draw_srht_rows_device": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "nsk_draw_sparse_device": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P,
                                               _P, _P]),
     "nsk_draw_gaussian_device": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
@@ -162,7 +163,7 @@ def _blocks(A):
             t, exp = t
         if t.dim() == 1:
             t = t.unsqueeze(1)
-        if t.stride(1) != 1:
+        if t.stride(1) != 1 and t.shape[1] != 1:
             raise ValueError("operand blocks must be row-major with unit column stride")
         if m is None:
             m = t.shape[0]
@@ -508,6 +509,13 @@ def draw_signs_device(seed, m, device="cuda"):
     d = torch.empty(m, dtype=torch.int8, device=device)
     _check("nsk_draw_signs_device", load().nsk_draw_signs_device(seed, m, d.data_ptr(), _stream(d.device)))
     return d
+
+
+def draw_srht_rows_device(seed, m, s, device="cuda"):
+    rows = torch.empty(s, dtype=torch.int32, device=device)
+    _check("nsk_draw_srht_rows_device", load().nsk_draw_srht_rows_device(seed, m, s, rows.data_ptr(),
+                                                                          _stream(rows.device)))
+    return rows
 
 
 def draw_sparse_device(seed, m, s, zeta, device="cuda"):

@@ -5,7 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <thread>
+#include <mutex>
 #include <vector>
 
 #include "nsk.h"
@@ -17,8 +17,8 @@ size_t sparse_lds_bytes(int s, int zeta, int acc);
 size_t gauss_lds_bytes(int s, int N, int dtype);
 int gauss_tiles_per_wave(int s, int N);
 size_t batched_lds_bytes(int s_max, int n_max);
-hipError_t launch_batched(const void* insts, const void* tiles, int ntiles, int* counters, int ncounters,
-                          int dtype, int acc, int grid, size_t lds, hipStream_t st);
+hipError_t launch_batched(const void* insts, int count, const void* tiles, int ntiles, int* counters, int dtype,
+                          int acc, int grid, size_t lds, hipStream_t st);
 size_t batch_inst_bytes();
 size_t batch_tile_bytes();
 void batch_fill_inst(void* dst, const Operand& op, int64_t m, int N, int s, int k, int groups, int ctiles,
@@ -148,7 +148,8 @@ int check_desc(const nsk_desc* d, int64_t m, int64_t N) {
     const int z = dflt_zeta(d);
     if (z < 1 || z > 32 || z > d->s || d->s > 65535) return NSK_EINVAL;
   }
-  if ((d->kind == NSK_SRHT || d->kind == NSK_SRDCT) && d->s > 2048) return NSK_EUNSUPPORTED;
+  if ((d->kind == NSK_SRHT || d->kind == NSK_SRDCT) && (d->s > 2048 || next_pow2(m) > ((int64_t)1 << 31)))
+    return NSK_EUNSUPPORTED;
   if (d->kind == NSK_HRHT && (d->acc == NSK_F32 || next_pow2(m) > ((int64_t)1 << 21) || rht_hash_cols(m, (int)d->s) == 0))
     return NSK_EUNSUPPORTED;
   if (d->kind == NSK_SPARSE_SIGN && sparse_lds_bytes((int)d->s, dflt_zeta(d), dflt_acc(d)) > 160 * 1024)
@@ -214,15 +215,67 @@ void srht_rows_host(uint64_t seed, int64_t pool, int64_t s, std::vector<int64_t>
   std::sort(out.begin(), out.end());
 }
 
-int upload_rows(uint64_t seed, int64_t pool, int64_t s, int* dst, hipStream_t st) {
-  std::vector<int64_t> r;
-  srht_rows_host(seed, pool, s, r);
-  std::vector<int> r32(r.begin(), r.end());
-  if (hipMemcpyAsync(dst, r32.data(), r32.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
-    return NSK_EDEVICE;
-  // the host vector dies at return: make sure the copy has consumed it
-  if (hipStreamSynchronize(st) != hipSuccess) return NSK_EDEVICE;
-  return NSK_OK;
+// The SRFT row sample drawn on the device into the workspace (stream-ordered, no host copy).
+int draw_rows(uint64_t seed, int64_t pool, int64_t s, int* dst, hipStream_t st) {
+  return launch_srht_rows(seed, pool, (int)s, dst, st) == hipSuccess ? NSK_OK : NSK_EDEVICE;
+}
+
+// ------------------------------------------------------------------ pinned staging
+// Host-built records that a call copies to the device (the batched call's instance and tile
+// lists, the row indices and signs of a row update) pass through library-owned pinned host
+// buffers, so the copies are asynchronous and the call returns without waiting for the stream.
+// A slot stays owned by its copy until the event recorded after that copy has completed; a
+// later call that reuses the slot waits for that copy only (normally long finished).  Slots
+// grow on demand (hipHostMalloc) and are kept for the life of the process.
+struct StageSlot {
+  void* ptr = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  int device = -1;
+  bool inflight = false;
+};
+constexpr int kStageSlots = 4;
+std::mutex g_stage_mu;
+StageSlot g_stage[kStageSlots];
+int g_stage_next = 0;
+
+// Takes a slot of at least `bytes` and locks the staging until stage_release.  Returns the slot
+// index, or -1 (lock released) on a runtime error.
+int stage_acquire(size_t bytes) {
+  g_stage_mu.lock();
+  const int i = g_stage_next;
+  g_stage_next = (g_stage_next + 1) % kStageSlots;
+  StageSlot& sl = g_stage[i];
+  int device = 0;
+  bool ok = hipGetDevice(&device) == hipSuccess;
+  if (ok && sl.inflight) ok = hipEventSynchronize(sl.ev) == hipSuccess;
+  sl.inflight = false;
+  if (ok && sl.cap < bytes) {
+    if (sl.ptr) (void)hipHostFree(sl.ptr);
+    sl.ptr = nullptr;
+    sl.cap = 0;
+    ok = hipHostMalloc(&sl.ptr, bytes, hipHostMallocDefault) == hipSuccess;
+    if (ok) sl.cap = bytes;
+  }
+  if (ok && (sl.ev == nullptr || sl.device != device)) {
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    sl.ev = nullptr;
+    ok = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess;
+    sl.device = device;
+  }
+  if (!ok) {
+    g_stage_mu.unlock();
+    return -1;
+  }
+  return i;
+}
+
+// Marks the copies enqueued from slot i on st and unlocks the staging.
+int stage_release(int i, hipStream_t st) {
+  const bool ok = hipEventRecord(g_stage[i].ev, st) == hipSuccess;
+  g_stage[i].inflight = ok;
+  g_stage_mu.unlock();
+  return ok ? NSK_OK : NSK_EDEVICE;
 }
 
 SketchPlan make_plan(const nsk_desc* d, int64_t m, int64_t N, int dtype, unsigned char* ws, const Layout& L) {
@@ -276,7 +329,7 @@ int run_sketch(const Operand& op, const nsk_desc* d, int64_t m, int64_t N, unsig
   prof_begin(st);
   if (d->kind == NSK_SRHT || d->kind == NSK_SRDCT) {
     const int64_t pool = d->kind == NSK_SRHT ? next_pow2(m) : srdct_pool(m);
-    const int rc = upload_rows(d->seed, pool, d->s, reinterpret_cast<int*>(ws + L.rows), st);
+    const int rc = draw_rows(d->seed, pool, d->s, reinterpret_cast<int*>(ws + L.rows), st);
     if (rc) return rc;
   }
   if (d->kind == NSK_SRDCT) {
@@ -596,15 +649,18 @@ int nsk_sketch_rows(const nsk_operand* blocks, int32_t nblocks, int64_t r, const
   int* srows = reinterpret_cast<int*>(w);
   int64_t* idx = reinterpret_cast<int64_t*>(w + align_up((size_t)d->s * 4));
   int8_t* sg = reinterpret_cast<int8_t*>(w + align_up((size_t)d->s * 4) + align_up((size_t)r * 8));
-  if (hipMemcpyAsync(idx, rows, (size_t)r * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(sg, ops, (size_t)r, hipMemcpyHostToDevice, st) != hipSuccess)
-    return NSK_EDEVICE;
+  const size_t rb = align_up((size_t)r * 8);
+  const int slot = stage_acquire(rb + (size_t)r);
+  if (slot < 0) return NSK_EDEVICE;
+  unsigned char* hs = static_cast<unsigned char*>(g_stage[slot].ptr);
+  std::memcpy(hs, rows, (size_t)r * 8);
+  std::memcpy(hs + rb, ops, (size_t)r);
+  const bool copied = hipMemcpyAsync(idx, hs, (size_t)r * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+                      hipMemcpyAsync(sg, hs + rb, (size_t)r, hipMemcpyHostToDevice, st) == hipSuccess;
+  if ((rc = stage_release(slot, st)) || !copied) return NSK_EDEVICE;
   if (d->kind == NSK_SRHT || d->kind == NSK_SRDCT) {
-    // synchronises the stream, so the host arrays above have been consumed as well
     const int64_t pool = d->kind == NSK_SRHT ? next_pow2(m) : srdct_pool(m);
-    if ((rc = upload_rows(d->seed, pool, d->s, srows, st))) return rc;
-  } else if (hipStreamSynchronize(st) != hipSuccess) {
-    return NSK_EDEVICE;
+    if ((rc = draw_rows(d->seed, pool, d->s, srows, st))) return rc;
   }
   SketchPlan p{};
   p.kind = d->kind;
@@ -716,7 +772,7 @@ int nsk_tls_backward(const nsk_desc* d, int64_t m, int64_t n, const void* state,
   size_t o[9];
   tls_state_layout(n, d->s, dflt_sweeps(d), o);
   SketchPlan p = make_plan(d, m, N, NSK_F64, w, L);
-  if (d->kind == NSK_SRHT && (rc = upload_rows(d->seed, next_pow2(m), d->s, reinterpret_cast<int*>(w + L.rows), st)))
+  if (d->kind == NSK_SRHT && (rc = draw_rows(d->seed, next_pow2(m), d->s, reinterpret_cast<int*>(w + L.rows), st)))
     return rc;
   TlsBack tb;
   tb.sa_rm = reinterpret_cast<const double*>(S + o[0]);
@@ -749,6 +805,7 @@ static int batch_plan(const nsk_problem* probs, int32_t count, const nsk_desc* b
     if (q.n < 1 || q.n > 256 || q.m < q.n || q.s <= q.n || q.s > q.m || q.s > 1024 || q.k < 1 || q.k > q.n ||
         q.ld < q.n || !q.A || !q.Vk || !q.sigma_k)
       return NSK_EINVAL;
+    if (q.m > ((int64_t)1 << 31)) return NSK_EUNSUPPORTED;
     if (q.dtype != NSK_F32 && q.dtype != NSK_F64) return NSK_EUNSUPPORTED;
     const int rpt = tuned_rows_per_tile((int)q.n, q.m, q.dtype, dflt_acc(base));
     const int64_t nb = (q.m + 1023) / 1024;
@@ -802,8 +859,16 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
     if (probs[a].n != probs[b].n) return probs[a].n > probs[b].n;
     return probs[a].m > probs[b].m;
   });
-  std::vector<unsigned char> hinst((size_t)count * batch_inst_bytes());
-  std::vector<unsigned char> htile((size_t)B.ntiles * batch_tile_bytes());
+  int dtype = probs[0].dtype;
+  for (int i = 1; i < count; ++i)
+    if (probs[i].dtype != dtype) return NSK_EINVAL;
+  // instance and tile records, built in a pinned staging slot and copied asynchronously
+  const size_t ib = align_up((size_t)count * batch_inst_bytes());
+  const size_t tb = (size_t)B.ntiles * batch_tile_bytes();
+  const int slot = stage_acquire(ib + tb);
+  if (slot < 0) return NSK_EDEVICE;
+  unsigned char* hinst = static_cast<unsigned char*>(g_stage[slot].ptr);
+  unsigned char* htile = hinst + ib;
   std::vector<size_t> rows_off(count);
   size_t roff = 0;
   int s_max = 0, n_max = 0;
@@ -811,23 +876,6 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
   for (int i = 0; i < count; ++i) {
     rows_off[i] = roff;
     roff += align_up((size_t)probs[i].s * 4);
-  }
-  // every instance's sampled rows, drawn on host threads (independent per instance)
-  std::vector<int> hrows(roff / 4, 0);
-  {
-    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    const int nthr = (int)std::min<unsigned>(hw, (unsigned)((count + 31) / 32));
-    auto work = [&](int part) {
-      std::vector<int64_t> r;
-      for (int i = part; i < count; i += nthr) {
-        srht_rows_host(probs[i].seed, next_pow2(probs[i].m), probs[i].s, r);
-        for (size_t t = 0; t < r.size(); ++t) hrows[rows_off[i] / 4 + t] = (int)r[t];
-      }
-    };
-    std::vector<std::thread> pool;
-    for (int part = 1; part < nthr; ++part) pool.emplace_back(work, part);
-    work(0);
-    for (std::thread& th : pool) th.join();
   }
   for (int i = 0; i < count; ++i) {
     const nsk_problem& q = probs[i];
@@ -852,7 +900,7 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
     int* order = reinterpret_cast<int*>(base_i + o); o = align_up(o + n * 4);
     double* cn = reinterpret_cast<double*>(base_i + o); o = align_up(o + n * 8);
     void* jr = base_i + o;
-    batch_fill_inst(hinst.data() + (size_t)i * batch_inst_bytes(), op, q.m, (int)q.n, (int)q.s, (int)q.k,
+    batch_fill_inst(hinst + (size_t)i * batch_inst_bytes(), op, q.m, (int)q.n, (int)q.s, (int)q.k,
                     B.groups[i], (int)((q.n + kBatchCols - 1) / kBatchCols), dflt_sweeps(base), q.seed,
                     reinterpret_cast<const int*>(w + B.rows + rows_off[i]), partial, sa, R, lg, sig, order, cn, jr,
                     q.Vk, q.sigma_k, q.info);
@@ -862,15 +910,11 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
     const int i = ord[oi];
     const int ct = (int)((probs[i].n + kBatchCols - 1) / kBatchCols);
     for (int g = 0; g < B.groups[i]; ++g)
-      for (int c = 0; c < ct; ++c) batch_fill_tile(htile.data() + (size_t)(t++) * batch_tile_bytes(), i, c, g);
+      for (int c = 0; c < ct; ++c) batch_fill_tile(htile + (size_t)(t++) * batch_tile_bytes(), i, c, g);
   }
-  int dtype = probs[0].dtype;
-  for (int i = 1; i < count; ++i)
-    if (probs[i].dtype != dtype) return NSK_EINVAL;
-  if (hipMemcpyAsync(w + B.insts, hinst.data(), hinst.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(w + B.tiles, htile.data(), htile.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(w + B.rows, hrows.data(), hrows.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
-    return NSK_EDEVICE;
+  const bool copied = hipMemcpyAsync(w + B.insts, hinst, ib, hipMemcpyHostToDevice, st) == hipSuccess &&
+                      hipMemcpyAsync(w + B.tiles, htile, tb, hipMemcpyHostToDevice, st) == hipSuccess;
+  if ((rc = stage_release(slot, st)) || !copied) return NSK_EDEVICE;
   int devid = 0, cus = 256;
   if (hipGetDevice(&devid) == hipSuccess) {
     int v = 0;
@@ -879,11 +923,8 @@ int nsk_trailing_rsv_batched(const nsk_problem* probs, int32_t count, const nsk_
   const size_t lds = batched_lds_bytes(s_max, n_max);
   const int per_cu = lds <= 80 * 1024 ? 2 : 1;
   const int grid = std::min(B.ntiles, cus * per_cu);
-  rc = dev(launch_batched(w + B.insts, w + B.tiles, B.ntiles, reinterpret_cast<int*>(w + B.counters), count + 1,
-                          dtype, acc, grid, lds, st));
-  if (rc) return rc;
-  // host staging vectors die at return
-  return dev(hipStreamSynchronize(st));
+  return dev(launch_batched(w + B.insts, count, w + B.tiles, B.ntiles, reinterpret_cast<int*>(w + B.counters), dtype,
+                            acc, grid, lds, st));
 }
 
 // ------------------------------------------------------------------------------ profiler
@@ -960,6 +1001,11 @@ int nsk_draw_sparse(uint64_t seed, int64_t m, int64_t s, int32_t zeta, int32_t* 
 int nsk_draw_signs_device(uint64_t seed, int64_t m, int8_t* d, void* stream) {
   if (m < 1 || !d) return NSK_EINVAL;
   return dev(launch_draw_signs(seed, m, d, (hipStream_t)stream));
+}
+
+int nsk_draw_srht_rows_device(uint64_t seed, int64_t m, int64_t s, int32_t* rows, void* stream) {
+  if (m < 1 || m > ((int64_t)1 << 31) || s < 1 || s > 2048 || s > next_pow2(m) || !rows) return NSK_EINVAL;
+  return dev(launch_srht_rows(seed, next_pow2(m), (int)s, rows, (hipStream_t)stream));
 }
 
 int nsk_draw_sparse_device(uint64_t seed, int64_t m, int64_t s, int32_t zeta, int32_t* rows, int8_t* signs,

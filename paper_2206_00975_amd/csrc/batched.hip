@@ -44,6 +44,13 @@ __global__ void batched_reset(int* counters, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counters[i] = 0;
 }
 
+// Every instance's row sample, one workgroup per instance.
+__global__ __launch_bounds__(kFloydThreads) void batched_rows_kernel(const BatchInst* __restrict__ insts) {
+  __shared__ __align__(16) unsigned char smem[floyd_smem_bytes()];
+  const BatchInst& I = insts[blockIdx.x];
+  floyd_rows_block(I.seed, next_pow2(I.m), I.s, const_cast<int*>(I.rows), smem);
+}
+
 constexpr int kBatchThreads = SrhtTile<kBatchCols>::kThreads;
 
 template <typename TIn, typename TAcc>
@@ -113,10 +120,13 @@ size_t batched_lds_bytes(int s_max, int n_max) {
   return a > b ? a : b;
 }
 
-hipError_t launch_batched(const void* insts, const void* tiles, int ntiles, int* counters, int ncounters,
-                          int dtype, int acc, int grid, size_t lds, hipStream_t st) {
+// counters: the tile counter followed by one completion counter per instance (count + 1).
+hipError_t launch_batched(const void* insts, int count, const void* tiles, int ntiles, int* counters, int dtype,
+                          int acc, int grid, size_t lds, hipStream_t st) {
+  const int ncounters = count + 1;
   batched_reset<<<(ncounters + 255) / 256, 256, 0, st>>>(counters, ncounters);
   const BatchInst* I = static_cast<const BatchInst*>(insts);
+  batched_rows_kernel<<<count, kFloydThreads, 0, st>>>(I);
   const BatchTile* T = static_cast<const BatchTile*>(tiles);
 #define NSK_BATCH(TI, TA)                                                                           \
   {                                                                                                 \

@@ -261,6 +261,9 @@ hipError_t launch_aaa_join(const double* z, const double* f, int64_t m, int64_t 
                            uint8_t* mask, double* row, int64_t* idx, int8_t* ops, double* col, hipStream_t st);
 hipError_t launch_aaa_transpose(const double* a, int64_t ld, int s, int N, double* cm, hipStream_t st);
 
+// The SRFT row sample (s <= 2048 sorted distinct rows of [0, pool), pool <= 2^31) drawn on
+// the device into rows[0..s).
+hipError_t launch_srht_rows(uint64_t seed, int64_t pool, int s, int* rows, hipStream_t st);
 hipError_t launch_draw_signs(uint64_t seed, int64_t m, int8_t* d, hipStream_t st);
 hipError_t launch_draw_sparse(uint64_t seed, int64_t m, int s, int zeta, int32_t* rows,
                               int8_t* signs, hipStream_t st);

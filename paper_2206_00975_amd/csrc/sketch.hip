@@ -260,17 +260,16 @@ __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m,
       float g[4] = {0, 0, 0, 0};
       if (j < m) {
         const Words r = philox(seed, (uint64_t)j, (uint32_t)q, kGauss);
-        box_muller(r.w[0], r.w[1], g[0], g[1]);
-        box_muller(r.w[2], r.w[3], g[2], g[3]);
+        gauss_hat4<FP8 ? NSK_F8E4M3 : NSK_BF16>(r, g);
       }
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         const int i = 4 * q + h;
         E e;
         if constexpr (FP8) {
-          e = (i < s) ? (E)e4m3_bits(e4m3_round(g[h])) : (E)0;
+          e = (i < s) ? (E)e4m3_bits(g[h]) : (E)0;
         } else {
-          e = (i < s) ? (E)bf16_round(g[h]) : (E)0.0f;
+          e = (i < s) ? (E)g[h] : (E)0.0f;
         }
         gs[(size_t)i * kGK + kk] = e;
       }
@@ -560,6 +559,17 @@ hipError_t launch_reduce(const Operand& op, const SketchPlan& p, double* sa_rm, 
 }
 
 // =============================================================================== draws
+__global__ __launch_bounds__(kFloydThreads) void floyd_rows_kernel(uint64_t seed, int64_t pool, int s, int* rows) {
+  __shared__ __align__(16) unsigned char smem[floyd_smem_bytes()];
+  floyd_rows_block(seed, pool, s, rows, smem);
+}
+
+hipError_t launch_srht_rows(uint64_t seed, int64_t pool, int s, int* rows, hipStream_t st) {
+  if (s < 1 || s > kFloydMax || pool < s || pool > ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  floyd_rows_kernel<<<1, kFloydThreads, 0, st>>>(seed, pool, s, rows);
+  return hipGetLastError();
+}
+
 __global__ void draw_signs_kernel(uint64_t seed, int64_t m, int8_t* d) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
@@ -590,17 +600,18 @@ __global__ void draw_gauss_kernel(uint64_t seed, int s, int64_t j0, int64_t j1, 
   if (4 * q >= s) return;
   const Words r = philox(seed, (uint64_t)(j0 + cc), (uint32_t)q, kGauss);
   float g[4];
-  box_muller(r.w[0], r.w[1], g[0], g[1]);
-  box_muller(r.w[2], r.w[3], g[2], g[3]);
+  if (dtype == NSK_BF16) {
+    gauss_hat4<NSK_BF16>(r, g);
+  } else if (dtype == NSK_F8E4M3) {
+    gauss_hat4<NSK_F8E4M3>(r, g);
+  } else {
+    box_muller(r.w[0], r.w[1], g[0], g[1]);
+    box_muller(r.w[2], r.w[3], g[2], g[3]);
+  }
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
     const int i = 4 * q + h;
-    if (i < s) {
-      float v = g[h];
-      if (dtype == NSK_BF16) v = bf16_round(v);
-      else if (dtype == NSK_F8E4M3) v = e4m3_round(v);
-      G[(size_t)i * ncol + cc] = v;
-    }
+    if (i < s) G[(size_t)i * ncol + cc] = g[h];
   }
 }
 

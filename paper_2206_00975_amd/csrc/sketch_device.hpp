@@ -37,15 +37,197 @@ __device__ inline uint32_t e4m3_bits(float r) {  // r already rounded
   return sign | (e << 3) | mant;
 }
 
-// Box-Muller on FP32 hardware transcendentals: v_log_f32 is log2, v_sin/cos_f32 take
-// their argument in revolutions.  Two words (a, b) give r cos(2 pi v), r sin(2 pi v) with
-// u = (a + 1) 2^-32, v = b 2^-32, r = sqrt(-2 ln u).
+// Round an FP64 value to bfloat16 (8 significant bits) and to E4M3 (4 significant bits, quantum
+// 2^-9 below 2^-6, saturating at 448), to nearest even, directly from FP64.
+__device__ inline float bf16_round_f64(double x) {
+  uint64_t b = (uint64_t)__double_as_longlong(x);
+  b = (b + 0x00000FFFFFFFFFFFull + ((b >> 45) & 1u)) & 0xFFFFE00000000000ull;
+  return (float)__longlong_as_double((long long)b);
+}
+__device__ inline float e4m3_round_f64(double x) {
+  if (fabs(x) < 0x1p-6) return (float)(rint(x * 512.0) * (1.0 / 512.0));
+  uint64_t b = (uint64_t)__double_as_longlong(x);
+  b = (b + 0x0000FFFFFFFFFFFFull + ((b >> 49) & 1u)) & 0xFFFE000000000000ull;
+  return fminf(fmaxf((float)__longlong_as_double((long long)b), -448.0f), 448.0f);
+}
+
+// Box-Muller from two 32-bit words (a, b): u = (a + 1) 2^-32, v = b 2^-32, r = sqrt(-2 ln u),
+// (g0, g1) = (r cos 2 pi v, r sin 2 pi v).  FP32 evaluation on the hardware transcendentals
+// (v_log_f32 is log2, v_sin/cos_f32 take revolutions):
+//  * for u <= 1/2, log2 of u itself; for u > 1/2, 1 - u = (~a) 2^-32 exactly and
+//    ln(1 - x) = ln(w) x / (w - 1) with w = fl(1 - x) (the log1p identity), so that radii of
+//    u near 1 keep their relative accuracy;
+//  * the angle as the signed revolution (int32) b 2^-32 in [-1/2, 1/2), the same point of the
+//    circle, where the hardware sine and cosine are most accurate.
+// Measured over all 2^32 values of each word on gfx950: radius relative error <= 1.9e-7,
+// sine and cosine absolute error <= 1.9e-7.
+struct GaussPair { float g0, g1, r; };
+__device__ inline GaussPair box_muller32(uint32_t a, uint32_t b) {
+  float l2;
+  if (a < 0x80000000u) {
+    l2 = __builtin_amdgcn_logf(fmaf((float)a, 0x1p-32f, 0x1p-32f));
+  } else {
+    const float x = (float)(~a) * 0x1p-32f;
+    const float w = 1.0f - x;
+    l2 = (w == 1.0f) ? -x * 1.4426950408889634f : __builtin_amdgcn_logf(w) * (x / (1.0f - w));
+  }
+  const float r = __builtin_sqrtf(-1.3862943611198906f * l2);
+  const float v = (float)(int32_t)b * 0x1p-32f;
+  return GaussPair{r * __builtin_amdgcn_cosf(v), r * __builtin_amdgcn_sinf(v), r};
+}
+
 __device__ inline void box_muller(uint32_t a, uint32_t b, float& g0, float& g1) {
-  const float u = fmaf((float)a, 0x1p-32f, 0x1p-32f);
-  const float v = (float)b * 0x1p-32f;
-  const float r = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));
-  g0 = r * __builtin_amdgcn_cosf(v);
-  g1 = r * __builtin_amdgcn_sinf(v);
+  const GaussPair p = box_muller32(a, b);
+  g0 = p.g0;
+  g1 = p.g1;
+}
+
+// Entry h (0 or 1) of the pair in FP64, the formulas of the definition evaluated in FP64
+// (u and v exact).
+__device__ inline double box_muller64(uint32_t a, uint32_t b, int h) {
+  const double u = ((double)a + 1.0) * 0x1p-32, v = (double)b * 0x1p-32;
+  const double r = sqrt(-2.0 * log(u));
+  const double ang = 6.283185307179586 * v;
+  return h ? r * sin(ang) : r * cos(ang);
+}
+
+// Rounded Gaussian entries G_hat (FMT: NSK_BF16 or NSK_F8E4M3) of one Philox block: words
+// (0, 1) give entries 0, 1 and words (2, 3) entries 2, 3.  The FP32 value g is within
+// E = 2^-21 (|g| + r) of the exact Gaussian (about twice the measured bounds); when g - E and
+// g + E round to the same narrow value, rounding is monotone, so the exact value rounds to it
+// as well.  Otherwise (a rounding tie within E, rare) the entry is recomputed in FP64 and
+// rounded from FP64: the rounding decision is then the one taken on the FP64 value.
+template <int FMT> __device__ inline float round_fmt(float x) {
+  if constexpr (FMT == NSK_BF16) return bf16_round(x); else return e4m3_round(x);
+}
+template <int FMT> __device__ inline float round_fmt64(double x) {
+  if constexpr (FMT == NSK_BF16) return bf16_round_f64(x); else return e4m3_round_f64(x);
+}
+template <int FMT> __device__ inline void gauss_hat4(const Words& w, float (&out)[4]) {
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const uint32_t a = w.w[2 * p], b = w.w[2 * p + 1];
+    const GaussPair g = box_muller32(a, b);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float x = h ? g.g1 : g.g0;
+      const float e = 0x1p-21f * (fabsf(x) + g.r);
+      const float lo = round_fmt<FMT>(x - e), hi = round_fmt<FMT>(x + e);
+      float q = round_fmt<FMT>(x);
+      if (lo != hi) q = round_fmt64<FMT>(box_muller64(a, b, h));
+      out[2 * p + h] = q;
+    }
+  }
+}
+
+// ========================================================================= sampled rows
+// The SRFT's row sample R (s distinct rows of [0, pool), sorted), drawn on the device.
+// Floyd's rule takes the draws in sequence: draw t (i_t = pool - s + t) takes
+// x_t = floor(u_t (i_t + 1) / 2^64), u_t from words 0 and 1 of Philox block (t, 0, stream 2),
+// unless an earlier draw already holds x_t, in which case it takes i_t.  The sequence is
+// resolved here in parallel.  An earlier draw t' holds x_t' or i_t', and i_t' exceeds every
+// x of an earlier draw, so x_t is already held exactly when
+//   (a) x_t = x_t' for some t' < t (draw t' kept x_t', or x_t' was held before t'), or
+//   (b) t' = x_t - (pool - s) satisfies 0 <= t' < t and draw t' took its i_t'.
+// (b) links draw t to one earlier draw, so "t takes i_t" is the OR of (a) along a chain of
+// decreasing indices, evaluated by pointer jumping in ceil(log2 s) rounds.  The s values
+// taken are distinct; each is stored at its rank.  One workgroup of kFloydThreads threads.
+constexpr int kFloydThreads = 1024;
+constexpr int kFloydMax = 2 * kFloydThreads;  // draws per workgroup (two per thread)
+__host__ __device__ constexpr size_t floyd_smem_bytes() { return (size_t)kFloydMax * 12; }
+
+__device__ inline void floyd_rows_block(uint64_t seed, int64_t pool, int s, int* __restrict__ out,
+                                        unsigned char* smem) {
+  int* xs = reinterpret_cast<int*>(smem);     // x_t, later the value taken
+  int* link = xs + kFloydMax;                  // pointer-jumping link (-1: end of chain)
+  int* flag = link + kFloydMax;                // "t takes i_t" along the chain so far
+  const int tid = threadIdx.x;
+  const int64_t base = pool - s;
+  int x[2], f[2], l[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = tid + h * kFloydThreads;
+    x[h] = 0;
+    if (t < s) {
+      const Words w = philox(seed, (uint64_t)t, 0, kRows);
+      const uint64_t u = (uint64_t)w.w[0] | ((uint64_t)w.w[1] << 32);
+      x[h] = (int)__umul64hi(u, (uint64_t)(base + t + 1));
+      xs[t] = x[h];
+    }
+  }
+  __syncthreads();
+  // (a): an equal value among the earlier draws
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = tid + h * kFloydThreads;
+    bool dup = false;
+    if (t < s) {
+      int q = 0;
+      for (; q + 4 <= t; q += 4) {
+        const int4 v = *reinterpret_cast<const int4*>(xs + q);
+        dup |= (v.x == x[h]) | (v.y == x[h]) | (v.z == x[h]) | (v.w == x[h]);
+      }
+      for (; q < t; ++q) dup |= xs[q] == x[h];
+      const int64_t tp = (int64_t)x[h] - base;
+      l[h] = (tp >= 0 && tp < t) ? (int)tp : -1;
+    } else {
+      l[h] = -1;
+    }
+    f[h] = dup;
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = tid + h * kFloydThreads;
+    link[t] = l[h];
+    flag[t] = f[h];
+  }
+  __syncthreads();
+  // (b): OR of (a) along the chain, by pointer jumping
+  for (int span = 1; span < s; span <<= 1) {
+    int nf[2], nl[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      nf[h] = f[h];
+      nl[h] = l[h];
+      if (l[h] >= 0) {
+        nf[h] |= flag[l[h]];
+        nl[h] = link[l[h]];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = tid + h * kFloydThreads;
+      f[h] = nf[h];
+      l[h] = nl[h];
+      flag[t] = f[h];
+      link[t] = l[h];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = tid + h * kFloydThreads;
+    if (t < s) {
+      x[h] = f[h] ? (int)(base + t) : x[h];
+      xs[t] = x[h];
+    }
+  }
+  __syncthreads();
+  // sort: each taken value goes to its rank
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = tid + h * kFloydThreads;
+    if (t < s) {
+      int rank = 0, q = 0;
+      for (; q + 4 <= s; q += 4) {
+        const int4 v = *reinterpret_cast<const int4*>(xs + q);
+        rank += (v.x < x[h]) + (v.y < x[h]) + (v.z < x[h]) + (v.w < x[h]);
+      }
+      for (; q < s; ++q) rank += xs[q] < x[h];
+      out[rank] = x[h];
+    }
+  }
 }
 
 // =================================================================================== SRHT

@@ -60,10 +60,8 @@ __device__ inline double gauss_fp64(uint64_t seed, int i, int64_t j) {
 __device__ inline double gauss_hat(uint64_t seed, int i, int64_t j, int gdtype) {
   const Words w = philox(seed, (uint64_t)j, (uint32_t)(i >> 2), kGauss);
   float g[4];
-  box_muller(w.w[0], w.w[1], g[0], g[1]);
-  box_muller(w.w[2], w.w[3], g[2], g[3]);
-  const float x = g[i & 3];
-  return (double)(gdtype == NSK_BF16 ? bf16_round(x) : e4m3_round(x));
+  if (gdtype == NSK_BF16) gauss_hat4<NSK_BF16>(w, g); else gauss_hat4<NSK_F8E4M3>(w, g);
+  return (double)g[i & 3];
 }
 
 // S_r(i, j)

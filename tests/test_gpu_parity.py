@@ -2,7 +2,8 @@
 
 Tolerances: sketches with FP64 accumulation agree with the oracle's FP64 product to
 rounding (1e-12 relative); plain-FP32 and narrow-operand sketches to the FP32 bound (1e-4
-relative: FP32 accumulation over the sketch's terms).  Trailing vectors agree to
+relative: FP32 accumulation over the sketch's terms).  Sketches are compared column by
+column (the largest relative error over the columns of SA).  Trailing vectors agree to
 max(1e-10, sqrt(N) u kappa_gap) with kappa_gap = sigma_1 / (sigma_{N-k} - sigma_{N-k+1})
 of the oracle's SA (the conditioning floor of a singular subspace under perturbations of
 size u sigma_1), and residual ratios to 1e-10 (FP64 arithmetic) or 1e-4 (FP32 arithmetic).
@@ -30,6 +31,14 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def colrel(a, b):
+    """Largest relative 2-norm error over the columns (sketch comparisons: a few wrong entries
+    of a small-norm column cannot hide behind the other columns)."""
+    num = np.linalg.norm(a - b, axis=0)
+    den = np.maximum(np.linalg.norm(b, axis=0), 1e-300)
+    return float(np.max(num / den))
+
+
 def assert_vectors(ref, got, tol):
     """got spans ref's subspace to tol (sin theta), with orthonormal columns: sin theta alone
     would accept a zero matrix."""
@@ -55,18 +64,33 @@ def test_device_signs_and_sparse_bit_exact(lib):
         assert np.array_equal(rows.cpu().numpy(), r2) and np.array_equal(sg.cpu().numpy(), s2)
 
 
-def test_device_gaussian_matches_oracle_box_muller(lib):
-    s, j0, j1 = 203, 17, 2017
-    g = lib.draw_gaussian_device(5, s, j0, j1, "f32").cpu().numpy().astype(np.float64)
-    ref = draws.gaussian_block(5, s, j0, j1)
-    assert np.max(np.abs(g - ref) / (1 + np.abs(ref))) < 2e-5
+@pytest.mark.parametrize("m,s", [(2000, 200), (64, 64), (64, 1), (100, 100), (2048, 2048), (1 << 20, 804),
+                                 (1 << 31, 2048), (3000, 2048), (5000, 1100), (700, 513)])
+def test_device_row_sample_bit_exact(lib, m, s):
+    """The device's parallel resolution of Floyd's rule returns the sequential rule's rows,
+    including sample sizes equal to the pool (every draw collides or is forced) and near it."""
+    for seed in (1, 7, 2 ** 40 + 3):
+        got = lib.draw_srht_rows_device(seed, m, s).cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, lib.draw_srht_rows(seed, m, s))
+        assert np.array_equal(got, draws.srht_rows(seed, draws.next_pow2(m), s))
+
+
+@pytest.mark.parametrize("seed,s,j0,j1", [(5, 203, 17, 2017), (6, 200, 0, 100_000), (2 ** 33 + 1, 64, 10 ** 9, 10 ** 9 + 50_000)])
+def test_device_gaussian_matches_oracle_box_muller(lib, seed, s, j0, j1):
+    """FP32 Box-Muller values within their error bound; the rounded entries G_hat equal the
+    oracle's rounding of its FP64 Box-Muller values exactly (the device settles every rounding
+    decision its FP32 error bound leaves open in FP64)."""
+    g = lib.draw_gaussian_device(seed, s, j0, j1, "f32").cpu().numpy().astype(np.float64)
+    ref = draws.gaussian_block(seed, s, j0, j1)
+    # the FP32 values lie within half the margin E = 2^-21 (|g| + r) the rounding check assumes
+    # (r: the pair's radius; rows 2p and 2p + 1 form a pair)
+    full = draws.gaussian_block(seed, 4 * ((s + 3) // 4), j0, j1)
+    r = np.repeat(np.hypot(full[0::2], full[1::2]), 2, axis=0)[:s]
+    assert np.all(np.abs(g - ref) <= 2.0 ** -22 * (np.abs(ref) + r)), np.max(np.abs(g - ref) / (np.abs(ref) + r))
     for fmt, rnd in (("bf16", round_bf16), ("e4m3", round_e4m3)):
-        gq = lib.draw_gaussian_device(5, s, j0, j1, fmt).cpu().numpy().astype(np.float64)
+        gq = lib.draw_gaussian_device(seed, s, j0, j1, fmt).cpu().numpy().astype(np.float64)
         rq = rnd(ref)
-        mism = gq != rq
-        assert mism.mean() < 2e-3, (fmt, mism.mean())
-        # every mismatch is one rounding step of an FP32-vs-FP64 boundary case
-        assert np.all(np.abs(gq[mism] - rq[mism]) <= np.abs(rq[mism]) * 2.0 ** -2 + 2.0 ** -9)
+        assert np.array_equal(gq, rq), (fmt, int((gq != rq).sum()))
 
 
 # ---------------------------------------------------------------------------- sketches
@@ -85,9 +109,9 @@ def test_srht_sketch_parity(lib, name, m, n, s, dt):
     a = np.random.default_rng(hash(name) % 2 ** 32).standard_normal((m, n)).astype(dt)
     SA = lib.sketch(t(a), "srht", s, 31).cpu().numpy()
     ref = operators.sketch(a.astype(np.float64), "srht", s, 31)
-    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    assert colrel(SA, ref) < 1e-12, colrel(SA, ref)
     SA32 = lib.sketch(t(a), "srht", s, 31, acc="f32").cpu().numpy()
-    assert rel(SA32, ref) < 1e-4
+    assert colrel(SA32, ref) < 1e-4
 
 
 SRDCT_CASES = [
@@ -105,9 +129,9 @@ def test_srdct_sketch_parity(lib, name, m, n, s, dt):
     a = np.random.default_rng(len(name) + m).standard_normal((m, n)).astype(dt)
     SA = lib.sketch(t(a), "srdct", s, 41).cpu().numpy()
     ref = operators.sketch(a.astype(np.float64), "srdct", s, 41)
-    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    assert colrel(SA, ref) < 1e-12, colrel(SA, ref)
     SA32 = lib.sketch(t(a), "srdct", s, 41, acc="f32").cpu().numpy()
-    assert rel(SA32, ref) < 1e-4, rel(SA32, ref)
+    assert colrel(SA32, ref) < 1e-4, colrel(SA32, ref)
 
 
 HRHT_CASES = [
@@ -124,7 +148,7 @@ def test_hrht_sketch_parity(lib, name, m, n, s, dt):
     a = np.random.default_rng(len(name) * 7 + m).standard_normal((m, n)).astype(dt)
     SA = lib.sketch(t(a), "hrht", s, 43).cpu().numpy()
     ref = operators.sketch(a.astype(np.float64), "hrht", s, 43)
-    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    assert colrel(SA, ref) < 1e-12, colrel(SA, ref)
 
 
 def test_srdct_one_workgroup_per_column_tile(lib):
@@ -134,9 +158,9 @@ def test_srdct_one_workgroup_per_column_tile(lib):
     a = np.random.default_rng(5).standard_normal((m, n)).astype(np.float32)
     ref = operators.sketch(a.astype(np.float64), "srdct", s, 9)
     SA = lib.sketch(t(a), "srdct", s, 9, row_groups=1).cpu().numpy()
-    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    assert colrel(SA, ref) < 1e-12, colrel(SA, ref)
     SA32 = lib.sketch(t(a), "srdct", s, 9, acc="f32", row_groups=1).cpu().numpy()
-    assert rel(SA32, ref) < 1e-4, rel(SA32, ref)
+    assert colrel(SA32, ref) < 1e-4, colrel(SA32, ref)
 
 
 @pytest.mark.parametrize("m,n,s,zeta,dt", [(5003, 37, 150, 8, np.float32), (20_000, 201, 804, 8, np.float32),
@@ -145,9 +169,9 @@ def test_sparse_sketch_parity(lib, m, n, s, zeta, dt):
     a = np.random.default_rng(m + n).standard_normal((m, n)).astype(dt)
     SA = lib.sketch(t(a), "sparse", s, 77, zeta=zeta).cpu().numpy()
     ref = operators.sketch(a.astype(np.float64), "sparse", s, 77, zeta=zeta)
-    assert rel(SA, ref) < 1e-12, rel(SA, ref)
+    assert colrel(SA, ref) < 1e-12, colrel(SA, ref)
     SA32 = lib.sketch(t(a), "sparse", s, 77, zeta=zeta, acc="f32").cpu().numpy()
-    assert rel(SA32, ref) < 1e-4
+    assert colrel(SA32, ref) < 1e-4
 
 
 def test_sketch_column_blocks_equal_concatenation(lib):
@@ -158,7 +182,7 @@ def test_sketch_column_blocks_equal_concatenation(lib):
     assert np.array_equal(whole, split)
     strided = lib.sketch([Mt[:, :40], Mt[:, 40:]], "srht", 164, 3).cpu().numpy()
     ref = operators.sketch(M.astype(np.float64), "srht", 164, 3)
-    assert rel(strided, ref) < 1e-12
+    assert colrel(strided, ref) < 1e-12
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "e4m3"])
@@ -176,7 +200,7 @@ def test_gaussian_sketch_parity(lib, fmt):
         stored = q.to(torch.float64).cpu().numpy() * 2.0 ** (-e[None, :].astype(np.float64))
         SA = lib.sketch([(q, t(-e))], "gauss", s, 12).cpu().numpy()
     ref = operators.sketch(stored, "gauss", s, 12, gauss_dtype=fmt)
-    assert rel(SA, ref) < 1e-4, rel(SA, ref)
+    assert colrel(SA, ref) < 1e-4, colrel(SA, ref)
 
 
 # ---------------------------------------------------------------------------- epsilon null space
@@ -213,14 +237,14 @@ def test_row_downdate_and_update_match_oracle(lib, kind, dt):
     a0 = a.astype(np.float64)
     a0[gone] = 0.0
     ref = operators.sketch(a0, kind, s, seed)
-    assert rel(SA.cpu().numpy(), ref) < 1e-12, rel(SA.cpu().numpy(), ref)
+    assert colrel(SA.cpu().numpy(), ref) < 1e-12, colrel(SA.cpu().numpy(), ref)
     # Algorithm 2 / Section 5.3: appended rows add Gaussian columns; a re-added original row its own
     before = SA.cpu().numpy()
     new = rng.standard_normal((3, n)).astype(dt)
     rows, ops = [m, m + 7, 5], [1, 1, 1]
     lib.sketch_rows(SA, t(new), rows, ops, m, kind=kind, seed=seed)
     ref = updates.update_rows(before, kind, seed, m, rows, new.astype(np.float64), ops)
-    assert rel(SA.cpu().numpy() - before, ref - before) < 1e-12
+    assert colrel(SA.cpu().numpy() - before, ref - before) < 1e-12
 
 
 def test_gaussian_row_update_matches_oracle(lib):
@@ -248,7 +272,7 @@ def test_column_update_writes_into_sketch_columns(lib, kind):
     SA = torch.zeros((s, n), dtype=torch.float64, device=DEV)
     lib.sketch(t(a[:, :37]), kind, s, 4, out=SA[:, :37])
     lib.sketch(t(a[:, 37:]), kind, s, 4, out=SA[:, 37:])
-    assert rel(SA.cpu().numpy(), whole) < 1e-13
+    assert colrel(SA.cpu().numpy(), whole) < 1e-13
 
 
 # ---------------------------------------------------------------------------- solves
