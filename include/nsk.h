@@ -157,6 +157,24 @@ int nsk_trailing_rsv(const nsk_operand* blocks, int32_t nblocks, int64_t m, int6
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * nsk_trailing_rsv without a caller workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid allocation).  The
+ * workspace is a fixed array of nsk_noalloc_scratch_bytes() bytes (96 MiB) that the library's
+ * code object places in device memory, one copy per GPU, held until the process ends; its
+ * device address is looked up once per GPU (first call with that GPU current).  The call
+ * itself allocates nothing.  Arguments, outputs and errors as nsk_trailing_rsv, plus
+ * NSK_EWORKSPACE when nsk_workspace_bytes(m, N, k, d) exceeds the array (the 1,000,000 x 201
+ * TLS workload needs 57-63 MiB, the 2,000,000 x 257 one 80 MiB) and NSK_EDEVICE when the
+ * array's address cannot be obtained.  `stream` must belong to the current GPU.  Every call on
+ * one GPU uses that GPU's array: calls whose work overlaps on one GPU (several streams or host
+ * threads) race; serialise them, e.g. on one stream.
+ */
+size_t nsk_noalloc_scratch_bytes(void);
+int nsk_trailing_rsv_noalloc(const nsk_operand* blocks, int32_t nblocks, int64_t m, int64_t k,
+                             const nsk_desc* d, double* Vk, double* sigma_k, nsk_info* info,
+                             void* stream);
+
+/*
  * Total least squares with k = nrhs right-hand sides (Section 4): the trailing nrhs right
  * singular vectors V_k of the sketched [A | B] (the operand's last nrhs columns are B, so
  * N = n + nrhs) give X = -V12 V22^{-1}, V12 = V_k(1:n, :), V22 = V_k(n+1:N, :).

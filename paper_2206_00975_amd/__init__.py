@@ -77,6 +77,9 @@ _SIGS = {
                                   _P, ctypes.c_int64, _P, ctypes.c_size_t, _P]),
     "nsk_trailing_rsv": (ctypes.c_int, [ctypes.POINTER(Operand), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.POINTER(Desc), _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "nsk_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "nsk_trailing_rsv_noalloc": (ctypes.c_int, [ctypes.POINTER(Operand), ctypes.c_int32, ctypes.c_int64,
+                                                ctypes.c_int64, ctypes.POINTER(Desc), _P, _P, _P, _P]),
     "nsk_residual": (ctypes.c_int, [ctypes.POINTER(Operand), ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
                                     _P, _P, ctypes.c_size_t, _P]),
     "nsk_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.POINTER(Desc)]),
@@ -316,6 +319,25 @@ def trailing_rsv(A, k=1, kind="srht", s=None, seed=0, zeta=8, acc="f64", max_swe
         Vk, sig, info = out
     _check("nsk_trailing_rsv", lib.nsk_trailing_rsv(ops, nb, m, k, ctypes.byref(d), Vk.data_ptr(), sig.data_ptr(),
                                                     info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)))
+    return Vk, sig, info
+
+
+def trailing_rsv_noalloc(A, k=1, kind="srht", s=None, seed=0, zeta=8, acc="f64", max_sweeps=0, residual=False,
+                         row_groups=0, out=None):
+    """:func:`trailing_rsv` on the library's own fixed device array instead of a workspace
+    (``nsk_trailing_rsv_noalloc``); ``out = (Vk, sigma_k, info)`` lets the caller supply every
+    output so that nothing is allocated."""
+    lib = load()
+    ops, nb, m, N, dev, keep = _blocks(A)
+    d = make_desc(kind, s, seed, zeta, acc, max_sweeps, row_groups, FLAG_RESIDUAL if residual else 0)
+    if out is None:
+        Vk = torch.empty((N, k), dtype=torch.float64, device=dev)
+        sig = torch.empty(k, dtype=torch.float64, device=dev)
+        info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    else:
+        Vk, sig, info = out
+    _check("nsk_trailing_rsv_noalloc", lib.nsk_trailing_rsv_noalloc(ops, nb, m, k, ctypes.byref(d), Vk.data_ptr(),
+                                                                    sig.data_ptr(), info.data_ptr(), _stream(dev)))
     return Vk, sig, info
 
 

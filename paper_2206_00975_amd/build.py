@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnsk.so")
-SOURCES = ["sketch.hip", "srdct.hip", "update.hip", "aaa.hip", "rht.hip", "svd.hip", "post.hip", "batched.hip", "api.cpp", "tune.cpp"]
+SOURCES = ["sketch.hip", "srdct.hip", "update.hip", "aaa.hip", "rht.hip", "svd.hip", "post.hip", "batched.hip", "api.cpp", "tune.cpp",
+           "noalloc.hip"]
 ARCH = os.environ.get("NSK_OFFLOAD_ARCH", "gfx950")
 
 
