@@ -14,8 +14,7 @@
 namespace nsk {
 // defined in the .hip translation units
 size_t sparse_lds_bytes(int s, int zeta, int acc);
-size_t gauss_lds_bytes(int s, int N, int dtype);
-int gauss_tiles_per_wave(int s, int N);
+int gauss_groups(int64_t m, int s, int N);
 size_t batched_lds_bytes(int s_max, int n_max);
 hipError_t launch_batched(const void* insts, int count, const void* tiles, int ntiles, int* counters, int dtype,
                           int acc, int grid, size_t lds, hipStream_t st);
@@ -87,8 +86,7 @@ int plan_groups(const nsk_desc* d, int64_t m, int64_t N, int dtype) {
     const int64_t ct = (N + cols - 1) / cols, nb = (m + 1023) / 1024;
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256 / ct));
   }
-  const int64_t ks = (m + 31) / 32;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(256, (ks + 7) / 8));
+  return gauss_groups(m, (int)d->s, (int)N);
 }
 
 struct Layout {
@@ -154,7 +152,6 @@ int check_desc(const nsk_desc* d, int64_t m, int64_t N) {
     return NSK_EUNSUPPORTED;
   if (d->kind == NSK_SPARSE_SIGN && sparse_lds_bytes((int)d->s, dflt_zeta(d), dflt_acc(d)) > 160 * 1024)
     return NSK_EUNSUPPORTED;
-  if (d->kind == NSK_GAUSSIAN && gauss_tiles_per_wave((int)d->s, (int)N) > 48) return NSK_EUNSUPPORTED;
   if (d->acc != 0 && d->acc != NSK_F64 && d->acc != NSK_F32) return NSK_EINVAL;
   if (d->max_sweeps < 0 || d->row_groups < 0) return NSK_EINVAL;
   return NSK_OK;

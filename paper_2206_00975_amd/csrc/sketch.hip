@@ -19,6 +19,9 @@
 // regenerated from Philox + Box-Muller per K-step and never read from memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "nsk_internal.hpp"
 #include "sketch_device.hpp"
 #include "wave_ops.hpp"
@@ -221,105 +224,202 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
 }
 
 // ============================================================================== Gaussian
-// v_mfma_f32_16x16x32_{bf16,fp8_fp8}: lane l supplies A[l%16][8(l/16)+0..7] and
-// B[8(l/16)+0..7][l%16]; the accumulator lane l holds C[4(l/16)+0..3][l%16].
+// SA = G_hat A / sqrt(s) on MFMA, v_mfma_f32_16x16x32_{bf16,fp8_fp8} with FP32 accumulation:
+// lane l supplies the A operand's row l % 16 at k = 8 (l / 16) .. + 7 and the B operand's column
+// l % 16 at the same k; the accumulator lane l holds rows 4 (l / 16) .. + 3 of column l % 16.
+// The A operand is G_hat (rows = sketch rows i, k = input rows j), the B operand A itself.
+//
+// A workgroup (K range, group of up to 8 column tiles, group of up to 8 MW row tiles) runs 8
+// waves; wave w takes row tiles w, w + 8, .. of its group and every column tile, so it draws
+// exactly the entries of G_hat its own MFMAs use.  Per K step (32 input rows):
+//  * the workgroup loads the A tile (32 rows x 128 columns; each thread 8 rows of one column,
+//    a wave load instruction 64 adjacent columns of one row) and stores it in LDS column by
+//    column (k contiguous), double-buffered, so each wave reads its B operands with one LDS
+//    read per column tile; one workgroup barrier per K step;
+//  * each wave draws its G_hat entries: the 4 lanes of a quad (rows 4a .. 4a + 3 of a tile, one
+//    k range) need the same 8 Philox blocks (block (j, q) holds rows 4q .. 4q + 3 of column j);
+//    each lane draws 2 of them, and a 4 x 4 exchange of 2-entry items over the quad (DPP quad
+//    permutations) leaves every lane the 8 entries of its own row;
+//  * entries whose FP32 rounding is not certified are redrawn in FP64, one per lane at a time;
+//  * MW x (column tiles) MFMAs.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
+typedef __attribute__((__vector_size__(2 * sizeof(unsigned)))) unsigned u32x2;
 
-constexpr int kGK = 32;        // K (rows of A) per MFMA step
-constexpr int kGThreads = 256;
-constexpr int kGMaxTiles = 48; // (s/16)*(N/16) output tiles per wave, at most
+constexpr int kGK = 32;                 // K (input rows) per MFMA step
+constexpr int kGWaves = 8;
+constexpr int kGThreads = 64 * kGWaves;
+constexpr int kGNT = 8;                 // column tiles of a column group
+constexpr int kGCols = 16 * kGNT;       // 128 columns
 
-template <bool FP8, int TPW>
-__global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m, int N, int s,
-                                                          uint64_t seed, int groups, int ksteps_per_group,
-                                                          float* __restrict__ partial) {
-  using E = typename std::conditional<FP8, uint8_t, __bf16>::type;
-  extern __shared__ unsigned char smem_raw[];
-  const int sp = (s + 15) & ~15;
-  const int np = (N + 15) & ~15;
-  E* gs = reinterpret_cast<E*>(smem_raw);            // sp x kGK (row i, k contiguous)
-  E* as = gs + (size_t)sp * kGK;                     // np x kGK (column j, k contiguous)
+// LDS bytes between consecutive columns of the staged A tile: the 32 k values plus 16 bytes
+// (keeps 16-byte alignment and spreads the columns over the banks).
+template <bool FP8> constexpr int gauss_col_stride() { return FP8 ? 48 : 80; }
+
+// Value of lane (l ^ D) of the same quad, 1 <= D <= 3 (DPP quad permutation).
+template <int D> __device__ inline unsigned quad_xor(unsigned x) {
+  constexpr int ctrl = D == 1 ? 0xB1 : D == 2 ? 0x4E : 0x1B;  // [1,0,3,2], [2,3,0,1], [3,2,1,0]
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, 0xF, 0xF, false);
+}
+__device__ inline unsigned sel4(int k, unsigned a, unsigned b, unsigned c, unsigned d) {
+  return k == 0 ? a : k == 1 ? b : k == 2 ? c : d;
+}
+
+template <bool FP8, int MW>
+__global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m, int N, int s, uint64_t seed,
+                                                          int ksteps_per_group, float* __restrict__ partial) {
+  using E = typename std::conditional<FP8, uint8_t, uint16_t>::type;
+  constexpr int FMT = FP8 ? NSK_F8E4M3 : NSK_BF16;
+  constexpr int IB = FP8 ? 8 : 16;        // bits of one entry
+  constexpr int CS = gauss_col_stride<FP8>();
+  __shared__ __align__(16) unsigned char btile[2][kGCols * CS];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int mt_n = sp / 16, nt_n = np / 16, tiles = mt_n * nt_n;
-  floatx4 accv[TPW];
+  const int kq = lane >> 4, li = lane & 15, quad = li >> 2, hq = li & 3;
+  const int mtiles = (s + 15) / 16, ntiles = (N + 15) / 16;
+  const int mt0 = blockIdx.z * kGWaves * MW + wave, nt0 = blockIdx.y * kGNT;
+
+  // the A tile: thread t loads rows 8 rg .. 8 rg + 7 of column n0 + ln
+  const int ln = t & (kGCols - 1), rg = t >> 7;
+  const int lcol = nt0 * 16 + ln;
+  const bool lval = lcol < N;
+  const E* lbase;
+  int64_t lld;
+  column_ref<E>(op, lval ? lcol : 0, lbase, lld);
+
+  floatx4 acc[MW][kGNT];
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) accv[q] = floatx4{0, 0, 0, 0};
+  for (int u = 0; u < MW; ++u)
+#pragma unroll
+    for (int c = 0; c < kGNT; ++c) acc[u][c] = floatx4{0, 0, 0, 0};
 
   const int64_t ksteps = (m + kGK - 1) / kGK;
-  const int64_t k_begin = (int64_t)blockIdx.x * ksteps_per_group;
-  const int64_t k_end = k_begin + ksteps_per_group < ksteps ? k_begin + ksteps_per_group : ksteps;
-  for (int64_t ks = k_begin; ks < k_end; ++ks) {
-    const int64_t j0 = ks * kGK;
-    __syncthreads();
-    // G_hat[i, j0 + kk]: Philox block (j, i>>2) gives rows 4q..4q+3 of column j
-    for (int w = t; w < (sp / 4) * kGK; w += kGThreads) {
-      const int kk = w % kGK, q = w / kGK;
-      const int64_t j = j0 + kk;
-      float g[4] = {0, 0, 0, 0};
-      if (j < m) {
-        const Words r = philox(seed, (uint64_t)j, (uint32_t)q, kGauss);
-        gauss_hat4<FP8 ? NSK_F8E4M3 : NSK_BF16>(r, g);
+  const int64_t kb = (int64_t)blockIdx.x * ksteps_per_group;
+  const int64_t ke = kb + ksteps_per_group < ksteps ? kb + ksteps_per_group : ksteps;
+
+  // rows ks * 32 + 8 rg .. + 7 of this thread's column, packed (zero past m and past N)
+  auto load_a = [&](int64_t ks, unsigned (&r)[FP8 ? 2 : 4]) {
+    const int64_t j0 = ks * kGK + 8 * rg;
+    unsigned e[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t j = j0 + i;
+      const E x = lbase[(j < m ? j : m - 1) * lld];
+      e[i] = (lval && j < m) ? (unsigned)x : 0u;
+    }
+    if constexpr (FP8) {
+      r[0] = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
+      r[1] = e[4] | (e[5] << 8) | (e[6] << 16) | (e[7] << 24);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r[q] = e[2 * q] | (e[2 * q + 1] << 16);
+    }
+  };
+  auto store_a = [&](int buf, const unsigned (&r)[FP8 ? 2 : 4]) {
+    unsigned char* p = &btile[buf][ln * CS + 8 * rg * (FP8 ? 1 : 2)];
+    if constexpr (FP8) *reinterpret_cast<u32x2*>(p) = u32x2{r[0], r[1]};
+    else *reinterpret_cast<u32x4*>(p) = u32x4{r[0], r[1], r[2], r[3]};
+  };
+
+  unsigned ra[FP8 ? 2 : 4];
+  if (kb < ke) {
+    load_a(kb, ra);
+    store_a((int)(kb & 1), ra);
+  }
+  __syncthreads();
+  for (int64_t ks = kb; ks < ke; ++ks) {
+    const int buf = (int)(ks & 1);
+    if (ks + 1 < ke) load_a(ks + 1, ra);
+    const int64_t jq = ks * kGK + 8 * kq + 2 * hq;  // this lane draws columns jq, jq + 1
+    // P[u][h]: rows 4q + h (q = 4 mt + quad) of columns jq (low item) and jq + 1 (high item);
+    // bit 8 u + 4 v + h of `doubt`: entry (row 4q + h, column jq + v) of tile u needs FP64
+    unsigned P[MW][4];
+    unsigned doubt = 0;
+#pragma unroll
+    for (int u = 0; u < MW; ++u) {
+      const int q = (mt0 + kGWaves * u) * 4 + quad;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) P[u][h] = 0;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int64_t j = jq + v;
+        float g[4];
+        unsigned d = gauss_hat4_fast<FMT>(philox(seed, (uint64_t)j, (uint32_t)q, kGauss), g);
+        if (j >= m) d = 0;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const bool ok = j < m && 4 * q + h < s;
+          const unsigned bits = FP8 ? e4m3_bits(g[h]) : __float_as_uint(g[h]) >> 16;
+          P[u][h] |= (ok ? bits : 0u) << (v * IB);
+          if (!ok) d &= ~(1u << h);
+        }
+        doubt |= d << (8 * u + 4 * v);
+      }
+    }
+    // entries whose FP32 rounding is not certified: FP64 Box-Muller, one entry per lane at a time
+    while (__any(doubt != 0)) {
+      if (doubt != 0) {
+        const int bit = __builtin_ctz(doubt);
+        doubt &= doubt - 1;
+        const int u = bit >> 3, v = (bit >> 2) & 1, h = bit & 3;
+        const int q = (mt0 + kGWaves * u) * 4 + quad;
+        const float g = gauss_hat64<FMT>(philox(seed, (uint64_t)(jq + v), (uint32_t)q, kGauss), h);
+        const unsigned bits = FP8 ? e4m3_bits(g) : __float_as_uint(g) >> 16;
+        const unsigned mask = ((1u << IB) - 1) << (v * IB);
+#pragma unroll
+        for (int uu = 0; uu < MW; ++uu)
+#pragma unroll
+          for (int hh = 0; hh < 4; ++hh)
+            if (uu == u && hh == h) P[uu][hh] = (P[uu][hh] & ~mask) | (bits << (v * IB));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < MW; ++u) {
+      if (mt0 + kGWaves * u >= mtiles) continue;
+      // lane hq needs row hq of every quad lane's columns: R[p] = P_p[hq]
+      const unsigned r1 = quad_xor<1>(sel4(hq ^ 1, P[u][0], P[u][1], P[u][2], P[u][3]));
+      const unsigned r2 = quad_xor<2>(sel4(hq ^ 2, P[u][0], P[u][1], P[u][2], P[u][3]));
+      const unsigned r3 = quad_xor<3>(sel4(hq ^ 3, P[u][0], P[u][1], P[u][2], P[u][3]));
+      const unsigned own = sel4(hq, P[u][0], P[u][1], P[u][2], P[u][3]);
+      unsigned R[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int d = p ^ hq;  // R[p] came from lane p = hq ^ d
+        R[p] = d == 0 ? own : d == 1 ? r1 : d == 2 ? r2 : r3;
       }
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int i = 4 * q + h;
-        E e;
+      for (int c = 0; c < kGNT; ++c) {
+        if (nt0 + c >= ntiles) continue;
+        const unsigned char* bp = &btile[buf][(16 * c + li) * CS + 8 * kq * (FP8 ? 1 : 2)];
         if constexpr (FP8) {
-          e = (i < s) ? (E)e4m3_bits(g[h]) : (E)0;
+          const u32x2 bv = *reinterpret_cast<const u32x2*>(bp);
+          const long av = (long)((unsigned long)(R[0] | (R[1] << 16)) | ((unsigned long)(R[2] | (R[3] << 16)) << 32));
+          const long bb = (long)((unsigned long)bv[0] | ((unsigned long)bv[1] << 32));
+          acc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bb, acc[u][c], 0, 0, 0);
         } else {
-          e = (i < s) ? (E)g[h] : (E)0.0f;
+          const u32x4 bv = *reinterpret_cast<const u32x4*>(bp);
+          const bf16x8 av = __builtin_bit_cast(bf16x8, u32x4{R[0], R[1], R[2], R[3]});
+          acc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bv), acc[u][c], 0, 0, 0);
         }
-        gs[(size_t)i * kGK + kk] = e;
       }
     }
-    // A[j0 + kk, col] -> as[col][kk]
-    for (int w = t; w < np * kGK; w += kGThreads) {
-      const int cc = w % np, kk = w / np;
-      const int64_t j = j0 + kk;
-      E e;
-      if constexpr (FP8) e = 0; else e = (E)0.0f;
-      if (cc < N && j < m) {
-        const E* b;
-        int64_t ld;
-        column_ref<E>(op, cc, b, ld);
-        e = b[j * ld];
-      }
-      as[(size_t)cc * kGK + kk] = e;
-    }
+    if (ks + 1 < ke) store_a(buf ^ 1, ra);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-      const int tile = wave + 4 * q;
-      if (tile < tiles) {
-        const int mt = tile / nt_n, nt = tile % nt_n;
-        const int ka = 8 * (lane >> 4);
-        const E* pa = gs + (size_t)(mt * 16 + (lane & 15)) * kGK + ka;
-        const E* pb = as + (size_t)(nt * 16 + (lane & 15)) * kGK + ka;
-        if constexpr (FP8) {
-          const long av = *reinterpret_cast<const long*>(pa);
-          const long bv = *reinterpret_cast<const long*>(pb);
-          accv[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, accv[q], 0, 0, 0);
-        } else {
-          const bf16x8 av = *reinterpret_cast<const bf16x8*>(pa);
-          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(pb);
-          accv[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, accv[q], 0, 0, 0);
-        }
-      }
-    }
   }
   float* out = partial + (size_t)blockIdx.x * s * N;
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    const int tile = wave + 4 * q;
-    if (tile < tiles) {
-      const int mt = tile / nt_n, nt = tile % nt_n;
-      const int cc = nt * 16 + (lane & 15);
+  for (int u = 0; u < MW; ++u) {
+    const int mt = mt0 + kGWaves * u;
+    if (mt >= mtiles) continue;
+#pragma unroll
+    for (int c = 0; c < kGNT; ++c) {
+      const int col = (nt0 + c) * 16 + li;
+      if (nt0 + c >= ntiles || col >= N) continue;
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const int i = mt * 16 + 4 * (lane >> 4) + h;
-        if (i < s && cc < N) out[(size_t)i * N + cc] = accv[q][h];
+        const int i = mt * 16 + 4 * kq + h;
+        if (i < s) out[(size_t)i * N + col] = acc[u][c][h];
       }
     }
   }
@@ -425,35 +525,43 @@ hipError_t launch_sparse_table(const SketchPlan& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-size_t gauss_lds_bytes(int s, int N, int dtype) {
-  const int sp = (s + 15) & ~15, np = (N + 15) & ~15;
-  return (size_t)(sp + np) * kGK * (dtype == NSK_F8E4M3 ? 1 : 2);
+// Row tiles per wave (MW) of the Gaussian kernel, and the row and column groups of its grid.
+struct GaussShape { int mw, mgroups, ngroups; };
+static GaussShape gauss_shape(int s, int N) {
+  const int mt = (s + 15) / 16, nt = (N + 15) / 16;
+  GaussShape g;
+  g.mw = mt <= kGWaves ? 1 : mt <= 2 * kGWaves ? 2 : 4;
+  g.mgroups = (mt + kGWaves * g.mw - 1) / (kGWaves * g.mw);
+  g.ngroups = (nt + kGNT - 1) / kGNT;
+  return g;
 }
 
-int gauss_tiles_per_wave(int s, int N) {
-  const int sp = (s + 15) / 16, np = (N + 15) / 16;
-  return (sp * np + 3) / 4;
+// K partitions: about six K steps each, at most 256 / (row groups x column groups) of them.
+int gauss_groups(int64_t m, int s, int N) {
+  const GaussShape g = gauss_shape(s, N);
+  const int64_t ks = (m + kGK - 1) / kGK;
+  const int64_t cap = std::max<int64_t>(1, 256 / ((int64_t)g.mgroups * g.ngroups));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (ks + 5) / 6));
 }
 
 static hipError_t gauss_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
+  const GaussShape g = gauss_shape(p.s, p.N);
   const int64_t ksteps = (p.m + kGK - 1) / kGK;
   const int per = (int)((ksteps + p.groups - 1) / p.groups);
-  const size_t lds = gauss_lds_bytes(p.s, p.N, op.dtype);
-  const int tpw = gauss_tiles_per_wave(p.s, p.N);
   float* part = static_cast<float*>(p.partial);
+  const dim3 grid(p.groups, g.ngroups, g.mgroups);
   const bool f8 = op.dtype == NSK_F8E4M3;
-#define NSK_GAUSS_CASE(TPWV)                                                                          \
-  if (tpw <= TPWV) {                                                                                  \
-    if (f8)                                                                                           \
-      gauss_kernel<true, TPWV><<<p.groups, kGThreads, lds, st>>>(op, p.m, p.N, p.s, p.seed, p.groups, per, part); \
-    else                                                                                              \
-      gauss_kernel<false, TPWV><<<p.groups, kGThreads, lds, st>>>(op, p.m, p.N, p.s, p.seed, p.groups, per, part); \
-    return hipGetLastError();                                                                         \
+#define NSK_GAUSS_CASE(MWV)                                                                      \
+  if (g.mw == MWV) {                                                                             \
+    if (f8)                                                                                      \
+      gauss_kernel<true, MWV><<<grid, kGThreads, 0, st>>>(op, p.m, p.N, p.s, p.seed, per, part);  \
+    else                                                                                         \
+      gauss_kernel<false, MWV><<<grid, kGThreads, 0, st>>>(op, p.m, p.N, p.s, p.seed, per, part); \
+    return hipGetLastError();                                                                    \
   }
-  NSK_GAUSS_CASE(8)
-  NSK_GAUSS_CASE(16)
-  NSK_GAUSS_CASE(32)
-  NSK_GAUSS_CASE(kGMaxTiles)
+  NSK_GAUSS_CASE(1)
+  NSK_GAUSS_CASE(2)
+  NSK_GAUSS_CASE(4)
 #undef NSK_GAUSS_CASE
   return hipErrorInvalidValue;
 }

@@ -103,6 +103,29 @@ template <int FMT> __device__ inline float round_fmt(float x) {
 template <int FMT> __device__ inline float round_fmt64(double x) {
   if constexpr (FMT == NSK_BF16) return bf16_round_f64(x); else return e4m3_round_f64(x);
 }
+// The FP32 part alone: out[h] rounded from the FP32 value, and bit h of the returned mask set
+// when that rounding is not certified (the entry must then be taken from gauss_hat64).
+template <int FMT> __device__ inline unsigned gauss_hat4_fast(const Words& w, float (&out)[4]) {
+  unsigned doubt = 0;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const GaussPair g = box_muller32(w.w[2 * p], w.w[2 * p + 1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float x = h ? g.g1 : g.g0;
+      const float e = 0x1p-21f * (fabsf(x) + g.r);
+      doubt |= (round_fmt<FMT>(x - e) != round_fmt<FMT>(x + e) ? 1u : 0u) << (2 * p + h);
+      out[2 * p + h] = round_fmt<FMT>(x);
+    }
+  }
+  return doubt;
+}
+// Entry h (0..3) of a block, rounded from its FP64 Box-Muller value.
+template <int FMT> __device__ inline float gauss_hat64(const Words& w, int h) {
+  const uint32_t a = h < 2 ? w.w[0] : w.w[2], b = h < 2 ? w.w[1] : w.w[3];
+  return round_fmt64<FMT>(box_muller64(a, b, h & 1));
+}
+
 template <int FMT> __device__ inline void gauss_hat4(const Words& w, float (&out)[4]) {
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
