@@ -432,7 +432,7 @@ def main():
     sketch_bytes = a_bytes + s * N * 8          # read A once, write SA
     sketch_gbs = sketch_bytes / (stage_ms["sketch"] * 1e-3) / 1e9
     sketch_kernel = {"sparse": "sparse_kernel", "srht": "srht_kernel", "srdct": "srdct_kernel"}[args.sketch_kind]
-    kernels = {"sketch": sketch_kernel, "qr": "svd_qr_coop_kernel", "jacobi": "svd_jacobi_coop_kernel",
+    kernels = {"sketch": sketch_kernel, "qr": "svd_qr_coop_la_kernel", "jacobi": "svd_jacobi_coop_kernel",
                "finish": "svd_finish_kernel", "post": "residual_kernel"}
     dom = max(kernels, key=lambda k: stage_ms[k])
     if dom in ("qr", "jacobi", "finish"):
@@ -467,31 +467,61 @@ def main():
     rho = inf.residual / opt
 
     forms = {}
+    equal_rho = None
     if not args.no_forms and args.sketch_kind == "sparse":
-        # sparse sign at s = 4N and 6N in both arithmetic forms; the DCT-II kind at s = 4N
+        # sparse sign at s = 4N and 6N in both arithmetic forms (FP32 loads with FP64 accumulation,
+        # and plain FP32), then the SRFT kinds at s = 4N and 6N; every form reports its solve rate,
+        # its sketch kernel's time and rate (live stage events) and the median residual ratio
+        # over five seeds
         cases = [("sparse", acc, c) for acc in ("f64", "f32") for c in (4, 6)] + \
-                [("srdct", acc, 4) for acc in ("f64", "f32")]
+                [(kind, acc, c) for kind in ("srht", "srdct") for acc in ("f64", "f32") for c in (4, 6)]
         for kind, acc, c in cases:
             s_c = c * N
             ws_c = nsk._ws(nsk.workspace_bytes(m, N, 1, nsk.make_desc(kind, s_c, 7, 8, acc=acc)), dev)
             st_c = nsk._ws(nsk.load().nsk_tls_state_bytes(n, s_c, 0), dev)
             step(acc=acc, s_=s_c, ws=ws_c, state=st_c, kind=kind)
             torch.cuda.synchronize()
+            reps = 5
+            nsk.profile_enable(reps)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            reps = 3
             rhos = []
             for r in range(reps):
                 _, _, inf_c = step(seed=100 + r, acc=acc, s_=s_c, ws=ws_c, state=st_c, kind=kind)
                 rhos.append(inf_c)
             e1.record()
             torch.cuda.synchronize()
+            st_f, calls_f = nsk.profile_read()
+            nsk.profile_enable(0)
+            sk_ms = st_f["sketch"] / max(calls_f, 1)
             rr = [nsk.read_info(i).residual / opt for i in rhos]
             prefix = "" if kind == "sparse" else f"{kind}_"
             forms[f"{prefix}{'fp64acc' if acc == 'f64' else 'plain_fp32'}_s{c}N"] = {
                 "s": s_c, "solves_per_s": 1000.0 * reps / e0.elapsed_time(e1),
+                "sketch_us": sk_ms * 1e3, "sketch_gbs": (a_bytes + s_c * N * 8) / (sk_ms * 1e-3) / 1e9,
                 "rho_median": float(np.median(rr))}
+        # the metric's comparison: each form against plain FP32 at the smallest s/N whose median
+        # residual ratio is <= 1.1 (for both sides)
+        for c in (4, 6):
+            a64, a32 = forms.get(f"fp64acc_s{c}N"), forms.get(f"plain_fp32_s{c}N")
+            if a64 and a32 and a64["rho_median"] <= 1.1 and a32["rho_median"] <= 1.1:
+                equal_rho = {"s_over_N": c, "s": c * N, "rho_fp64acc": a64["rho_median"],
+                             "rho_plain_fp32": a32["rho_median"],
+                             "solves_per_s_fp64acc": a64["solves_per_s"],
+                             "solves_per_s_plain_fp32": a32["solves_per_s"],
+                             "sketch_us_fp64acc": a64["sketch_us"], "sketch_us_plain_fp32": a32["sketch_us"],
+                             "speedup_fp64acc_over_plain_fp32": a64["solves_per_s"] / a32["solves_per_s"]}
+                break
         print(f"[bench] forms {forms}", file=sys.stderr, flush=True)
+
+    # the plain (tiny) workload: 2000 x 50 FP64, SRHT s = 200, k = 1; microseconds per solve
+    plain = None
+    if not args.no_forms:
+        ap_, _, _ = W.plain_matrix(m=2000, n=50)
+        Ap = torch.from_numpy(ap_).to(dev)
+        ms_p, _ = _timed(torch, lambda: nsk.trailing_rsv(Ap, 1, kind="srht", s=200, seed=1), 50)
+        plain = {"workload": "A = U diag(sigma) V^T 2000 x 50 FP64, SRHT s = 200, k = 1",
+                 "us_per_solve": ms_p * 1e3}
 
     cpu = None
     if not args.no_cpu_baseline and args.sketch_kind == "sparse":
@@ -509,6 +539,7 @@ def main():
                    "m": m, "N": N, "s": s, "k": 1},
         "sketch_gbs": sketch_gbs, "stage_ms": stage_ms, "rho": rho, "jacobi_sweeps": inf.sweeps,
         "roofline": roof, "sketch_roofline": sketch_roof, "residual_roofline": post_roof, "forms": forms,
+        "equal_residual_ratio_comparison": equal_rho, "plain_workload": plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

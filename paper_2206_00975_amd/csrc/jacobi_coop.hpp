@@ -46,8 +46,17 @@ __device__ inline double coop_reduce(double (&v)[16], int lane, int wave, double
 
 struct CoopCount {
   int rotations;   // counted by the first wave's leading lanes only
-  double offmax;   // largest squared relative cosine g^2 / (a b)
+  double offnum;   // largest squared relative cosine g^2 / (a b), kept as a fraction so that the
+  double offden;   // step needs no reciprocal: (g^2, a b) replaces it when g^2 offden > offnum a b
 };
+
+__device__ inline void count_off(CoopCount& cc, double g, double ab) {
+  const double g2 = g * g;
+  if (ab > 0 && g2 * cc.offden > cc.offnum * ab) {
+    cc.offnum = g2;
+    cc.offden = ab;
+  }
+}
 
 template <int NW, int B>
 __device__ inline void coop_intra_block(double* __restrict__ R, int ld, int blk, double2* lg, int stride,
@@ -91,7 +100,7 @@ __device__ inline void coop_intra_block(double* __restrict__ R, int ld, int blk,
     jacobi_params(alpha, beta, g, tol, c, s, t, act);
     if (lead) {
       const double ab = alpha * beta;
-      if (ab > 0) cc.offmax = fmax(cc.offmax, g * g * rcp_nr(ab));
+      count_off(cc, g, ab);
       if (act) cc.rotations++;
       lg[pi] = make_double2(c, s);
     }
@@ -164,11 +173,12 @@ __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, in
   }
   const int nxt_pair = pi + 1 == B ? 0 : (valid ? pi + 1 : pi);
   const int nxt_lane = (nxt_pair << SH) | (lane & ((1 << SH) - 1));
+  // sub-round j pairs T_i with U_{(i + j) mod B}; unrolled, so the pairing is a register choice
+#pragma unroll
   for (int j = 0; j < B; ++j) {
-    // slot i of U holds block column (i + j) mod B
     double z[16];
 #pragma unroll
-    for (int i = 0; i < B; ++i) z[i] = T[i] * U[i];
+    for (int i = 0; i < B; ++i) z[i] = T[i] * U[(i + j) % B];
     const double g = coop_reduce<B, NW>(z, lane, wave, part, buf);
     double c, s, t;
     bool act;
@@ -181,7 +191,7 @@ __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, in
     }
     if (lead) {
       const double ab = alpha * beta;
-      if (ab > 0) cc.offmax = fmax(cc.offmax, g * g * rcp_nr(ab));
+      count_off(cc, g, ab);
       if (act) cc.rotations++;
       lg[pi] = make_double2(c, s);
     }
@@ -199,14 +209,10 @@ __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, in
 #pragma unroll
     for (int i = 0; i < B; ++i) {
       const double ci = csv[i].x, si = csv[i].y;
-      const double a = T[i], b = U[i];
+      const double a = T[i], b = U[(i + j) % B];
       T[i] = ci * a - si * b;
-      U[i] = si * a + ci * b;
+      U[(i + j) % B] = si * a + ci * b;
     }
-    const double first = U[0];
-#pragma unroll
-    for (int b = 0; b < B - 1; ++b) U[b] = U[b + 1];
-    U[B - 1] = first;
     beta = __shfl(beta, nxt_lane, 64);
     lg += stride;
   }
@@ -349,7 +355,7 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
   if (threadIdx.x == 0) sh_off = 0.0;
   grid.sync();
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    CoopCount cc{0, 0.0};
+    CoopCount cc{0, 0.0, 1.0};
     double2* sweep_log = log + (size_t)sw * per_sweep;
     for (int b = blockIdx.x; b < js.nb; b += gridDim.x)
       coop_intra_block<NW, B>(R, ld, b, sweep_log + (size_t)b * 16, js.nb * 16, tol, cc, part, buf, lane, wave,
@@ -370,7 +376,7 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
       if (r == js.nb - 2 && wave == 0) {
         // this workgroup's counts of the sweep, published before the round's grid barrier
         int rot = cc.rotations;
-        double om = cc.offmax;
+        double om = cc.offnum / cc.offden;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
           rot += __shfl_xor(rot, o, 64);

@@ -15,6 +15,8 @@
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "qr_panel.hpp"
 #include "wave_ops.hpp"
 
@@ -311,25 +313,28 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
   };
 
   // panel pv's reflectors (in LDS) applied, in order, to this workgroup's columns in panels
-  // qa..qb (those with q mod G == me), CPW consecutive columns per wave task
-  auto apply = [&](int pv, int qa, int qb) {
+  // qa..qb (those with q mod G == me), CW consecutive columns per wave task (CW = CPW for the
+  // bulk of the trailing matrix; one column per wave for the single lookahead panel, so that
+  // all waves take part in the step on the critical path)
+  auto apply = [&](auto cw_tag, int pv, int qa, int qb) {
+    constexpr int CW = decltype(cw_tag)::value;
     const int j0 = pv * NB;
     const int nbc = N - j0 < NB ? N - j0 : NB;
     const int rows = s - j0;
     const double* vb = vbuf(pv);
     const double* tau = taus(pv);
     const int first_q = qa + ((me - qa % G) % G + G) % G;
-    const int per_panel_tasks = (NB + CPW - 1) / CPW;
+    const int per_panel_tasks = (NB + CW - 1) / CW;
     int ntasks = 0;
     for (int q = first_q; q <= qb; q += G) ++ntasks;
     ntasks *= per_panel_tasks;
     for (int task = wave; task < ntasks; task += nw) {
       const int q = first_q + (task / per_panel_tasks) * G;
-      const int c0 = q * NB + (task % per_panel_tasks) * CPW;
+      const int c0 = q * NB + (task % per_panel_tasks) * CW;
       const int cend = (q + 1) * NB < N ? (q + 1) * NB : N;
-      double cl[CPW][RPL];
+      double cl[CW][RPL];
 #pragma unroll
-      for (int u = 0; u < CPW; ++u) {
+      for (int u = 0; u < CW; ++u) {
         const bool cu = c0 + u < cend;
         const double* a = uniform_ptr(A + (size_t)(cu ? c0 + u : c0) * s + j0);
 #pragma unroll
@@ -342,33 +347,33 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
       for (int jj = 0; jj < nbc; ++jj) {
         const double* v = vb + (size_t)jj * s;
         double vv[RPL];
-        double d[CPW];
+        double d[CW];
 #pragma unroll
-        for (int u = 0; u < CPW; ++u) d[u] = 0;
+        for (int u = 0; u < CW; ++u) d[u] = 0;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
           const int rr = lane + 64 * i;
           vv[i] = rr < rows ? v[rr] : 0.0;
 #pragma unroll
-          for (int u = 0; u < CPW; ++u) d[u] += vv[i] * cl[u][i];
+          for (int u = 0; u < CW; ++u) d[u] += vv[i] * cl[u][i];
         }
         const double tj = tau[jj];
         {
-          constexpr int SH = 6 - ceil_log2(CPW);
+          constexpr int SH = 6 - ceil_log2(CW);
           double v16[16];
 #pragma unroll
-          for (int u = 0; u < CPW; ++u) v16[u] = d[u];
-          const double tot = reduce_t<CPW>(v16, lane);
+          for (int u = 0; u < CW; ++u) v16[u] = d[u];
+          const double tot = reduce_t<CW>(v16, lane);
 #pragma unroll
-          for (int u = 0; u < CPW; ++u) d[u] = bcast_d(tot, u << SH) * tj;
+          for (int u = 0; u < CW; ++u) d[u] = bcast_d(tot, u << SH) * tj;
         }
 #pragma unroll
         for (int i = 0; i < RPL; ++i)
 #pragma unroll
-          for (int u = 0; u < CPW; ++u) cl[u][i] -= d[u] * vv[i];
+          for (int u = 0; u < CW; ++u) cl[u][i] -= d[u] * vv[i];
       }
 #pragma unroll
-      for (int u = 0; u < CPW; ++u) {
+      for (int u = 0; u < CW; ++u) {
         if (c0 + u >= cend) continue;
         double* a = opaque_uniform(A + (size_t)(c0 + u) * s + j0);
 #pragma unroll
@@ -389,16 +394,18 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
     const int nx = p + 1;
     if (me != owner) copy(p);
     __syncthreads();
+    using One = std::integral_constant<int, 1>;
+    using Bulk = std::integral_constant<int, CPW>;
     if (nx < npanels && me == nx % G) {
-      apply(p, nx, nx);  // the next panel first, then factorise it
+      apply(One{}, p, nx, nx);  // the next panel first, then factorise it
       __syncthreads();
       factorise(nx);
     } else if (me == owner && p > 0) {
-      apply(p - 1, p + 1, npanels - 1);  // deferred while this workgroup factorised panel p
+      apply(Bulk{}, p - 1, p + 1, npanels - 1);  // deferred while this workgroup factorised panel p
       __syncthreads();
-      apply(p, p + 1, npanels - 1);
+      apply(Bulk{}, p, p + 1, npanels - 1);
     } else {
-      apply(p, p + 1, npanels - 1);
+      apply(Bulk{}, p, p + 1, npanels - 1);
     }
     __syncthreads();
   }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "nsk_internal.hpp"
+#include "wave_ops.hpp"
 
 namespace nsk {
 
@@ -269,8 +270,9 @@ template <int COLS> struct SrhtTile {
 // out[i * N + c].  Must be called by all 32 * COLS threads of the workgroup.
 // smem: at least srht_smem_bytes(s, COLS) bytes.  PF: prefetch the next block's values while
 // the current one is transformed (32 more registers a thread).
+// LDS: the block tile, one set of sign words per wave (cols / 2 waves), the sample records.
 __host__ __device__ inline size_t srht_smem_bytes(int s, int cols) {
-  return (size_t)(kT * cols + 64) * 8 + (kT / 32) * 4 + (size_t)s * 8;
+  return (size_t)(kT * cols + 64) * 8 + (size_t)(kT / 32) * 4 * (cols / 2) + (size_t)s * 8;
 }
 
 template <typename TIn, typename TAcc, int UMAX, int COLS, bool PF = true>
@@ -280,8 +282,8 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
   constexpr int NT = SrhtTile<COLS>::kThreads;
   constexpr int RS = 32 * COLS + 2;            // doubles between rows rl and rl + 32 of the tile
   double* tile = reinterpret_cast<double*>(smem);
-  uint32_t* signbits = reinterpret_cast<uint32_t*>(tile + kT * COLS + 64);
-  int2* srec = reinterpret_cast<int2*>(signbits + kT / 32);  // per sample: tile offset of i2, i1
+  uint32_t* signbits = reinterpret_cast<uint32_t*>(tile + kT * COLS + 64) + (threadIdx.x >> 6) * (kT / 32);
+  int2* srec = reinterpret_cast<int2*>(reinterpret_cast<uint32_t*>(tile + kT * COLS + 64) + (NT / 64) * (kT / 32));
 
   const int t = threadIdx.x;
   const int col = t % COLS;
@@ -319,11 +321,15 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
   // 0..4 in registers) and the sampled outer stage.  raw holds rows rs + 32 k of block j1
   // (zero past m).
   auto block = [&](int64_t j1, const TIn (&raw)[32]) {
-    __syncthreads();
-    if (t < kT / 128) {
-      const Words w = philox(seed, (uint64_t)(j1 * kT >> 7) + t, 0, kSigns);
-      *reinterpret_cast<uint4*>(signbits + 4 * t) = make_uint4(w.w[0], w.w[1], w.w[2], w.w[3]);
+    // every wave draws the block's sign words into its own slot (lanes 0..7, one Philox block
+    // each), so only the tile needs the workgroup barrier: the previous block's sampled reads
+    // are done before this block's rows are written
+    const int lane = t & 63;
+    if (lane < kT / 128) {
+      const Words w = philox(seed, (uint64_t)(j1 * kT >> 7) + lane, 0, kSigns);
+      *reinterpret_cast<uint4*>(signbits + 4 * lane) = make_uint4(w.w[0], w.w[1], w.w[2], w.w[3]);
     }
+    wave_lds_sync();
     __syncthreads();
     // phase 1: row rs + 32 k carries bit rs of sign word k (the same word across the wave)
     TAcc x[32];
