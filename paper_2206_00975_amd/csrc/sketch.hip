@@ -390,6 +390,18 @@ __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m,
             if (uu == u && hh == h) P[uu][hh] = (P[uu][hh] & ~mask) | (bits << (v * IB));
       }
     }
+    // this K step's B operands, once for every row tile
+    u32x4 bop[kGNT];
+#pragma unroll
+    for (int c = 0; c < kGNT; ++c) {
+      const unsigned char* bp = &btile[buf][(16 * c + li) * CS + 8 * kq * (FP8 ? 1 : 2)];
+      if constexpr (FP8) {
+        const u32x2 v = *reinterpret_cast<const u32x2*>(bp);
+        bop[c] = u32x4{v[0], v[1], 0u, 0u};
+      } else {
+        bop[c] = *reinterpret_cast<const u32x4*>(bp);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < MW; ++u) {
       if (mt0 + kGWaves * u >= mtiles) continue;
@@ -407,16 +419,13 @@ __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m,
 #pragma unroll
       for (int c = 0; c < kGNT; ++c) {
         if (nt0 + c >= ntiles) continue;
-        const unsigned char* bp = &btile[buf][(16 * c + li) * CS + 8 * kq * (FP8 ? 1 : 2)];
         if constexpr (FP8) {
-          const u32x2 bv = *reinterpret_cast<const u32x2*>(bp);
           const long av = (long)((unsigned long)(R[0] | (R[1] << 16)) | ((unsigned long)(R[2] | (R[3] << 16)) << 32));
-          const long bb = (long)((unsigned long)bv[0] | ((unsigned long)bv[1] << 32));
+          const long bb = (long)((unsigned long)bop[c][0] | ((unsigned long)bop[c][1] << 32));
           acc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bb, acc[u][c], 0, 0, 0);
         } else {
-          const u32x4 bv = *reinterpret_cast<const u32x4*>(bp);
           const bf16x8 av = __builtin_bit_cast(bf16x8, u32x4{R[0], R[1], R[2], R[3]});
-          acc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bv), acc[u][c], 0, 0, 0);
+          acc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bop[c]), acc[u][c], 0, 0, 0);
         }
       }
     }

@@ -64,14 +64,17 @@ __device__ inline float e4m3_round_f64(double x) {
 // sine and cosine absolute error <= 1.9e-7.
 struct GaussPair { float g0, g1, r; };
 __device__ inline GaussPair box_muller32(uint32_t a, uint32_t b) {
-  float l2;
-  if (a < 0x80000000u) {
-    l2 = __builtin_amdgcn_logf(fmaf((float)a, 0x1p-32f, 0x1p-32f));
-  } else {
-    const float x = (float)(~a) * 0x1p-32f;
-    const float w = 1.0f - x;
-    l2 = (w == 1.0f) ? -x * 1.4426950408889634f : __builtin_amdgcn_logf(w) * (x / (1.0f - w));
-  }
+  // both branches evaluated and selected (one logarithm a pair); the identity's ratio
+  // x / (1 - w) takes the reciprocal estimate and one Newton step
+  const bool low = a < 0x80000000u;
+  const float u = fmaf((float)a, 0x1p-32f, 0x1p-32f);
+  const float x = (float)(~a) * 0x1p-32f;
+  const float w = 1.0f - x;
+  const float dw = 1.0f - w;
+  float rc = __builtin_amdgcn_rcpf(dw);
+  rc = fmaf(rc, fmaf(-dw, rc, 1.0f), rc);
+  const float lg = __builtin_amdgcn_logf(low ? u : w);
+  const float l2 = low ? lg : (w == 1.0f ? -x * 1.4426950408889634f : lg * (x * rc));
   const float r = __builtin_sqrtf(-1.3862943611198906f * l2);
   const float v = (float)(int32_t)b * 0x1p-32f;
   return GaussPair{r * __builtin_amdgcn_cosf(v), r * __builtin_amdgcn_sinf(v), r};
