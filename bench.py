@@ -198,11 +198,18 @@ def suite(nsk, W, torch, np, only=None):
         ms_b, outs = _timed(torch, lambda: nsk.trailing_rsv_batched(As, ks, ss, seeds), 3)
         total_bytes = sum(mi * ni * 4 for mi, ni in shapes)
         ang = [metrics.sin_theta(vp.cpu().numpy(), o[0].cpu().numpy()) for vp, o in zip(Vps[:64], outs[:64])]
+        # the widest instance alone: through the batched launch (one workgroup runs its SVD) and
+        # through the single-instance path (cooperative QR and Jacobi)
+        big = max(range(len(shapes)), key=lambda i: (shapes[i][1], shapes[i][0]))
+        ms_one, _ = _timed(torch, lambda: nsk.trailing_rsv_batched([As[big]], [4], [ss[big]], [seeds[big]]), 3)
+        ms_single, _ = _timed(torch, lambda: nsk.trailing_rsv(As[big], 4, "srht", ss[big], seeds[big]), 3)
         rec4 = {"suite": "batched", "workload": "512 planted instances, m in [5000, 200000], n in [16, 256], "
                                                  "FP32, SRHT s = 4n, k = 4",
                 "ms": ms_b, "instances_per_s": 512 / (ms_b * 1e-3), "input_gb": total_bytes / 1e9,
                 "input_gbs": total_bytes / (ms_b * 1e-3) / 1e9,
-                "planted_subspace_sin_theta_median_first64": float(np.median(ang))}
+                "planted_subspace_sin_theta_median_first64": float(np.median(ang)),
+                "widest_instance": {"m": shapes[big][0], "n": shapes[big][1], "ms_alone_batched": ms_one,
+                                    "ms_alone_single_instance_path": ms_single}}
         print(json.dumps(rec4), flush=True)
         del As, outs
 
