@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst*
       w.N = I.N;
       w.k = I.k;
       w.max_sweeps = I.max_sweeps;
-      svd_pipeline<kBatchThreads>(w, smem);
+      svd_pipeline(w, smem);
     }
     __syncthreads();
   }

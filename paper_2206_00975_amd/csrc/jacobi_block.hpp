@@ -416,32 +416,21 @@ __device__ inline int jacobi_block_sweeps(double* __restrict__ R, const JacobiSh
 // Between steps the slots move exactly as the Jacobi kernel's registers did, here with DPP
 // row rotations inside the 16- or 8-lane group.  A vector group of replay_waves(js) waves
 // replays one vector (x in LDS, nb * B doubles); several groups replay different vectors at
-// once, all from one copy of the log.
+// once.
 //
-// The log is staged one phase (the intra phase of a sweep, or one block round) at a time:
-// the whole workgroup loads the next phase's entries into registers while the current phase
-// is applied from LDS.  Entry k of a phase sits at k + k / 16 in LDS, so that the 16-entry
-// groups of one step fall in different banks.
-constexpr int kReplayMaxEntries = 4608;  // largest phase for N <= 320: 9 steps x 32 blocks x 16
-
-__host__ __device__ constexpr size_t replay_stage_bytes() {
-  return (size_t)(kReplayMaxEntries + kReplayMaxEntries / 16) * sizeof(double2);
-}
-
-// entries per thread that a workgroup of `threads` threads prefetches per phase
-__host__ __device__ constexpr int replay_per_thread(int threads) {
-  return (kReplayMaxEntries + threads - 1) / threads;
-}
+// A phase is the intra phase of a sweep or one block round.  Every lane reads its own
+// rotations of a phase (at most B, one per step, in processing order) straight from the log
+// into registers, one phase ahead, so a step is a rotation and a slot move with no memory
+// access on the chain; one barrier per phase hands x over between the lanes of a group.
 
 // waves per vector group: 8 lanes per block in the intra phase (16 per pair in a round)
 __host__ __device__ inline int replay_waves(const JacobiShape& js) { return (js.nb * 8 + 63) / 64; }
 
 // Phase k of the replay (processing order) of `sweeps` sweeps: its sweep, round (-1 for the
-// intra phase), first log entry and entry count.
+// intra phase) and first log entry.
 struct ReplayPhase {
   int sw, r;
   size_t begin;
-  int len;
 };
 
 __device__ inline ReplayPhase replay_phase(const JacobiShape& js, size_t per_sweep, int sweeps, bool fwd, int k) {
@@ -453,118 +442,132 @@ __device__ inline ReplayPhase replay_phase(const JacobiShape& js, size_t per_swe
   const size_t intra = (size_t)(js.bq - 1) * js.nb * 16;
   const size_t round = (size_t)js.B * (js.nb / 2) * 16;
   ph.begin = (size_t)ph.sw * per_sweep + (ph.r < 0 ? 0 : intra + (size_t)ph.r * round);
-  ph.len = (int)(ph.r < 0 ? intra : round);
   return ph;
 }
 
-template <int PER>
-__device__ inline void replay_prefetch(const double2* __restrict__ log, const ReplayPhase& ph, double2 (&pre)[PER]) {
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + (int)blockDim.x * u;
-    pre[u] = e < ph.len ? log[ph.begin + e] : make_double2(1.0, 0.0);
-  }
-}
-
-template <int PER>
-__device__ inline void replay_stage(double2* stage, const double2 (&pre)[PER]) {
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int k = threadIdx.x + (int)blockDim.x * u;
-    if (k < kReplayMaxEntries) stage[k + (k >> 4)] = pre[u];
-  }
-}
-
-__device__ inline void rot_pair(double& x, double& y, double2 cs, bool fwd) {
-  const double c = cs.x, s = fwd ? cs.y : -cs.y;
+template <bool FWD>
+__device__ inline void rot_pair(double& x, double& y, double2 cs) {
+  const double c = cs.x, s = FWD ? cs.y : -cs.y;
   const double a = x, b = y;
   x = c * a - s * b;
   y = s * a + c * b;
 }
 
-// All threads of the workgroup call this with the same arguments except x and vl: vl is the
-// thread's lane within its vector group (0 .. 64 * replay_waves - 1), member is false for
-// threads outside any group (they take part in the barriers only), x the group's vector.
-// PER >= replay_per_thread(blockDim.x).
-template <int B, int PER>
-__device__ inline void jacobi_replay(double* x, const double2* __restrict__ log, const JacobiShape& js, int sweeps,
-                                     bool fwd, int vl, bool member, double2* stage) {
+// The lane's rotations of phase ph in processing order: e[u] is step u (FWD) or step
+// n - 1 - u (backward) of the phase's n steps; (1, 0) past n and for idle lanes, so that
+// every lane can rotate unconditionally (idle lanes hold zeros).
+template <int B, bool FWD>
+__device__ inline void replay_fetch(const double2* __restrict__ log, const JacobiShape& js, const ReplayPhase& ph,
+                                    int vl, bool member, double2 (&e)[B]) {
+  constexpr int BQ = B + (B & 1);
+  const bool intra = ph.r < 0;
+  const int n = intra ? BQ - 1 : B;
+  const int grp = intra ? vl >> 3 : vl >> 4, i = intra ? vl & 7 : vl & 15;
+  const int groups = intra ? js.nb : js.nb / 2;  // log groups per step
+  const bool act = member && grp < groups && i < (intra ? BQ / 2 : B);
+  const double2* base = log + ph.begin + (size_t)grp * 16 + i;
+  const size_t step = (size_t)groups * 16;
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    const int st = FWD ? u : n - 1 - u;
+    e[u] = act && u < n ? base[st * step] : make_double2(1.0, 0.0);
+  }
+}
+
+template <int B, bool FWD>
+__device__ inline void jacobi_replay_dir(double* x, const double2* __restrict__ log, const JacobiShape& js,
+                                         int sweeps, int vl, bool member) {
   constexpr int BQ = B + (B & 1);
   constexpr int H = BQ / 2;
   const int nb = js.nb, nbp = js.nb / 2;
   const size_t per_sweep = jacobi_log_entries_per_sweep(js);
   const int nphases = sweeps * nb;
-  double2 pre[PER];
-  if (nphases > 0) replay_prefetch<PER>(log, replay_phase(js, per_sweep, sweeps, fwd, 0), pre);
-  for (int k = 0; k < nphases; ++k) {
-    const ReplayPhase ph = replay_phase(js, per_sweep, sweeps, fwd, k);
-    lds_barrier();  // the previous phase is done with the stage and its x updates are visible
-    replay_stage<PER>(stage, pre);
-    lds_barrier();
-    if (k + 1 < nphases) replay_prefetch<PER>(log, replay_phase(js, per_sweep, sweeps, fwd, k + 1), pre);
+  // lane roles: intra phase lane 8 g + i (positions i and BQ-1-i of block g), block round
+  // lane 16 g + i (T_i and U slot i of pair g); idle lanes hold zeros and rotate by (1, 0)
+  const int gi = vl >> 3, ii = vl & 7;
+  const bool act_i = member && gi < nb && ii < H;
+  const int gr = vl >> 4, ir = vl & 15;
+  const bool act_r = member && gr < nbp && ir < B;
+  // phase k applies cur while phase k + 1's rotations load into nxt; the two buffers swap
+  // roles every phase (two phases per loop trip, so no register copies)
+  auto phase = [&](int k, const double2 (&cur)[B], double2 (&nxt)[B]) {
+    const ReplayPhase ph = replay_phase(js, per_sweep, sweeps, FWD, k);
+    if (k + 1 < nphases)
+      replay_fetch<B, FWD>(log, js, replay_phase(js, per_sweep, sweeps, FWD, k + 1), vl, member, nxt);
+    lds_barrier();  // the previous phase's x updates are visible
     if (ph.r < 0) {
-      // ---- intra phase: lane 8 g + i holds positions i and BQ-1-i of block g
-      const int g = vl >> 3, i = vl & 7;
-      const bool act = member && g < nb && i < H;
-      const int pa = i, pb = BQ - 1 - i;
-      double a = act && pa < B ? x[g * B + pa] : 0.0;
-      double b = act && pb < B ? x[g * B + pb] : 0.0;
-      const int base = 17 * g + i;  // entry (step q, group g, slot i) at 17 (q nb + g) + i
-      for (int qi = 0; qi < BQ - 1; ++qi) {
-        const int q = fwd ? qi : BQ - 2 - qi;
-        if (!fwd && H > 1) {  // undo the circle shift that followed step q
+      const int pa = ii, pb = BQ - 1 - ii;
+      double a = act_i && pa < B ? x[gi * B + pa] : 0.0;
+      double b = act_i && pb < B ? x[gi * B + pb] : 0.0;
+#pragma unroll
+      for (int u = 0; u < BQ - 1; ++u) {
+        if constexpr (!FWD && H > 1) {  // undo the circle shift that followed the step
           const double a_prev = lane_plus<15>(a), b_prev = lane_plus<15>(b), b_next = lane_plus<1>(b);
-          const double na = i == 0 ? a : i == 1 ? b_prev : a_prev;
-          const double nbv = i + 1 < H ? b_next : a;
+          const double na = ii == 0 ? a : ii == 1 ? b_prev : a_prev;
+          const double nbv = ii + 1 < H ? b_next : a;
           a = na;
           b = nbv;
         }
-        if (act) rot_pair(a, b, stage[17 * q * nb + base], fwd);
-        if (fwd && H > 1) {  // circle shift: position p takes p + 1 (p >= 1), the last takes 1
+        rot_pair<FWD>(a, b, cur[u]);
+        if constexpr (FWD && H > 1) {  // circle shift: position p takes p + 1 (p >= 1), the last takes 1
           const double a_next = lane_plus<1>(a), b_prev = lane_plus<15>(b);
-          const double na = i == 0 ? a : i + 1 < H ? a_next : b;
-          const double nbv = i == 0 ? a_next : b_prev;
+          const double na = ii == 0 ? a : ii + 1 < H ? a_next : b;
+          const double nbv = ii == 0 ? a_next : b_prev;
           a = na;
           b = nbv;
         }
       }
-      if (act) {
-        if (pa < B) x[g * B + pa] = a;
-        if (pb < B) x[g * B + pb] = b;
+      if (act_i) {
+        if (pa < B) x[gi * B + pa] = a;
+        if (pb < B) x[gi * B + pb] = b;
       }
     } else {
-      // ---- block round: lane 16 g + i holds T_i and U slot i of pair g
-      const int g = vl >> 4, i = vl & 15;
-      const bool act = member && g < nbp && i < B;
-      const int gg = g < nbp ? g : 0;
+      const int gg = gr < nbp ? gr : 0;
       int I = circle_pos(gg, ph.r, nb), J = circle_pos(nb - 1 - gg, ph.r, nb);
       if (I > J) {
         const int u = I;
         I = J;
         J = u;
       }
-      double T = act ? x[I * B + i] : 0.0;
-      double U = act ? x[J * B + i] : 0.0;
-      const int base = 17 * g + i;  // entry (step j, group g, slot i) at 17 (j nbp + g) + i
-      for (int ji = 0; ji < B; ++ji) {
-        const int j = fwd ? ji : B - 1 - ji;
-        if (!fwd) {  // undo the slot move that followed sub-round j
+      double T = act_r ? x[I * B + ir] : 0.0;
+      double U = act_r ? x[J * B + ir] : 0.0;
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if constexpr (!FWD) {  // undo the slot move that followed the sub-round
           const double from_prev = lane_plus<15>(U), from_last = lane_plus<(B - 1) % 16 ? (B - 1) % 16 : 15>(U);
-          U = i == 0 ? from_last : from_prev;
+          U = ir == 0 ? from_last : from_prev;
         }
-        if (act) rot_pair(T, U, stage[17 * j * nbp + base], fwd);
-        if (fwd) {  // slot i takes slot i + 1 (mod B)
+        rot_pair<FWD>(T, U, cur[u]);
+        if constexpr (FWD) {  // slot i takes slot i + 1 (mod B)
           const double from_next = lane_plus<1>(U), from_first = lane_plus<(17 - B) % 16 ? (17 - B) % 16 : 1>(U);
-          U = i == B - 1 ? from_first : from_next;
+          U = ir == B - 1 ? from_first : from_next;
         }
       }
-      if (act) {
-        x[I * B + i] = T;
-        x[J * B + i] = U;
+      if (act_r) {
+        x[I * B + ir] = T;
+        x[J * B + ir] = U;
       }
     }
+  };
+  double2 e0[B], e1[B];
+  if (nphases > 0) replay_fetch<B, FWD>(log, js, replay_phase(js, per_sweep, sweeps, FWD, 0), vl, member, e0);
+  for (int k = 0; k < nphases; k += 2) {
+    phase(k, e0, e1);
+    if (k + 1 < nphases) phase(k + 1, e1, e0);
   }
   lds_barrier();
+}
+
+// All threads of the workgroup call this with the same arguments except x and vl: vl is the
+// thread's lane within its vector group (0 .. 64 * replay_waves - 1), member is false for
+// threads outside any group (they take part in the barriers only), x the group's vector.
+template <int B>
+__device__ inline void jacobi_replay(double* x, const double2* __restrict__ log, const JacobiShape& js, int sweeps,
+                                     bool fwd, int vl, bool member) {
+  if (fwd)
+    jacobi_replay_dir<B, true>(x, log, js, sweeps, vl, member);
+  else
+    jacobi_replay_dir<B, false>(x, log, js, sweeps, vl, member);
 }
 
 }  // namespace nsk

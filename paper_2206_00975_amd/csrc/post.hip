@@ -248,7 +248,6 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
   const int ncols = js.nb * js.B;
   double* xb = sm;             // ncols
   double* wl = xb + ncols;     // N: w
-  double2* stage = reinterpret_cast<double2*>(sm + ((ncols + N + 1) & ~1));
   __shared__ double red[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = N - 1;
@@ -269,7 +268,7 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
   __syncthreads();
   const int sweeps = tb.jres->sweeps;
   const int vw = replay_waves(js);
-  replay_any<replay_per_thread(512)>(xb, tb.log, js, sweeps, true, tid, wave < vw, stage);
+  replay_any(xb, tb.log, js, sweeps, true, tid, wave < vw);
   __syncthreads();
   const int cN = tb.order[N - 1];
   const double lamN = tb.colnorm[cN] * tb.colnorm[cN];
@@ -278,7 +277,7 @@ __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack 
     xb[c] = (c < N && c != cN) ? xb[c] / (lamN - sc * sc) : 0.0;
   }
   __syncthreads();
-  replay_any<replay_per_thread(512)>(xb, tb.log, js, sweeps, false, tid, wave < vw, stage);
+  replay_any(xb, tb.log, js, sweeps, false, tid, wave < vw);
   __syncthreads();
   for (int e = tid; e < N; e += blockDim.x) wl[e] = xb[e];
   __syncthreads();
@@ -408,7 +407,7 @@ hipError_t launch_tls_backward(const SketchPlan& p, int64_t m, const TlsBack& tb
                                void* dA, int64_t ldda, void* db, int out_dtype, hipStream_t st) {
   const int N = p.N, s = p.s;
   const JacobiShape js = jacobi_shape(N);
-  const size_t alds = (size_t)((js.nb * js.B + N + 1) & ~1) * sizeof(double) + replay_stage_bytes();
+  const size_t alds = (size_t)((js.nb * js.B + N + 1) & ~1) * sizeof(double);
   if (hipError_t e = lds_limit((const void*)tls_adjoint_kernel, alds)) return e;
   tls_adjoint_kernel<<<1, 512, alds, st>>>(s, N, tb, gx, work);
   const size_t lds = (size_t)(2 * s + 2 * N) * sizeof(double) + (size_t)s * 4;

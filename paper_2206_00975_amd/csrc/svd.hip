@@ -143,7 +143,7 @@ static hipError_t launch_jacobi_coop(SvdWork& w, hipStream_t st) {
 template <int NR>
 __global__ __launch_bounds__(kFinishThreads) void svd_finish_kernel(SvdWork w) {
   extern __shared__ unsigned char smem[];
-  svd_stage_finish_nr<NR, replay_per_thread(kFinishThreads)>(w, smem);
+  svd_stage_finish_nr<NR>(w, smem);
 }
 
 

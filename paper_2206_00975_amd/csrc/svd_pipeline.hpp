@@ -69,7 +69,7 @@ __host__ __device__ inline size_t finish_vec_bytes(int N) {
 
 __host__ __device__ inline size_t svd_fast_lds_bytes(int s, int N, int nwaves) {
   const size_t qr = qr_panel_lds_bytes(s, qr_panel_width(s, nwaves));
-  const size_t fin = finish_head_bytes(N) + replay_stage_bytes() + (size_t)finish_groups(N, nwaves) * finish_vec_bytes(N);
+  const size_t fin = finish_head_bytes(N) + (size_t)finish_groups(N, nwaves) * finish_vec_bytes(N);
   return qr > fin ? qr : fin;
 }
 
@@ -144,20 +144,18 @@ __device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
 // ---------------------------------------------------------------- stage 3: finish
 // x <- V x (fwd = false) or V^T x (fwd = true), any block size; called by every thread of
 // the workgroup (see jacobi_replay)
-template <int PER>
 __device__ inline void replay_any(double* x, const double2* log, const JacobiShape& js, int sweeps, bool fwd,
-                                  int vl, bool member, double2* stage) {
+                                  int vl, bool member) {
   switch (js.NR) {
-    case 1: jacobi_replay<jacobi_block_size(1), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
-    case 2: jacobi_replay<jacobi_block_size(2), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
-    case 3: jacobi_replay<jacobi_block_size(3), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
-    case 4: jacobi_replay<jacobi_block_size(4), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
-    default: jacobi_replay<jacobi_block_size(5), PER>(x, log, js, sweeps, fwd, vl, member, stage); break;
+    case 1: jacobi_replay<jacobi_block_size(1)>(x, log, js, sweeps, fwd, vl, member); break;
+    case 2: jacobi_replay<jacobi_block_size(2)>(x, log, js, sweeps, fwd, vl, member); break;
+    case 3: jacobi_replay<jacobi_block_size(3)>(x, log, js, sweeps, fwd, vl, member); break;
+    case 4: jacobi_replay<jacobi_block_size(4)>(x, log, js, sweeps, fwd, vl, member); break;
+    default: jacobi_replay<jacobi_block_size(5)>(x, log, js, sweeps, fwd, vl, member); break;
   }
 }
 
-// PER = replay_per_thread(blockDim.x) of the calling kernel
-template <int NR, int PER>
+template <int NR>
 __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem) {
   const JacobiShape js = jacobi_shape(w.N);
   const int N = w.N, k = w.k;
@@ -170,9 +168,7 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
   const int grp = wave / vw;
   const bool member = grp < ngroups;
   const int vl = (wave - grp * vw) * 64 + lane;
-  double2* stage = reinterpret_cast<double2*>(smem + finish_head_bytes(N));
-  double* x = reinterpret_cast<double*>(smem + finish_head_bytes(N) + replay_stage_bytes() +
-                                        (size_t)(member ? grp : 0) * finish_vec_bytes(N));
+  double* x = reinterpret_cast<double*>(smem + finish_head_bytes(N) + (size_t)(member ? grp : 0) * finish_vec_bytes(N));
   // singular values: column norms of the rotated R
   for (int c = wave; c < N; c += nw) {
     double a = 0;
@@ -209,7 +205,7 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
       for (int e = vl; e < ncols; e += vw * 64) x[e] = e == c ? 1.0 : 0.0;
     }
     lds_barrier();
-    jacobi_replay<jacobi_block_size(NR), PER>(x, w.log, js, sweeps, false, vl, mine, stage);
+    jacobi_replay<jacobi_block_size(NR)>(x, w.log, js, sweeps, false, vl, mine);
     // sign: largest-magnitude entry positive, lowest index on ties (first wave of the group)
     if (mine && vl < 64) {
       double best = -1;
@@ -246,23 +242,21 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
   __syncthreads();
 }
 
-template <int PER>
 __device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
   switch (jacobi_shape(w.N).NR) {
-    case 1: svd_stage_finish_nr<1, PER>(w, smem); break;
-    case 2: svd_stage_finish_nr<2, PER>(w, smem); break;
-    case 3: svd_stage_finish_nr<3, PER>(w, smem); break;
-    case 4: svd_stage_finish_nr<4, PER>(w, smem); break;
-    default: svd_stage_finish_nr<5, PER>(w, smem); break;
+    case 1: svd_stage_finish_nr<1>(w, smem); break;
+    case 2: svd_stage_finish_nr<2>(w, smem); break;
+    case 3: svd_stage_finish_nr<3>(w, smem); break;
+    case 4: svd_stage_finish_nr<4>(w, smem); break;
+    default: svd_stage_finish_nr<5>(w, smem); break;
   }
 }
 
-// the single-workgroup SVD; THREADS = blockDim.x of the calling kernel
-template <int THREADS>
+// the single-workgroup SVD
 __device__ inline void svd_pipeline(const SvdWork& w, unsigned char* smem) {
   svd_stage_qr(w, smem);
   svd_stage_jacobi(w, smem);
-  svd_stage_finish<replay_per_thread(THREADS)>(w, smem);
+  svd_stage_finish(w, smem);
 }
 
 }  // namespace nsk

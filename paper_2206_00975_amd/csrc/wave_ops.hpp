@@ -53,8 +53,9 @@ template <int K>
 __device__ inline double lane_plus(double v) {
   static_assert(K >= 1 && K <= 15, "lane_plus takes 1..15");
   constexpr int ctrl = 0x120 + (16 - K);
-  return dpp_join(__builtin_amdgcn_update_dpp(0, dlo(v), ctrl, 0xF, 0xF, false),
-                  __builtin_amdgcn_update_dpp(0, dhi(v), ctrl, 0xF, 0xF, false));
+  // every lane has a source in its row, so no old value is needed (no register initialisation)
+  return dpp_join(__builtin_amdgcn_mov_dpp(dlo(v), ctrl, 0xF, 0xF, true),
+                  __builtin_amdgcn_mov_dpp(dhi(v), ctrl, 0xF, 0xF, true));
 }
 
 __device__ inline double bcast_d(double v, int lane) {
