@@ -188,20 +188,53 @@ __device__ inline void qr_coop(double* __restrict__ A, int s, int N, double* __r
 
 // The same factorisation with a one-panel lookahead.  After panel p is published, the owner
 // of panel p + 1 applies p's reflectors to panel p + 1 only and factorises it at once; its
-// other columns receive panel p after the next grid barrier, just before panel p + 1.  So the
-// barrier of panel p + 1 waits for one panel's worth of updates and one factorisation rather
-// than for the owner's whole share of the trailing matrix.  Reflectors of two panels live in
-// LDS at a time (double buffer).  Within a factorisation the pivot entry is read from its
-// lane, and the later columns keep the reflector in registers between the dot product and
-// the update.  Needs at least two workgroups (the lookahead owner differs from the panel's).
-// LDS: qr_coop_la_lds_bytes(s, NB).
+// other columns receive panel p afterwards, together with panel p + 1.  Reflectors of two
+// panels live in LDS at a time (double buffer).  Within a factorisation the pivot entry is read
+// from its lane, and the later columns keep the reflector in registers between the dot product
+// and the update.  Needs at least two workgroups (the lookahead owner differs from the panel's).
+//
+// No grid barrier per panel: the only dependency between workgroups is that panel p's
+// reflectors are complete before anyone reads them, so its owner raises a flag (flags[p]) after
+// writing them and every other workgroup waits for that flag alone before copying them; each
+// workgroup applies the panels to its own columns in order.  The wait is bounded: past
+// kQrSpinLimit polls a workgroup raises flags[npanels] (abort), every later wait returns at
+// once, and the factor is marked invalid (R[0] = NaN), so a fault in the protocol cannot hang
+// the GPU.  flags: npanels + 1 words of global scratch.  LDS: qr_coop_la_lds_bytes(s, NB).
 __host__ __device__ inline size_t qr_coop_la_lds_bytes(int s, int NB) {
   return 2 * ((size_t)NB * s * 8 + (size_t)NB * 8) + 64;
 }
 
+constexpr unsigned kQrSpinLimit = 1u << 20;
+
+// Every wave's stores have reached the L2 (each waits for its own), then one thread releases
+// them at agent scope (the L2's dirty lines are written back for the other XCDs) with the flag.
+__device__ inline void qr_publish(unsigned* flag) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One thread polls the flag, then takes an agent-scope acquire (stale cached lines dropped for
+// the whole workgroup, whose waves share the CU's caches) before the workgroup reads.
+__device__ inline void qr_wait(unsigned* flag, unsigned* abort_word) {
+  if (threadIdx.x == 0) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins == kQrSpinLimit) {
+        __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
 template <int RPL, int NB, int CPW>
 __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* __restrict__ R, int ldr,
-                                  size_t r_elems, double* __restrict__ tau_g, unsigned char* smem) {
+                                  size_t r_elems, double* __restrict__ tau_g, unsigned* flags, unsigned char* smem) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
   double* vbase = reinterpret_cast<double*>(smem);
@@ -386,13 +419,21 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
     }
   };
 
-  grid.sync();  // R zeroed everywhere before any panel writes into it
-  if (me == 0 % G) factorise(0);
+  if (me == 0)
+    for (int i = threadIdx.x; i <= npanels; i += blockDim.x) flags[i] = 0u;
+  grid.sync();  // R and the flags zeroed everywhere before any panel writes or polls them
+  unsigned* abort_word = flags + npanels;
+  if (me == 0 % G) {
+    factorise(0);
+    qr_publish(flags);
+  }
   for (int p = 0; p < npanels; ++p) {
-    grid.sync();  // panel p's reflectors are in A and tau_g
     const int owner = p % G;
     const int nx = p + 1;
-    if (me != owner) copy(p);
+    if (me != owner) {
+      qr_wait(flags + p, abort_word);  // panel p's reflectors are in A and tau_g
+      copy(p);
+    }
     __syncthreads();
     using One = std::integral_constant<int, 1>;
     using Bulk = std::integral_constant<int, CPW>;
@@ -400,6 +441,7 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
       apply(One{}, p, nx, nx);  // the next panel first, then factorise it
       __syncthreads();
       factorise(nx);
+      qr_publish(flags + nx);
     } else if (me == owner && p > 0) {
       apply(Bulk{}, p - 1, p + 1, npanels - 1);  // deferred while this workgroup factorised panel p
       __syncthreads();
@@ -409,6 +451,9 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
     }
     __syncthreads();
   }
+  // a wait that gave up leaves a wrong factor: mark it (no later write in this launch touches R[0])
+  if (threadIdx.x == 0 && __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+    R[0] = __builtin_nan("");
 }
 
 }  // namespace nsk

@@ -86,15 +86,17 @@ template <int RPL>
 __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_coop_la_kernel(SvdWork w) {
   extern __shared__ unsigned char smem[];
   constexpr int C = QrCpw<RPL>::value;
+  // the rotation log is free until the Jacobi stage: the panel flags live at its start
+  unsigned* flags = reinterpret_cast<unsigned*>(w.log);
   const JacobiShape js = jacobi_shape(w.N);
   const int ldr = 64 * js.NR;
   const size_t relems = (size_t)ldr * js.nb * js.B;
   switch (qr_panel_width(w.s, blockDim.x >> 6)) {
-    case 16: qr_coop_la<RPL, 16, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
-    case 8: qr_coop_la<RPL, 8, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
-    case 4: qr_coop_la<RPL, 4, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
-    case 2: qr_coop_la<RPL, 2, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
-    default: qr_coop_la<RPL, 1, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, smem); break;
+    case 16: qr_coop_la<RPL, 16, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
+    case 8: qr_coop_la<RPL, 8, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
+    case 4: qr_coop_la<RPL, 4, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
+    case 2: qr_coop_la<RPL, 2, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
+    default: qr_coop_la<RPL, 1, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
   }
 }
 
