@@ -19,10 +19,51 @@
 
 namespace nsk {
 
-// Per-sweep rotation counts and largest relative cosines, then the two words of the Gram
-// check (violation flag, largest squared cosine), appended to the rotation log.
+// Per-sweep rotation counts and largest relative cosines, the two words of the Gram check
+// (violation flag, largest squared cosine), then the block versions and the abort word of the
+// round hand-over (kCoopVersionWords 64-bit words), appended to the rotation log.
+constexpr int kCoopMaxBlocks = 64;
+constexpr int kCoopVersionWords = kCoopMaxBlocks + 1;
+
 __host__ __device__ inline size_t jacobi_coop_counter_bytes(int max_sweeps) {
-  return ((size_t)max_sweeps * 2 + 2) * sizeof(unsigned long long);
+  return ((size_t)max_sweeps * 2 + 2 + kCoopVersionWords) * sizeof(unsigned long long);
+}
+
+// Hand-over of blocks between block rounds without a grid barrier.  A block is written once
+// per phase (the intra phase, then each of the nb - 1 rounds), so after phase ph of sweep sw
+// its version is sw * nb + ph + 1.  The workgroup that wrote a block publishes the new version
+// once every wave's stores have reached the L2 (agent-scope release); the workgroup that takes
+// the block in the next round polls the two versions it needs (one thread, bounded) and takes
+// an agent-scope acquire.  Past kCoopSpinLimit polls the abort word is raised, every later wait
+// returns at once, and the result is marked invalid, so a protocol fault cannot hang the GPU.
+constexpr unsigned kCoopSpinLimit = 1u << 20;
+
+__device__ inline void coop_publish(unsigned long long* ver, int I, int J, unsigned long long v) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&ver[I], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (J != I) __hip_atomic_store(&ver[J], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ inline void coop_wait(unsigned long long* ver, int I, int J, unsigned long long v,
+                                 unsigned long long* abort_word) {
+  if (threadIdx.x == 0) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(&ver[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v ||
+           __hip_atomic_load(&ver[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+      if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins == kCoopSpinLimit) {
+        __hip_atomic_store(abort_word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
 }
 
 
@@ -348,8 +389,12 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
   const double tol = (double)N * 0x1p-53;
   unsigned long long* rot_count = counters;
   unsigned long long* off_bits = counters + max_sweeps;
-  if (blockIdx.x == 0)
+  unsigned long long* ver = counters + 2 * max_sweeps + 2;
+  unsigned long long* abort_word = ver + kCoopMaxBlocks;
+  if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < 2 * max_sweeps; i += blockDim.x) counters[i] = 0;
+    for (int i = threadIdx.x; i < kCoopVersionWords; i += blockDim.x) ver[i] = 0;
+  }
   int buf = 0;
   int sweeps = 0, conv = 0;
   if (threadIdx.x == 0) sh_off = 0.0;
@@ -357,10 +402,13 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
   for (int sw = 0; sw < max_sweeps; ++sw) {
     CoopCount cc{0, 0.0, 1.0};
     double2* sweep_log = log + (size_t)sw * per_sweep;
-    for (int b = blockIdx.x; b < js.nb; b += gridDim.x)
+    // the sweep starts after a grid barrier, so the intra phase needs no wait
+    const unsigned long long base_ver = (unsigned long long)sw * js.nb;
+    for (int b = blockIdx.x; b < js.nb; b += gridDim.x) {
       coop_intra_block<NW, B>(R, ld, b, sweep_log + (size_t)b * 16, js.nb * 16, tol, cc, part, buf, lane, wave,
                               bcs[wave]);
-    grid.sync();
+      coop_publish(ver, b, b, base_ver + 1);
+    }
     for (int r = 0; r < js.nb - 1; ++r) {
       double2* round_log = sweep_log + jacobi_log_step_offset(js, js.bq - 1 + r * B);
       for (int i = blockIdx.x; i < nbp; i += gridDim.x) {
@@ -370,8 +418,10 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
           I = J;
           J = t;
         }
+        coop_wait(ver, I, J, base_ver + 1 + r, abort_word);
         coop_inter_pair<NW, B>(R, ld, I, J, round_log + (size_t)i * 16, nbp * 16, tol, cc, part, buf, lane, wave,
                                bcs[wave]);
+        coop_publish(ver, I, J, base_ver + 2 + r);
       }
       if (r == js.nb - 2 && wave == 0) {
         // this workgroup's counts of the sweep, published before the round's grid barrier
@@ -387,8 +437,8 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
           atomicMax(&off_bits[sw], (unsigned long long)__double_as_longlong(om));
         }
       }
-      grid.sync();
     }
+    grid.sync();  // the sweep's counts are complete and every block is final
     if (threadIdx.x == 0) {
       sh_rot = (int)__hip_atomic_load(&rot_count[sw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       sh_off = __longlong_as_double(
@@ -413,9 +463,12 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // a hand-over that gave up leaves wrong columns: report no convergence and poison R
+    const bool aborted = __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull;
     jres->sweeps = sweeps;
-    jres->converged = conv;
+    jres->converged = aborted ? 0 : conv;
     jres->off = sweeps > 0 ? sqrt(sh_off) : 0.0;
+    if (aborted) R[0] = __builtin_nan("");
   }
 }
 
