@@ -109,19 +109,26 @@ __device__ inline double rsq_nr(double x, int steps) {
   }
   return y;
 }
+// Rotation of the column pair with squared norms a, b and inner product g.  The Rutishauser
+// form t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / (2 g), c = 1 / sqrt(1 + t^2),
+// s = c t, is evaluated without zeta: with d = b - a and r = sqrt(d^2 + 4 g^2),
+// t = sign(d) 2 g / (|d| + r), 1 + t^2 = 2 r / (|d| + r), so c = w u and s = sign(d) 2 g u with
+// w = |d| + r and u = 1 / sqrt(2 r w).  c and s then follow from two reciprocal square roots in
+// a chain instead of two reciprocals and two reciprocal square roots; t (for the norm updates
+// a - t g, b + t g) takes a reciprocal of w beside the second.  c^2 + s^2 = 2 r w u^2 = 1 to
+// rounding.  (sign(0) = +1.)
 __device__ inline void jacobi_params(double a, double b, double g, double tol, double& c, double& s,
                                      double& t, bool& act) {
   act = g * g > (tol * tol) * (a * b);
-  const double zeta = (b - a) * rcp_nr(2.0 * g);
-  const double az = fabs(zeta);
-  const double q = fma(zeta, zeta, 1.0);
-  const double root = az > 1e150 ? az : q * rsq_nr(q, 2);     // sqrt(1 + zeta^2)
-  const double r = rcp_nr(az + root);
-  const double tt = zeta >= 0 ? r : -r;
-  const double cc = rsq_nr(fma(tt, tt, 1.0), 2);
-  c = act ? cc : 1.0;
-  s = act ? cc * tt : 0.0;
-  t = act ? tt : 0.0;
+  const double d = b - a;
+  const double q = fma(d, d, 4.0 * g * g);
+  const double r = q * rsq_nr(q, 2);
+  const double w = fabs(d) + r;
+  const double u = rsq_nr(2.0 * r * w, 2);
+  const double g2 = d >= 0 ? 2.0 * g : -2.0 * g;
+  c = act ? w * u : 1.0;
+  s = act ? g2 * u : 0.0;
+  t = act ? g2 * rcp_nr(w) : 0.0;
 }
 
 template <int NR>
