@@ -37,17 +37,22 @@ def jacobi_flops(N: int, sweeps: int) -> float:
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_tls_1e6x201_sparse_s804.md")
 
 
-def library_source_hash() -> str:
-    """sha256 prefix over the library's HIP/C++ sources and its header (the same digest the
-    HBM traffic summary records at measurement time)."""
+# translation unit of the library that defines each measured kernel (name prefix)
+KERNEL_SOURCES = (("svd_", "svd.hip"), ("sparse_", "sketch.hip"), ("srht_", "sketch.hip"), ("reduce_", "sketch.hip"),
+                  ("srdct_", "srdct.hip"), ("residual_", "post.hip"), ("tls_", "post.hip"))
+
+
+def kernel_source_hash(unit: str) -> str:
+    """sha256 prefix over one library translation unit (paper_2206_00975_amd/csrc/<unit>), every
+    header of the library and include/nsk.h: what a kernel defined in that unit is built from.
+    The HBM traffic summary records it per unit at measurement time."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2206_00975_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(f.read())
+    for name in [unit] + sorted(f for f in os.listdir(d) if f.endswith(".hpp")):
+        h.update(name.encode())
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
     with open(os.path.join(ROOT, "include", "nsk.h"), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
@@ -55,14 +60,15 @@ def library_source_hash() -> str:
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` (fetched + written, calibrated against a plain copy)
-    from the committed rocprofv3 counter summary of this workload, or None when the library
-    sources changed after the counters were taken or the kernel is not listed."""
+    from the committed rocprofv3 counter summary of this workload, or None when the sources the
+    kernel is built from changed after the counters were taken or the kernel is not listed."""
     try:
         with open(TRAFFIC_SUMMARY) as f:
             text = f.read()
     except OSError:
         return None
-    if f"`{library_source_hash()}`" not in text:
+    unit = next((u for prefix, u in KERNEL_SOURCES if kernel.startswith(prefix)), None)
+    if unit is None or f"`{unit}`: `{kernel_source_hash(unit)}`" not in text:
         return None
     for line in text.splitlines():
         if line.startswith(f"| `nsk::{kernel}<") or line.startswith(f"| `nsk::{kernel}`"):
@@ -356,6 +362,8 @@ def main():
     ap.add_argument("--n", type=int, default=200)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--acc", default="f64", choices=["f64", "f32"],
+                    help="sketch accumulation of the timed workload: FP64 (default) or the plain-FP32 form")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--sketch-kind", default="sparse", choices=["sparse", "srht", "srdct"],
                     help="sketch of the timed solves (the headline workload is sparse sign)")
@@ -407,12 +415,12 @@ def main():
     A, b = Mt[:, :n], Mt[:, n:]            # two column blocks, no concatenated copy
     print(f"[bench] input {m}x{N} FP32 resident ({Mt.numel() * 4 / 1e6:.0f} MB)", file=sys.stderr, flush=True)
 
-    def step(seed=7, acc="f64", s_=s, ws=None, state=None, kind=args.sketch_kind):
+    def step(seed=7, acc=args.acc, s_=s, ws=None, state=None, kind=args.sketch_kind):
         return nsk.tls_solve(A, b, kind=kind, s=s_, seed=seed, acc=acc, residual=True, ws=ws, state=state)
 
     x, state, info = step()
     torch.cuda.synchronize()
-    ws = nsk._ws(nsk.workspace_bytes(m, N, 1, nsk.make_desc(args.sketch_kind, s, 7, 8)), dev)
+    ws = nsk._ws(nsk.workspace_bytes(m, N, 1, nsk.make_desc(args.sketch_kind, s, 7, 8, acc=args.acc)), dev)
     for _ in range(args.warmup):
         step(ws=ws, state=state)
     torch.cuda.synchronize()
@@ -539,7 +547,7 @@ def main():
         "metric": "trailing-RSV solves/s + sketch HBM GB/s vs plain FP32 at residual ratio<=1.1",
         "value": 1000.0 / ms_per_step, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32-in/f64-acc", "data": "synthetic",
+        "vs_baseline": None, "dtype": f"f32-in/{args.acc}-acc", "data": "synthetic",
         "config": {"workload": (f"TLS [A|b] {m:,} x {N} FP32, "
                                 + {"sparse": "sparse-sign sketch zeta=8", "srht": "SRHT sketch",
                                    "srdct": "DCT-II SRFT sketch"}[args.sketch_kind] + f", s={s}, k=1"),
