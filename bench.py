@@ -70,10 +70,13 @@ def measured_traffic(kernel: str):
     unit = next((u for prefix, u in KERNEL_SOURCES if kernel.startswith(prefix)), None)
     if unit is None or f"`{unit}`: `{kernel_source_hash(unit)}`" not in text:
         return None
+    cols = None
     for line in text.splitlines():
-        if line.startswith(f"| `nsk::{kernel}<") or line.startswith(f"| `nsk::{kernel}`"):
-            cells = [c.strip() for c in line.strip("|").split("|")]
-            return (float(cells[3]) + float(cells[4])) * 1e6
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if "fetched MB" in cells and "written MB" in cells:
+            cols = (cells.index("fetched MB"), cells.index("written MB"))
+        elif cols and (line.startswith(f"| `nsk::{kernel}<") or line.startswith(f"| `nsk::{kernel}`")):
+            return (float(cells[cols[0]]) + float(cells[cols[1]])) * 1e6
     return None
 
 
