@@ -48,17 +48,34 @@ __host__ __device__ constexpr int jacobi_block_size(int NR) {
   return NR == 1 ? 4 : NR == 2 ? 8 : NR == 3 ? 12 : NR == 4 ? 13 : NR == 5 ? 10 : NR <= 8 ? 6 : 3;
 }
 
-__host__ __device__ inline JacobiShape jacobi_shape(int N) {
+// Block size of the one-workgroup Jacobi (eight waves, a wave holding a whole block pair at NR
+// rows per lane).  It keeps the multi-workgroup blocks while their nb / 2 pairs fit the eight
+// waves in one pass.  Past that (NR = 4 with N > 208) a round takes two passes of the waves
+// anyway, and blocks of 8 make those two passes full (16 pairs at N = 256) with each pair's two
+// 8-column blocks in 128 registers a lane, where 13-column blocks (208 registers) spill.
+__host__ __device__ constexpr int jacobi_block_size_wg(int NR, int N) {
+  return NR == 4 && N > 16 * jacobi_block_size(4) ? 8 : jacobi_block_size(NR);
+}
+
+__host__ __device__ inline JacobiShape jacobi_shape_of(int N, int B) {
   JacobiShape s;
   s.N = N;
   s.NR = jacobi_nr(N);
-  s.B = jacobi_block_size(s.NR);
+  s.B = B;
   s.nb = (N + s.B - 1) / s.B;
   if (s.nb < 2) s.nb = 2;
   s.nb += s.nb & 1;
   s.bq = s.B + (s.B & 1);
   s.spw = (s.bq - 1) + s.B * (s.nb - 1);
   return s;
+}
+
+// shape of the multi-workgroup Jacobi (and of the one-workgroup one for NR <= 2)
+__host__ __device__ inline JacobiShape jacobi_shape(int N) { return jacobi_shape_of(N, jacobi_block_size(jacobi_nr(N))); }
+
+// shape of the one-workgroup Jacobi
+__host__ __device__ inline JacobiShape jacobi_shape_wg(int N) {
+  return jacobi_shape_of(N, jacobi_block_size_wg(jacobi_nr(N), N));
 }
 
 // Log layout of one sweep: intra steps have nb groups (blocks) of 16 slots, inter steps

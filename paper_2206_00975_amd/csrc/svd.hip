@@ -145,7 +145,7 @@ static hipError_t launch_jacobi_coop(SvdWork& w, hipStream_t st) {
 template <int NR>
 __global__ __launch_bounds__(kFinishThreads) void svd_finish_kernel(SvdWork w) {
   extern __shared__ unsigned char smem[];
-  svd_stage_finish_nr<NR>(w, smem);
+  svd_stage_finish_nr<NR, JacobiB<NR>::value>(w, jacobi_shape(w.N), smem);
 }
 
 
@@ -203,7 +203,7 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
     if (e != hipSuccess) return e;
     prof_mark(4, st);
     const int tf = kFinishThreads;
-    const size_t lf = svd_fast_lds_bytes(p.s, p.N, tf / 64);
+    const size_t lf = finish_lds_bytes(jacobi_shape(p.N), tf / 64);  // the log's shape (see svd_stage_finish_nr)
     switch (jacobi_shape(p.N).NR) {
       case 1:
         e = lds_attr((const void*)svd_finish_kernel<1>, lf);

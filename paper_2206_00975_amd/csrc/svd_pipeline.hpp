@@ -1,8 +1,10 @@
 // SVD of the sketch SA for N <= 320 and s <= 4096: panel Householder QR -> block
 // one-sided Jacobi with a rotation log -> singular values, ordering and the requested
 // right singular vectors rebuilt from the log.  Every stage runs inside one workgroup and
-// synchronises with barriers only (the batched persistent kernel calls it directly); the
-// single-instance path launches the three stages as three kernels.
+// synchronises with barriers only (the batched persistent kernel calls it directly, with the
+// one-workgroup block shape jacobi_shape_wg); the single-instance path launches the stages as
+// kernels (one-workgroup QR and Jacobi for N <= 64, where the two shapes agree; the
+// multi-workgroup kernels and the finish stage with jacobi_shape above).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,11 +33,13 @@ struct SvdWork {
   int s, N, k, max_sweeps;
 };
 
-// rotation log, followed by the per-sweep counters of the multi-workgroup Jacobi
+// rotation log, followed by the per-sweep counters of the multi-workgroup Jacobi; large enough
+// for the log of either shape (the one-workgroup Jacobi keeps no counters)
 __host__ __device__ inline size_t svd_fast_log_bytes(int N, int max_sweeps) {
-  const JacobiShape js = jacobi_shape(N);
-  return (size_t)max_sweeps * jacobi_log_entries_per_sweep(js) * sizeof(double2) +
-         jacobi_coop_counter_bytes(max_sweeps);
+  const size_t coop = (size_t)max_sweeps * jacobi_log_entries_per_sweep(jacobi_shape(N)) * sizeof(double2) +
+                      jacobi_coop_counter_bytes(max_sweeps);
+  const size_t wg = (size_t)max_sweeps * jacobi_log_entries_per_sweep(jacobi_shape_wg(N)) * sizeof(double2);
+  return coop > wg ? coop : wg;
 }
 
 __host__ __device__ inline unsigned long long* jacobi_counters(double2* log, int N, int max_sweeps) {
@@ -44,8 +48,9 @@ __host__ __device__ inline unsigned long long* jacobi_counters(double2* log, int
 }
 
 __host__ __device__ inline size_t svd_fast_R_bytes(int N) {
-  const JacobiShape js = jacobi_shape(N);
-  return (size_t)64 * js.NR * js.nb * js.B * sizeof(double);
+  const JacobiShape a = jacobi_shape(N), b = jacobi_shape_wg(N);
+  const int cols = a.nb * a.B > b.nb * b.B ? a.nb * a.B : b.nb * b.B;
+  return (size_t)64 * a.NR * cols * sizeof(double);
 }
 
 __host__ __device__ inline int qr_panel_width(int s, int nwaves) {
@@ -54,22 +59,26 @@ __host__ __device__ inline int qr_panel_width(int s, int nwaves) {
   return nb;
 }
 
-// vector groups of the finish stage that replay concurrently
-__host__ __device__ inline int finish_groups(int N, int nwaves) {
-  const int g = nwaves / replay_waves(jacobi_shape(N));
+// vector groups of the finish stage that replay concurrently (js: the Jacobi's shape)
+__host__ __device__ inline int finish_groups(const JacobiShape& js, int nwaves) {
+  const int g = nwaves / replay_waves(js);
   return g > 0 ? g : 1;
 }
 
 __host__ __device__ inline size_t finish_head_bytes(int N) { return ((size_t)N * 12 + 255) & ~(size_t)255; }
 
-__host__ __device__ inline size_t finish_vec_bytes(int N) {
-  const JacobiShape js = jacobi_shape(N);
+__host__ __device__ inline size_t finish_vec_bytes(const JacobiShape& js) {
   return ((size_t)js.nb * js.B * 8 + 255) & ~(size_t)255;
 }
 
+__host__ __device__ inline size_t finish_lds_bytes(const JacobiShape& js, int nwaves) {
+  return finish_head_bytes(js.N) + (size_t)finish_groups(js, nwaves) * finish_vec_bytes(js);
+}
+
+// LDS of the one-workgroup pipeline (QR, then the finish stage in the one-workgroup shape)
 __host__ __device__ inline size_t svd_fast_lds_bytes(int s, int N, int nwaves) {
   const size_t qr = qr_panel_lds_bytes(s, qr_panel_width(s, nwaves));
-  const size_t fin = finish_head_bytes(N) + (size_t)finish_groups(N, nwaves) * finish_vec_bytes(N);
+  const size_t fin = finish_lds_bytes(jacobi_shape_wg(N), nwaves);
   return qr > fin ? qr : fin;
 }
 
@@ -83,10 +92,11 @@ struct QrCpw {
   static constexpr int value = RPL <= 16 ? 4 : RPL <= 32 ? 2 : 1;
 };
 
+// R goes into the one-workgroup Jacobi's layout
 template <int RPL>
 __device__ inline void svd_stage_qr_rpl(const SvdWork& w, unsigned char* smem) {
   constexpr int C = QrCpw<RPL>::value;
-  const JacobiShape js = jacobi_shape(w.N);
+  const JacobiShape js = jacobi_shape_wg(w.N);
   const int ldr = 64 * js.NR;
   const size_t total = (size_t)ldr * js.nb * js.B;
   for (size_t e = threadIdx.x; e < total; e += blockDim.x) w.R[e] = 0.0;
@@ -110,9 +120,10 @@ __device__ inline void svd_stage_qr(const SvdWork& w, unsigned char* smem) {
 }
 
 // ---------------------------------------------------------------- stage 2: Jacobi
+// the one-workgroup Jacobi, in the shape jacobi_shape_wg(w.N) (B must be its block size)
 template <int NR, int B>
 __device__ inline void svd_stage_jacobi_nr(const SvdWork& w, unsigned char* smem) {
-  const JacobiShape js = jacobi_shape(w.N);
+  const JacobiShape js = jacobi_shape_wg(w.N);
   int* sh_rot = reinterpret_cast<int*>(smem);
   double* sh_off = reinterpret_cast<double*>(smem + 8);
   int conv = 0;
@@ -131,12 +142,16 @@ struct JacobiB {
   static constexpr int value = jacobi_block_size(NR);
 };
 
+
 __device__ inline void svd_stage_jacobi(const SvdWork& w, unsigned char* smem) {
   switch (jacobi_shape(w.N).NR) {
     case 1: svd_stage_jacobi_nr<1, JacobiB<1>::value>(w, smem); break;
     case 2: svd_stage_jacobi_nr<2, JacobiB<2>::value>(w, smem); break;
     case 3: svd_stage_jacobi_nr<3, JacobiB<3>::value>(w, smem); break;
-    case 4: svd_stage_jacobi_nr<4, JacobiB<4>::value>(w, smem); break;
+    case 4:
+      if (jacobi_shape_wg(w.N).B == 8) svd_stage_jacobi_nr<4, 8>(w, smem);
+      else svd_stage_jacobi_nr<4, JacobiB<4>::value>(w, smem);
+      break;
     default: svd_stage_jacobi_nr<5, JacobiB<5>::value>(w, smem); break;
   }
 }
@@ -155,20 +170,21 @@ __device__ inline void replay_any(double* x, const double2* log, const JacobiSha
   }
 }
 
-template <int NR>
-__device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem) {
-  const JacobiShape js = jacobi_shape(w.N);
+// The log was written in the shape js with blocks of B (the one-workgroup shape in the batched
+// pipeline, the multi-workgroup one after the single-instance kernels).
+template <int NR, int B>
+__device__ inline void svd_stage_finish_nr(const SvdWork& w, const JacobiShape& js, unsigned char* smem) {
   const int N = w.N, k = w.k;
   const int ldr = 64 * js.NR;
   const int ncols = js.nb * js.B;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   double* nrm = reinterpret_cast<double*>(smem);
   int* rk = reinterpret_cast<int*>(nrm + N);
-  const int vw = replay_waves(js), ngroups = finish_groups(N, nw);
+  const int vw = replay_waves(js), ngroups = finish_groups(js, nw);
   const int grp = wave / vw;
   const bool member = grp < ngroups;
   const int vl = (wave - grp * vw) * 64 + lane;
-  double* x = reinterpret_cast<double*>(smem + finish_head_bytes(N) + (size_t)(member ? grp : 0) * finish_vec_bytes(N));
+  double* x = reinterpret_cast<double*>(smem + finish_head_bytes(N) + (size_t)(member ? grp : 0) * finish_vec_bytes(js));
   // singular values: column norms of the rotated R
   for (int c = wave; c < N; c += nw) {
     double a = 0;
@@ -205,7 +221,7 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
       for (int e = vl; e < ncols; e += vw * 64) x[e] = e == c ? 1.0 : 0.0;
     }
     lds_barrier();
-    jacobi_replay<jacobi_block_size(NR)>(x, w.log, js, sweeps, false, vl, mine);
+    jacobi_replay<B>(x, w.log, js, sweeps, false, vl, mine);
     // sign: largest-magnitude entry positive, lowest index on ties (first wave of the group)
     if (mine && vl < 64) {
       double best = -1;
@@ -243,12 +259,16 @@ __device__ inline void svd_stage_finish_nr(const SvdWork& w, unsigned char* smem
 }
 
 __device__ inline void svd_stage_finish(const SvdWork& w, unsigned char* smem) {
-  switch (jacobi_shape(w.N).NR) {
-    case 1: svd_stage_finish_nr<1>(w, smem); break;
-    case 2: svd_stage_finish_nr<2>(w, smem); break;
-    case 3: svd_stage_finish_nr<3>(w, smem); break;
-    case 4: svd_stage_finish_nr<4>(w, smem); break;
-    default: svd_stage_finish_nr<5>(w, smem); break;
+  const JacobiShape js = jacobi_shape_wg(w.N);
+  switch (js.NR) {
+    case 1: svd_stage_finish_nr<1, JacobiB<1>::value>(w, js, smem); break;
+    case 2: svd_stage_finish_nr<2, JacobiB<2>::value>(w, js, smem); break;
+    case 3: svd_stage_finish_nr<3, JacobiB<3>::value>(w, js, smem); break;
+    case 4:
+      if (js.B == 8) svd_stage_finish_nr<4, 8>(w, js, smem);
+      else svd_stage_finish_nr<4, JacobiB<4>::value>(w, js, smem);
+      break;
+    default: svd_stage_finish_nr<5, JacobiB<5>::value>(w, js, smem); break;
   }
 }
 
