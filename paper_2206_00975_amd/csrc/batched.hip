@@ -57,7 +57,7 @@ template <typename TIn, typename TAcc>
 __global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst* __restrict__ insts,
                                                                const BatchTile* __restrict__ tiles, int ntiles,
                                                                int* __restrict__ counters) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_task;
   __shared__ int sh_last;
   const int tid = threadIdx.x;
@@ -109,6 +109,8 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst*
       w.N = I.N;
       w.k = I.k;
       w.max_sweeps = I.max_sweeps;
+      w.coop_local = 0;
+      w.coop_stride = 1;
       svd_pipeline(w, smem);
     }
     __syncthreads();

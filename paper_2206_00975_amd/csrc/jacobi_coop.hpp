@@ -21,28 +21,31 @@ namespace nsk {
 
 // Per-sweep rotation counts and largest relative cosines, the two words of the Gram check
 // (violation flag, largest squared cosine), then the block versions and the abort word of the
-// round hand-over (kCoopVersionWords 64-bit words), appended to the rotation log.
+// round hand-over (kCoopVersionWords 64-bit words) and the workers' XCC ids (kCoopMaxBlocks / 2
+// 32-bit words), appended to the rotation log.
 constexpr int kCoopMaxBlocks = 64;
 constexpr int kCoopVersionWords = kCoopMaxBlocks + 1;
 
 __host__ __device__ inline size_t jacobi_coop_counter_bytes(int max_sweeps) {
-  return ((size_t)max_sweeps * 2 + 2 + kCoopVersionWords) * sizeof(unsigned long long);
+  return ((size_t)max_sweeps * 2 + 2 + kCoopVersionWords) * sizeof(unsigned long long) +
+         (size_t)(kCoopMaxBlocks / 2) * sizeof(unsigned);
 }
 
 // Hand-over of blocks between block rounds without a grid barrier.  A block is written once
 // per phase (the intra phase, then each of the nb - 1 rounds), so after phase ph of sweep sw
 // its version is sw * nb + ph + 1.  The workgroup that wrote a block publishes the new version
-// once every wave's stores have reached the L2 (agent-scope release); the workgroup that takes
-// the block in the next round polls the two versions it needs (one thread, bounded) and takes
-// an agent-scope acquire.  Past kCoopSpinLimit polls the abort word is raised, every later wait
-// returns at once, and the result is marked invalid, so a protocol fault cannot hang the GPU.
+// once every wave's stores have reached the L2 (with workers on several XCDs, after an
+// agent-scope release); the workgroup that takes the block in the next round polls the two
+// versions it needs (one thread, bounded) and takes an agent-scope acquire.  Past
+// kCoopSpinLimit polls the abort word is raised, every later wait returns at once, and the
+// result is marked invalid, so a protocol fault cannot hang the GPU.
 constexpr unsigned kCoopSpinLimit = 1u << 20;
 
-__device__ inline void coop_publish(unsigned long long* ver, int I, int J, unsigned long long v) {
+__device__ inline void coop_publish(unsigned long long* ver, int I, int J, unsigned long long v, bool local) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(&ver[I], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (J != I) __hip_atomic_store(&ver[J], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -273,7 +276,7 @@ __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, in
 // summed through LDS) and tests them.  flags: two words (violation, largest squared cosine,
 // which is returned in off2).
 template <int NW, int B>
-__device__ inline bool coop_gram_clear(const double* __restrict__ R, const JacobiShape& js, int N, double tol,
+__device__ inline bool coop_gram_clear(const double* __restrict__ R, const JacobiShape& js, int N, double tol, int stride,
                                        double* __restrict__ norms_g, unsigned long long* flags,
                                        double (*part)[NW][16], int& buf, int lane, int wave, double& off2) {
   namespace cg = cooperative_groups;
@@ -284,12 +287,13 @@ __device__ inline bool coop_gram_clear(const double* __restrict__ R, const Jacob
   __shared__ double gp[NW][NCH * 16];
   __shared__ unsigned long long sh_flags[2];
   const int ld = 64 * NW;
-  const int G = gridDim.x;
+  const int G = coop_workers(stride);
+  const int me = coop_worker(stride) ? coop_worker_index(stride) : js.nb * js.nb;  // other workgroups take no work
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     flags[0] = 0;
     flags[1] = 0;
   }
-  for (int b = blockIdx.x; b < js.nb; b += G) {
+  for (int b = me; b < js.nb; b += G) {
     const double* p = uniform_ptr(R + (size_t)b * B * ld) + 64 * wave + lane;
     double v[16];
 #pragma unroll
@@ -307,7 +311,7 @@ __device__ inline bool coop_gram_clear(const double* __restrict__ R, const Jacob
   const int npairs = js.nb * (js.nb + 1) / 2;
   bool bad = false;
   double om = 0.0;
-  for (int bp = blockIdx.x; bp < npairs; bp += G) {
+  for (int bp = me; bp < npairs; bp += G) {
     int I = 0, rem = bp;
     while (rem >= js.nb - I) {
       rem -= js.nb - I;
@@ -370,11 +374,14 @@ __device__ inline bool coop_gram_clear(const double* __restrict__ R, const Jacob
 }
 
 // Sweeps until one performs no rotation (or max_sweeps).  Launched cooperatively with
-// nb / 2 workgroups of NW * 64 threads, NW = rows / 64.  counters: 2 * max_sweeps words.
+// `stride` workgroups per worker (see coop_worker) and nb / 2 workers of NW * 64 threads,
+// NW = rows / 64; the other workgroups take part in the grid barriers only.  counters:
+// jacobi_coop_counter_bytes(max_sweeps).  allow_local: take the one-XCD hand-over when the
+// placement allows.
 template <int NW, int B>
 __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max_sweeps, double2* __restrict__ log,
                                           unsigned long long* __restrict__ counters, JacobiResult* jres,
-                                          double* __restrict__ scratch) {
+                                          double* __restrict__ scratch, int stride, bool allow_local) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
   __shared__ double part[2][NW][16];
@@ -391,27 +398,33 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
   unsigned long long* off_bits = counters + max_sweeps;
   unsigned long long* ver = counters + 2 * max_sweeps + 2;
   unsigned long long* abort_word = ver + kCoopMaxBlocks;
+  unsigned* xcc_ids = reinterpret_cast<unsigned*>(ver + kCoopVersionWords);
+  const int G = coop_workers(stride);
+  const bool worker = coop_worker(stride);
+  const int me = worker ? coop_worker_index(stride) : js.nb;  // other workgroups take no blocks
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < 2 * max_sweeps; i += blockDim.x) counters[i] = 0;
     for (int i = threadIdx.x; i < kCoopVersionWords; i += blockDim.x) ver[i] = 0;
   }
+  xcd_record(xcc_ids, stride);
   int buf = 0;
   int sweeps = 0, conv = 0;
   if (threadIdx.x == 0) sh_off = 0.0;
   grid.sync();
+  const bool local = xcd_all_local(xcc_ids, stride, allow_local);
   for (int sw = 0; sw < max_sweeps; ++sw) {
     CoopCount cc{0, 0.0, 1.0};
     double2* sweep_log = log + (size_t)sw * per_sweep;
     // the sweep starts after a grid barrier, so the intra phase needs no wait
     const unsigned long long base_ver = (unsigned long long)sw * js.nb;
-    for (int b = blockIdx.x; b < js.nb; b += gridDim.x) {
+    for (int b = me; b < js.nb; b += G) {
       coop_intra_block<NW, B>(R, ld, b, sweep_log + (size_t)b * 16, js.nb * 16, tol, cc, part, buf, lane, wave,
                               bcs[wave]);
-      coop_publish(ver, b, b, base_ver + 1);
+      coop_publish(ver, b, b, base_ver + 1, local);
     }
     for (int r = 0; r < js.nb - 1; ++r) {
       double2* round_log = sweep_log + jacobi_log_step_offset(js, js.bq - 1 + r * B);
-      for (int i = blockIdx.x; i < nbp; i += gridDim.x) {
+      for (int i = me; i < nbp; i += G) {
         int I = circle_pos(i, r, js.nb), J = circle_pos(js.nb - 1 - i, r, js.nb);
         if (I > J) {
           const int t = I;
@@ -421,9 +434,9 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
         coop_wait(ver, I, J, base_ver + 1 + r, abort_word);
         coop_inter_pair<NW, B>(R, ld, I, J, round_log + (size_t)i * 16, nbp * 16, tol, cc, part, buf, lane, wave,
                                bcs[wave]);
-        coop_publish(ver, I, J, base_ver + 2 + r);
+        coop_publish(ver, I, J, base_ver + 2 + r, local);
       }
-      if (r == js.nb - 2 && wave == 0) {
+      if (r == js.nb - 2 && wave == 0 && worker) {
         // this workgroup's counts of the sweep, published before the round's grid barrier
         int rot = cc.rotations;
         double om = cc.offnum / cc.offden;
@@ -454,7 +467,7 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
     }
     if (sh_off <= kGramCheckCos2) {
       double off2 = 0.0;
-      if (coop_gram_clear<NW, B>(R, js, N, tol, scratch, counters + 2 * max_sweeps, part, buf, lane, wave, off2)) {
+      if (coop_gram_clear<NW, B>(R, js, N, tol, stride, scratch, counters + 2 * max_sweeps, part, buf, lane, wave, off2)) {
         if (threadIdx.x == 0) sh_off = off2;
         __syncthreads();
         conv = 1;

@@ -97,6 +97,35 @@ __host__ __device__ inline int64_t xcd_work_item(int64_t b, int64_t n) {
   return w < n ? w : -1;
 }
 
+// Cooperative kernels whose workgroups hand data to each other (the multi-workgroup QR and
+// Jacobi) launch `stride` workgroups per worker and keep only b = stride w as worker w; with
+// stride = kXcds and the dealing above all workers run on one XCD and share its L2 (stride 1
+// where the device has too few CUs for that launch).  Each worker records the
+// hardware XCC id it runs on (hwreg XCC_ID) before the launch's first grid barrier; after it,
+// xcd_all_local tells every worker whether all W ids agree.  When they do, the writer of a
+// hand-over needs no L2 write-back (agent-scope release): it waits for its stores, which the
+// vector L1 writes through to the shared L2, and raises its flag.  The reader always takes an
+// agent-scope acquire (buffer_inv sc1): it drops the CU's stale L1 lines, which a
+// workgroup-scope invalidate (buffer_inv sc0) leaves in place, measured on gfx950, and keeps the
+// dirty lines of the shared L2.  With workers on several XCDs the writer keeps the release.
+__device__ inline unsigned xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (15 << 11)); }
+__device__ inline bool coop_worker(int stride) { return blockIdx.x % stride == 0; }
+__device__ inline int coop_worker_index(int stride) { return (int)(blockIdx.x / stride); }
+__device__ inline int coop_workers(int stride) { return (int)(gridDim.x / stride); }
+__device__ inline void xcd_record(unsigned* ids, int stride) {
+  if (coop_worker(stride) && threadIdx.x == 0) ids[coop_worker_index(stride)] = xcc_id();
+}
+// After a grid barrier that follows every worker's xcd_record (at most 64 workers); the same in
+// every wave.  Lane w of each wave compares worker w's id with worker 0's (vector loads, no
+// LDS: static LDS here would shift the callers' dynamic LDS off its 8-byte alignment).
+__device__ inline bool xcd_all_local(const unsigned* ids, int stride, bool allowed) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int W = coop_workers(stride);
+  const unsigned mine = lane < W ? __hip_atomic_load(&ids[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+  const unsigned first = __shfl(mine, 0, 64);
+  return allowed && W <= 64 && __all(lane >= W || mine == first);
+}
+
 __host__ __device__ inline int64_t next_pow2(int64_t m) {
   int64_t p = 1;
   while (p < m) p <<= 1;

@@ -61,7 +61,7 @@ template <typename T, int KQ, int RT, int CI>
 __global__ __launch_bounds__(kResThreads) void residual_kernel(Operand op, int64_t m, int N,
                                                                const double* __restrict__ Vk, int k,
                                                                double* __restrict__ partial) {
-  extern __shared__ double vsh[];  // N x k row-major
+  extern __shared__ __align__(16) double vsh[];  // N x k row-major
   __shared__ double wsum[kResThreads / 64];
   for (int e = threadIdx.x; e < N * k; e += blockDim.x) vsh[e] = Vk[e];
   __syncthreads();
@@ -243,7 +243,7 @@ hipError_t launch_count_below(const double* sigma, int N, double eps, int relati
 // Jacobi rotation log forward (transposed) and backward.  work = [SA v (s), SA w (s), v, w].
 __global__ __launch_bounds__(512) void tls_adjoint_kernel(int s, int N, TlsBack tb, const double* __restrict__ gx,
                                                            double* __restrict__ work) {
-  extern __shared__ double sm[];
+  extern __shared__ __align__(16) double sm[];
   const JacobiShape js = jacobi_shape(N);
   const int ncols = js.nb * js.B;
   double* xb = sm;             // ncols
@@ -330,7 +330,7 @@ template <typename TOut, int ZMAX>
 __global__ __launch_bounds__(256) void tls_grad_sparse_kernel(int64_t m, int N, int s, int zeta, uint64_t seed,
                                                               const double* __restrict__ work, TOut* __restrict__ dA,
                                                               int64_t ldda, TOut* __restrict__ db) {
-  extern __shared__ double sm[];
+  extern __shared__ __align__(16) double sm[];
   double* yv = sm;
   double* yw = yv + s;
   double* vv = yw + s;
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void tls_grad_srht_kernel(int64_t m, int N, in
                                                             const int* __restrict__ rows,
                                                             const double* __restrict__ work, TOut* __restrict__ dA,
                                                             int64_t ldda, TOut* __restrict__ db) {
-  extern __shared__ double sm[];
+  extern __shared__ __align__(16) double sm[];
   double* yv = sm;
   double* yw = yv + s;
   double* vv = yw + s;

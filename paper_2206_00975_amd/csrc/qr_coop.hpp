@@ -206,12 +206,16 @@ __host__ __device__ inline size_t qr_coop_la_lds_bytes(int s, int NB) {
 
 constexpr unsigned kQrSpinLimit = 1u << 20;
 
-// Every wave's stores have reached the L2 (each waits for its own), then one thread releases
-// them at agent scope (the L2's dirty lines are written back for the other XCDs) with the flag.
-__device__ inline void qr_publish(unsigned* flag) {
+// Every wave's stores have reached the L2 (each waits for its own), then one thread raises the
+// flag; with workers on several XCDs it first releases the stores at agent scope (the L2's
+// dirty lines are written back for the other XCDs).
+__device__ inline void qr_publish(unsigned* flag, bool local) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    if (local) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // One thread polls the flag, then takes an agent-scope acquire (stale cached lines dropped for
@@ -232,9 +236,12 @@ __device__ inline void qr_wait(unsigned* flag, unsigned* abort_word) {
   __syncthreads();
 }
 
+// Launched with `stride` workgroups per worker (see coop_worker); flags: npanels + 1 words, then
+// one XCC id word per worker.  allow_local: take the one-XCD hand-over when the placement allows.
 template <int RPL, int NB, int CPW>
 __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* __restrict__ R, int ldr,
-                                  size_t r_elems, double* __restrict__ tau_g, unsigned* flags, unsigned char* smem) {
+                                  size_t r_elems, double* __restrict__ tau_g, unsigned* flags, int stride,
+                                  bool allow_local, unsigned char* smem) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
   double* vbase = reinterpret_cast<double*>(smem);
@@ -242,8 +249,10 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
   auto vbuf = [&](int p) { return vbase + (size_t)(p & 1) * ((size_t)NB * s + NB); };
   auto taus = [&](int p) { return vbuf(p) + (size_t)NB * s; };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int G = gridDim.x, me = blockIdx.x;
-  for (size_t e = (size_t)me * blockDim.x + threadIdx.x; e < r_elems; e += (size_t)G * blockDim.x) R[e] = 0.0;
+  const int G = coop_workers(stride), me = coop_worker_index(stride);
+  const bool worker = coop_worker(stride);
+  if (worker)
+    for (size_t e = (size_t)me * blockDim.x + threadIdx.x; e < r_elems; e += (size_t)G * blockDim.x) R[e] = 0.0;
   const int npanels = (N + NB - 1) / NB;
 
   auto factorise = [&](int p) {
@@ -419,13 +428,17 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
     }
   };
 
-  if (me == 0)
+  unsigned* xcc_ids = flags + npanels + 1;
+  if (blockIdx.x == 0)
     for (int i = threadIdx.x; i <= npanels; i += blockDim.x) flags[i] = 0u;
+  xcd_record(xcc_ids, stride);
   grid.sync();  // R and the flags zeroed everywhere before any panel writes or polls them
+  if (!worker) return;
+  const bool local = xcd_all_local(xcc_ids, stride, allow_local);
   unsigned* abort_word = flags + npanels;
   if (me == 0 % G) {
     factorise(0);
-    qr_publish(flags);
+    qr_publish(flags, local);
   }
   for (int p = 0; p < npanels; ++p) {
     const int owner = p % G;
@@ -441,7 +454,7 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
       apply(One{}, p, nx, nx);  // the next panel first, then factorise it
       __syncthreads();
       factorise(nx);
-      qr_publish(flags + nx);
+      qr_publish(flags + nx, local);
     } else if (me == owner && p > 0) {
       apply(Bulk{}, p - 1, p + 1, npanels - 1);  // deferred while this workgroup factorised panel p
       __syncthreads();

@@ -35,7 +35,7 @@ static size_t rht_block_lds_bytes(int cols) { return (size_t)(kRhtT * cols + 64)
 template <typename TIn, int COLS>
 __global__ __launch_bounds__(32 * COLS) void rht_block_kernel(Operand op, int64_t m, int N, uint64_t seed,
                                                               int64_t B, double* __restrict__ Y) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   constexpr int RS = 32 * COLS + 2;
   double* tile = reinterpret_cast<double*>(smem);
   uint32_t* signbits = reinterpret_cast<uint32_t*>(tile + kRhtT * COLS + 64);
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(32 * COLS) void rht_hash_kernel(int N, int64_t B, i
                                                              const double* __restrict__ Y,
                                                              const uint32_t* __restrict__ hash, int groups,
                                                              double* __restrict__ partial) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   double* buf = reinterpret_cast<double*>(smem);  // B x COLS
   double* acc = buf + B * COLS;                   // s x COLS
   const int tiles = (N + COLS - 1) / COLS;
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(32 * kRhtRegCols) void rht_hash_reg_kernel(int N, i
                                                                         const uint32_t* __restrict__ hash,
                                                                         int groups, double* __restrict__ partial) {
   constexpr int COLS = kRhtRegCols, RS = 32 * COLS + 2;
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   double* acc = tile + kRhtT * COLS + 64;
   const int tiles = (N + COLS - 1) / COLS;

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
   constexpr int RPP = kSpThreads / COLS;  // rows per pass of the workgroup
   constexpr int VPT = COLS;               // values per thread per chunk (kSpThreads / RPP)
   constexpr int ZW = ZMAX / 8;            // 16-byte table words per row
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   TAcc* acc = reinterpret_cast<TAcc*>(smem_raw);                                  // (s + 1) x COLS
   uint4* hrow = reinterpret_cast<uint4*>(acc + (size_t)(s + 1) * COLS);          // 2 x kSpThreads x ZW
   uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + 2 * kSpThreads * ZW);       // 2 x kSpThreads

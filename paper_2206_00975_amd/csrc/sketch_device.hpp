@@ -12,6 +12,14 @@ namespace nsk {
 // ------------------------------------------------------------------------------ helpers
 template <typename T> __device__ inline double to_f64(T x) { return (double)x; }
 
+// x with its sign bit flipped by bit 31 of `sign` (the other bits of `sign` are ignored).
+__device__ inline double flip_sign(double x, uint32_t sign) {
+  return __hiloint2double(__double2hiint(x) ^ (int)(sign & 0x80000000u), __double2loint(x));
+}
+__device__ inline float flip_sign(float x, uint32_t sign) {
+  return __uint_as_float(__float_as_uint(x) ^ (sign & 0x80000000u));
+}
+
 __device__ inline float bf16_round(float x) {
   uint32_t b = __float_as_uint(x);
   b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;
@@ -273,9 +281,11 @@ template <int COLS> struct SrhtTile {
 // out[i * N + c].  Must be called by all 32 * COLS threads of the workgroup.
 // smem: at least srht_smem_bytes(s, COLS) bytes.  PF: prefetch the next block's values while
 // the current one is transformed (32 more registers a thread).
-// LDS: the block tile, one set of sign words per wave (cols / 2 waves), the sample records.
+// LDS: the block tile, a zero row, one set of sign words per wave (cols / 2 waves), the sample
+// records padded to 32 UMAX (the padding points at the zero row).
+__host__ __device__ constexpr int srht_umax(int s) { return s <= 256 ? 8 : s <= 512 ? 16 : s <= 1024 ? 32 : 64; }
 __host__ __device__ inline size_t srht_smem_bytes(int s, int cols) {
-  return (size_t)(kT * cols + 64) * 8 + (size_t)(kT / 32) * 4 * (cols / 2) + (size_t)s * 8;
+  return (size_t)(kT * cols + 64 + cols) * 8 + (size_t)(kT / 32) * 4 * (cols / 2) + (size_t)32 * srht_umax(s) * 8;
 }
 
 template <typename TIn, typename TAcc, int UMAX, int COLS, bool PF = true>
@@ -284,9 +294,10 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
                                  TAcc* __restrict__ out, unsigned char* smem) {
   constexpr int NT = SrhtTile<COLS>::kThreads;
   constexpr int RS = 32 * COLS + 2;            // doubles between rows rl and rl + 32 of the tile
+  constexpr int kZero = kT * COLS + 64;        // the zero row, after the tile
   double* tile = reinterpret_cast<double*>(smem);
-  uint32_t* signbits = reinterpret_cast<uint32_t*>(tile + kT * COLS + 64) + (threadIdx.x >> 6) * (kT / 32);
-  int2* srec = reinterpret_cast<int2*>(reinterpret_cast<uint32_t*>(tile + kT * COLS + 64) + (NT / 64) * (kT / 32));
+  uint32_t* signbits = reinterpret_cast<uint32_t*>(tile + kZero + COLS) + (threadIdx.x >> 6) * (kT / 32);
+  int2* srec = reinterpret_cast<int2*>(reinterpret_cast<uint32_t*>(tile + kZero + COLS) + (NT / 64) * (kT / 32));
 
   const int t = threadIdx.x;
   const int col = t % COLS;
@@ -300,11 +311,17 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
   column_ref<TIn>(op, live ? c : 0, base, ld);
 
   __syncthreads();
-  for (int i = t; i < s; i += NT) {
-    const int r = rows[i];
-    const int i2 = r & (kT - 1);
-    srec[i] = make_int2(i2 * COLS + (i2 >> 5) * 2, r >> 10);
+  // records past s read the zero row with sign +, so the sampled stage needs no branch
+  for (int i = t; i < 32 * UMAX; i += NT) {
+    if (i < s) {
+      const int r = rows[i];
+      const int i2 = r & (kT - 1);
+      srec[i] = make_int2(i2 * COLS + (i2 >> 5) * 2, r >> 10);
+    } else {
+      srec[i] = make_int2(kZero, 0);
+    }
   }
+  if (t < COLS) tile[kZero + t] = 0.0;
 
   TAcc acc[UMAX];
 #pragma unroll
@@ -343,8 +360,7 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = 4 * q + e;
-        const TAcc v = (TAcc)to_f64(raw[k]);
-        x[k] = ((ws[e] >> rs) & 1u) ? -v : v;
+        x[k] = flip_sign((TAcc)to_f64(raw[k]), (ws[e] >> rs) << 31);
       }
     }
 #pragma unroll
@@ -382,15 +398,21 @@ __device__ inline void srht_tile(const Operand& op, int64_t m, int N, int s, uin
     for (int k = 0; k < 32; ++k) tr[k * COLS] = (double)x[k];
     __syncthreads();
     // sampled outer stage: sample i = rs + 32 u takes row i2 of the block with the sign
-    // (-1)^popcount(i1 & j1)
+    // (-1)^popcount(i1 & j1); groups of 8 samples, each group's reads issued together, groups
+    // wholly past s skipped (a wave-uniform test)
     const uint32_t jlo = (uint32_t)j1;
 #pragma unroll
-    for (int u = 0; u < UMAX; ++u) {
-      const int i = rs + 32 * u;
-      if (i < s) {
-        const int2 rec = srec[i];
-        const TAcc y = (TAcc)tile[rec.x + col];
-        acc[u] += (__popc((uint32_t)rec.y & jlo) & 1) ? -y : y;
+    for (int u0 = 0; u0 < UMAX; u0 += 8) {
+      if (32 * u0 < s) {
+        int2 rec[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rec[u] = srec[rs + 32 * (u0 + u)];
+        double y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y[u] = tile[rec[u].x + col];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          acc[u0 + u] += flip_sign((TAcc)y[u], (uint32_t)__popc((uint32_t)rec[u].y & jlo) << 31);
       }
     }
   };
@@ -438,7 +460,7 @@ template <typename TIn, typename TAcc, int UMAX, int COLS>
 __global__ __launch_bounds__(SrhtTile<COLS>::kThreads) void srht_kernel(Operand op, int64_t m, int N, int s,
                                                                          uint64_t seed, const int* __restrict__ rows,
                                                                          int groups, TAcc* __restrict__ partial) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int tiles = (N + COLS - 1) / COLS;
   const int64_t item = xcd_work_item(blockIdx.x, (int64_t)tiles * groups);
   if (item < 0) return;

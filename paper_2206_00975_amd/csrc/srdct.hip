@@ -107,7 +107,7 @@ __global__ __launch_bounds__(32 * COLS) void srdct_kernel(Operand op, int64_t m,
                                                           const cx<double>* __restrict__ rot, int groups,
                                                           TAcc* __restrict__ partial) {
   constexpr int NT = 32 * COLS;
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   cx<TAcc>* zb = reinterpret_cast<cx<TAcc>*>(smem);          // 512 x COLS: element q at q * COLS + col
   cx<TAcc>* wq = zb + 512 * COLS;                             // e^{-2 pi i r / 512}, r < 128
   cx<TAcc>* cf = wq + 128;                                    // per sample: (alpha, beta), (gamma, delta)

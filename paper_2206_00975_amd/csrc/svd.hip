@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
 
 #include "nsk_internal.hpp"
 #include "svd_device.hpp"
@@ -37,6 +39,10 @@ static SvdWork to_work(const SvdPlan& p) {
   w.N = p.N;
   w.k = p.k;
   w.max_sweeps = p.max_sweeps;
+  // NSK_COOP_LOCAL=0 keeps the agent-scope hand-over even where all workers share an XCD
+  const char* env = std::getenv("NSK_COOP_LOCAL");
+  w.coop_local = env != nullptr && env[0] == '0' ? 0 : 1;
+  w.coop_stride = 1;
   return w;
 }
 
@@ -48,7 +54,7 @@ constexpr int kFinishThreads = 512;
 
 template <int RPL>
 __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_kernel(SvdWork w) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   svd_stage_qr_rpl<RPL>(w, smem);
 }
 
@@ -67,7 +73,7 @@ static hipError_t lds_attr(const void* fn, size_t lds) {
 // the sigma array (overwritten by the finish stage).
 template <int RPL>
 __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_coop_kernel(SvdWork w) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   constexpr int C = QrCpw<RPL>::value;
   const JacobiShape js = jacobi_shape(w.N);
   const int ldr = 64 * js.NR;
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_coop_kernel(SvdWork w)
 // Lookahead variant (two panels of reflectors in LDS, at least two workgroups).
 template <int RPL>
 __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_coop_la_kernel(SvdWork w) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   constexpr int C = QrCpw<RPL>::value;
   // the rotation log is free until the Jacobi stage: the panel flags live at its start
   unsigned* flags = reinterpret_cast<unsigned*>(w.log);
@@ -92,12 +98,29 @@ __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_coop_la_kernel(SvdWork
   const int ldr = 64 * js.NR;
   const size_t relems = (size_t)ldr * js.nb * js.B;
   switch (qr_panel_width(w.s, blockDim.x >> 6)) {
-    case 16: qr_coop_la<RPL, 16, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
-    case 8: qr_coop_la<RPL, 8, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
-    case 4: qr_coop_la<RPL, 4, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
-    case 2: qr_coop_la<RPL, 2, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
-    default: qr_coop_la<RPL, 1, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, smem); break;
+    case 16: qr_coop_la<RPL, 16, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, w.coop_stride, w.coop_local != 0, smem); break;
+    case 8: qr_coop_la<RPL, 8, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, w.coop_stride, w.coop_local != 0, smem); break;
+    case 4: qr_coop_la<RPL, 4, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, w.coop_stride, w.coop_local != 0, smem); break;
+    case 2: qr_coop_la<RPL, 2, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, w.coop_stride, w.coop_local != 0, smem); break;
+    default: qr_coop_la<RPL, 1, C>(w.sa, w.s, w.N, w.R, ldr, relems, w.sigma, flags, w.coop_stride, w.coop_local != 0, smem); break;
   }
+}
+
+// Workgroups launched per worker of the multi-workgroup QR and Jacobi: kXcds (the workers on one
+// XCD) when the device has a CU for each of the groups * kXcds workgroups, else 1.
+// The CU count is queried once per device (the query is slow next to a solve).
+static hipError_t set_coop_stride(SvdWork& w, int groups) {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> cus_of[kMaxDevices];
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  int cus = dev < kMaxDevices ? cus_of[dev].load(std::memory_order_relaxed) : 0;
+  if (cus == 0) {
+    if (hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) return e;
+    if (dev < kMaxDevices) cus_of[dev].store(cus, std::memory_order_relaxed);
+  }
+  w.coop_stride = cus >= groups * kXcds ? kXcds : 1;
+  return hipSuccess;
 }
 
 // workgroups of the multi-workgroup QR: one per panel, at most 16
@@ -117,8 +140,10 @@ static hipError_t launch_qr_coop(SvdWork& w, hipStream_t st) {
   // up to 16 rows per lane (s <= 1024): the variant for more rows per lane spills registers
   if (RPL <= 16 && groups >= 2 && lds_la <= 160 * 1024) {
     if (hipError_t e = lds_attr((const void*)svd_qr_coop_la_kernel<RPL>, lds_la)) return e;
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_qr_coop_la_kernel<RPL>), dim3(groups),
-                                      dim3(threads), args, lds_la, st);
+    // coop_stride workgroups per worker: the workers (b = kXcds w) share one XCD's L2
+    if (hipError_t e = set_coop_stride(w, groups)) return e;
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_qr_coop_la_kernel<RPL>),
+                                      dim3(groups * w.coop_stride), dim3(threads), args, lds_la, st);
   }
   const size_t lds = qr_panel_lds_bytes(w.s, nb);
   if (hipError_t e = lds_attr((const void*)svd_qr_coop_kernel<RPL>, lds)) return e;
@@ -131,20 +156,23 @@ template <int NR>
 __global__ __launch_bounds__(NR * 64) void svd_jacobi_coop_kernel(SvdWork w) {
   // colnorm is free until the finish stage recomputes it: scratch for the Gram check
   jacobi_coop_sweeps<NR, JacobiB<NR>::value>(w.R, w.N, w.max_sweeps, w.log,
-                                             jacobi_counters(w.log, w.N, w.max_sweeps), w.jres, w.colnorm);
+                                             jacobi_counters(w.log, w.N, w.max_sweeps), w.jres, w.colnorm,
+                                             w.coop_stride, w.coop_local != 0);
 }
 
 template <int NR>
 static hipError_t launch_jacobi_coop(SvdWork& w, hipStream_t st) {
   void* args[] = {&w};
   const int groups = jacobi_shape(w.N).nb / 2;
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_jacobi_coop_kernel<NR>), dim3(groups),
-                                    dim3(NR * 64), args, 0, st);
+  // coop_stride workgroups per worker: the workers (b = kXcds w) share one XCD's L2
+  if (hipError_t e = set_coop_stride(w, groups)) return e;
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(svd_jacobi_coop_kernel<NR>),
+                                    dim3(groups * w.coop_stride), dim3(NR * 64), args, 0, st);
 }
 
 template <int NR>
 __global__ __launch_bounds__(kFinishThreads) void svd_finish_kernel(SvdWork w) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   svd_stage_finish_nr<NR, JacobiB<NR>::value>(w, jacobi_shape(w.N), smem);
 }
 

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(1024) void svd_big_finish_kernel(const double* __re
                                                               double* __restrict__ sigma, int* __restrict__ order,
                                                               double* __restrict__ Vk, double* __restrict__ sigma_k,
                                                               nsk_info* info) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   double* nrm = reinterpret_cast<double*>(smem);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   for (int c = wave; c < N; c += nw) {

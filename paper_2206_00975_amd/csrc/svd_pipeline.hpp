@@ -31,6 +31,8 @@ struct SvdWork {
   double* sigma_k;     // k (nullable)
   nsk_info* info;      // nullable
   int s, N, k, max_sweeps;
+  int coop_local;      // multi-workgroup QR and Jacobi may take the one-XCD hand-over
+  int coop_stride;     // workgroups launched per worker of the multi-workgroup QR and Jacobi
 };
 
 // rotation log, followed by the per-sweep counters of the multi-workgroup Jacobi; large enough

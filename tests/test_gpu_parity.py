@@ -377,6 +377,27 @@ def test_deterministic_bitwise(lib):
     assert torch.equal(e, f)
 
 
+@pytest.mark.parametrize("m,N,k", [(12_000, 201, 2), (9000, 150, 3), (20_000, 320, 2)])
+def test_coop_hand_over_forms_agree_bitwise(lib, m, N, k, monkeypatch):
+    """The multi-workgroup QR and Jacobi hand columns between workgroups either within one
+    XCD's L2 (the default where every worker shares an XCD) or with agent-scope release and
+    acquire (NSK_COOP_LOCAL=0); the arithmetic is the same, so the results agree bit for bit,
+    and both match the oracle."""
+    a = W.planted_matrix(m, N, k=k, level=1e-4, seed=(9, N))[0].astype(np.float64)
+    at = t(a)
+    s = 4 * N
+    monkeypatch.delenv("NSK_COOP_LOCAL", raising=False)
+    v1, s1, i1 = lib.trailing_rsv(at, k, kind="sparse", s=s, seed=13)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("NSK_COOP_LOCAL", "0")
+    v0, s0, i0 = lib.trailing_rsv(at, k, kind="sparse", s=s, seed=13)
+    torch.cuda.synchronize()
+    assert torch.equal(v1, v0) and torch.equal(s1, s0)
+    assert lib.read_info(i1).sweeps == lib.read_info(i0).sweeps and lib.read_info(i1).converged
+    vk_ref, sk_ref, sa, sig, V, _ = method.trailing_rsv(a, k, "sparse", s, 13, return_all=True)
+    assert_vectors(vk_ref, v1.cpu().numpy(), vec_tol(sig, k))
+
+
 def test_residual_entry_point(lib):
     a = np.random.default_rng(3).standard_normal((50_001, 33)).astype(np.float32)
     v = np.linalg.qr(np.random.default_rng(4).standard_normal((33, 3)))[0]
