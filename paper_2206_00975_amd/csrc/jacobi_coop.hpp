@@ -36,7 +36,8 @@ __host__ __device__ inline size_t jacobi_coop_counter_bytes(int max_sweeps) {
 // its version is sw * nb + ph + 1.  The workgroup that wrote a block publishes the new version
 // once every wave's stores have reached the L2 (with workers on several XCDs, after an
 // agent-scope release); the workgroup that takes the block in the next round polls the two
-// versions it needs (one thread, bounded) and takes an agent-scope acquire.  Past
+// versions it needs (one thread, bounded) and takes an agent-scope acquire, or, with all
+// workers on one XCD, reads the two blocks with agent-scope loads (load_handed).  Past
 // kCoopSpinLimit polls the abort word is raised, every later wait returns at once, and the
 // result is marked invalid, so a protocol fault cannot hang the GPU.
 constexpr unsigned kCoopSpinLimit = 1u << 20;
@@ -52,7 +53,7 @@ __device__ inline void coop_publish(unsigned long long* ver, int I, int J, unsig
 }
 
 __device__ inline void coop_wait(unsigned long long* ver, int I, int J, unsigned long long v,
-                                 unsigned long long* abort_word) {
+                                 unsigned long long* abort_word, bool local) {
   if (threadIdx.x == 0) {
     unsigned spins = 0;
     while (__hip_atomic_load(&ver[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v ||
@@ -64,7 +65,7 @@ __device__ inline void coop_wait(unsigned long long* ver, int I, int J, unsigned
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
@@ -189,7 +190,7 @@ __device__ inline void coop_intra_block(double* __restrict__ R, int ld, int blk,
 template <int NW, int B>
 __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, int J, double2* lg, int stride,
                                        double tol, CoopCount& cc, double (*part)[NW][16], int& buf, int lane,
-                                       int wave, double2* bc) {
+                                       int wave, double2* bc, bool local) {
   constexpr int SH = 6 - ceil_log2(B);
   const int pi = lane >> SH;
   const bool valid = pi < B;
@@ -197,10 +198,18 @@ __device__ inline void coop_inter_pair(double* __restrict__ R, int ld, int I, in
   double* pt = uniform_ptr(R + (size_t)I * B * ld) + 64 * wave + lane;
   double* pu = uniform_ptr(R + (size_t)J * B * ld) + 64 * wave + lane;
   double T[B], U[B];
+  if (local) {  // blocks handed over within the XCD: agent-scope loads, past the CU's L1
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    T[b] = pt[(size_t)b * ld];
-    U[b] = pu[(size_t)b * ld];
+    for (int b = 0; b < B; ++b) {
+      T[b] = load_handed(&pt[(size_t)b * ld]);
+      U[b] = load_handed(&pu[(size_t)b * ld]);
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      T[b] = pt[(size_t)b * ld];
+      U[b] = pu[(size_t)b * ld];
+    }
   }
   double alpha, beta;
   {
@@ -431,9 +440,9 @@ __device__ inline void jacobi_coop_sweeps(double* __restrict__ R, int N, int max
           I = J;
           J = t;
         }
-        coop_wait(ver, I, J, base_ver + 1 + r, abort_word);
+        coop_wait(ver, I, J, base_ver + 1 + r, abort_word, local);
         coop_inter_pair<NW, B>(R, ld, I, J, round_log + (size_t)i * 16, nbp * 16, tol, cc, part, buf, lane, wave,
-                               bcs[wave]);
+                               bcs[wave], local);
         coop_publish(ver, I, J, base_ver + 2 + r, local);
       }
       if (r == js.nb - 2 && wave == 0 && worker) {

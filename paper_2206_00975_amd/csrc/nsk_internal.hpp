@@ -102,18 +102,26 @@ __host__ __device__ inline int64_t xcd_work_item(int64_t b, int64_t n) {
 // stride = kXcds and the dealing above all workers run on one XCD and share its L2 (stride 1
 // where the device has too few CUs for that launch).  Each worker records the
 // hardware XCC id it runs on (hwreg XCC_ID) before the launch's first grid barrier; after it,
-// xcd_all_local tells every worker whether all W ids agree.  When they do, the writer of a
-// hand-over needs no L2 write-back (agent-scope release): it waits for its stores, which the
-// vector L1 writes through to the shared L2, and raises its flag.  The reader always takes an
-// agent-scope acquire (buffer_inv sc1): it drops the CU's stale L1 lines, which a
-// workgroup-scope invalidate (buffer_inv sc0) leaves in place, measured on gfx950, and keeps the
-// dirty lines of the shared L2.  With workers on several XCDs the writer keeps the release.
+// xcd_all_local tells every worker whether all W ids agree.  When they do, a hand-over needs
+// neither the writer's L2 write-back (agent-scope release) nor the reader's L2 invalidation
+// (agent-scope acquire): the writer waits for its stores, which the vector L1 writes through to
+// the shared L2, and raises its flag; the reader fetches the handed-over data with agent-scope
+// relaxed atomic loads (load_handed), which the CU's L1 does not serve, so they read the L2.
+// Measured on gfx950: after another workgroup's stores and flag, plain loads and loads after a
+// workgroup-scope invalidate (buffer_inv sc0) or with the sc0 bit return the CU's stale L1
+// lines; agent-scope loads and loads after an agent-scope acquire return the new values.
+// With workers on several XCDs the kernels keep agent-scope release and acquire.
 __device__ inline unsigned xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (15 << 11)); }
 __device__ inline bool coop_worker(int stride) { return blockIdx.x % stride == 0; }
 __device__ inline int coop_worker_index(int stride) { return (int)(blockIdx.x / stride); }
 __device__ inline int coop_workers(int stride) { return (int)(gridDim.x / stride); }
 __device__ inline void xcd_record(unsigned* ids, int stride) {
   if (coop_worker(stride) && threadIdx.x == 0) ids[coop_worker_index(stride)] = xcc_id();
+}
+// Load of data another workgroup handed over: agent-scope (past the CU's L1) in the one-XCD
+// hand-over, plain after an agent-scope acquire.
+template <typename T> __device__ inline T load_handed(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // After a grid barrier that follows every worker's xcd_record (at most 64 workers); the same in
 // every wave.  Lane w of each wave compares worker w's id with worker 0's (vector loads, no

@@ -218,9 +218,10 @@ __device__ inline void qr_publish(unsigned* flag, bool local) {
   }
 }
 
-// One thread polls the flag, then takes an agent-scope acquire (stale cached lines dropped for
-// the whole workgroup, whose waves share the CU's caches) before the workgroup reads.
-__device__ inline void qr_wait(unsigned* flag, unsigned* abort_word) {
+// One thread polls the flag; with workers on several XCDs it then takes an agent-scope acquire
+// (stale cached lines dropped for the whole workgroup, whose waves share the CU's caches) before
+// the workgroup reads; on one XCD the reads themselves are agent-scope (load_handed).
+__device__ inline void qr_wait(unsigned* flag, unsigned* abort_word, bool local) {
   if (threadIdx.x == 0) {
     unsigned spins = 0;
     while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
@@ -231,7 +232,7 @@ __device__ inline void qr_wait(unsigned* flag, unsigned* abort_word) {
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
@@ -326,8 +327,8 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
   };
 
   // panel p's reflectors, as its owner stored them in A and tau_g, into this workgroup's LDS;
-  // every load is issued before the first store
-  auto copy = [&](int p) {
+  // every load is issued before the first store (agent-scope loads in the one-XCD hand-over)
+  auto copy = [&](int p, bool local) {
     const int j0 = p * NB;
     const int nbc = N - j0 < NB ? N - j0 : NB;
     const int rows = s - j0;
@@ -335,15 +336,20 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
     // rows per thread: s <= 64 RPL rows over the 512 (RPL < 64) or 256 (RPL = 64) threads
     constexpr int RR = RPL >= 64 ? RPL / 4 : RPL / 8;
     double val[NB][RR];
+    auto fetch = [&](auto handed) {
 #pragma unroll
-    for (int jj = 0; jj < NB; ++jj)
+      for (int jj = 0; jj < NB; ++jj)
 #pragma unroll
-      for (int k = 0; k < RR; ++k) {
-        const int rr = threadIdx.x + k * (int)blockDim.x;
-        const bool ok = jj < nbc && rr < rows;
-        const double x = A[(size_t)(j0 + (ok ? jj : 0)) * s + j0 + (ok ? rr : 0)];
-        val[jj][k] = rr < jj ? 0.0 : rr == jj ? 1.0 : x;
-      }
+        for (int k = 0; k < RR; ++k) {
+          const int rr = threadIdx.x + k * (int)blockDim.x;
+          const bool ok = jj < nbc && rr < rows;
+          const double* xp = &A[(size_t)(j0 + (ok ? jj : 0)) * s + j0 + (ok ? rr : 0)];
+          const double x = decltype(handed)::value ? load_handed(xp) : *xp;
+          val[jj][k] = rr < jj ? 0.0 : rr == jj ? 1.0 : x;
+        }
+    };
+    if (local) fetch(std::true_type{});
+    else fetch(std::false_type{});
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj)
 #pragma unroll
@@ -351,7 +357,7 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
         const int rr = threadIdx.x + k * (int)blockDim.x;
         if (jj < nbc && rr < rows) vb[(size_t)jj * s + rr] = val[jj][k];
       }
-    if (threadIdx.x < nbc) taus(p)[threadIdx.x] = tau_g[j0 + threadIdx.x];
+    if (threadIdx.x < nbc) taus(p)[threadIdx.x] = local ? load_handed(&tau_g[j0 + threadIdx.x]) : tau_g[j0 + threadIdx.x];
   };
 
   // panel pv's reflectors (in LDS) applied, in order, to this workgroup's columns in panels
@@ -444,8 +450,8 @@ __device__ inline void qr_coop_la(double* __restrict__ A, int s, int N, double* 
     const int owner = p % G;
     const int nx = p + 1;
     if (me != owner) {
-      qr_wait(flags + p, abort_word);  // panel p's reflectors are in A and tau_g
-      copy(p);
+      qr_wait(flags + p, abort_word, local);  // panel p's reflectors are in A and tau_g
+      copy(p, local);
     }
     __syncthreads();
     using One = std::integral_constant<int, 1>;
