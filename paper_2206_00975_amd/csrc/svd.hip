@@ -180,13 +180,22 @@ __global__ __launch_bounds__(kFinishThreads) void svd_finish_kernel(SvdWork w) {
 
 bool svd_fast_path(int s, int N) { return N <= kFastMaxN && s <= kFastMaxS; }
 
+// Past the fast path, a sketch of at most kFastMaxS rows (and more rows than columns) is first
+// reduced to R by the multi-workgroup QR, and the large-N Jacobi runs on R's 64 NR rows
+// (zero-padded, ld = 64 NR) instead of SA's s rows: R^T R = (SA)^T SA, so the rotations are the
+// same and every column pair moves fewer rows.
+static bool svd_big_qr_first(int s, int N) { return !svd_fast_path(s, N) && s <= kFastMaxS && s > N; }
+
 size_t svd_work_R_bytes(int s, int N) {
-  return svd_fast_path(s, N) ? svd_fast_R_bytes(N) : 0;
+  return svd_fast_path(s, N) || svd_big_qr_first(s, N) ? svd_fast_R_bytes(N) : 0;
 }
 
-// the fast path's rotation log; the large path's per-sweep counters
+// the fast path's rotation log; the large path's per-sweep counters (and, before them, the QR's
+// panel flags and XCC ids: at most N + 1 + kCoopMaxBlocks / 2 words)
 size_t svd_work_log_bytes(int s, int N, int max_sweeps) {
-  return svd_fast_path(s, N) ? svd_fast_log_bytes(N, max_sweeps) : svd_big_counter_bytes(max_sweeps);
+  if (svd_fast_path(s, N)) return svd_fast_log_bytes(N, max_sweeps);
+  const size_t flags = (size_t)(N + 1 + kCoopMaxBlocks / 2) * sizeof(unsigned);
+  return std::max(svd_big_counter_bytes(max_sweeps), flags);
 }
 
 hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
@@ -258,24 +267,37 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
     prof_mark(5, st);
     return hipGetLastError();
   }
-  // large sizes: cooperative Jacobi on SA, then the one-workgroup finish
+  // large sizes: the QR when it applies, cooperative Jacobi on R (or SA), then the one-workgroup
+  // finish
+  double* sa = p.sa;
+  int s = p.s, N = p.N, sweeps = p.max_sweeps;
+  if (svd_big_qr_first(p.s, p.N)) {
+    SvdWork w = to_work(p);
+    hipError_t e = hipSuccess;
+    switch (qr_rpl(p.s)) {
+      case 16: e = launch_qr_coop<16>(w, st); break;
+      case 32: e = launch_qr_coop<32>(w, st); break;
+      default: e = launch_qr_coop<64>(w, st); break;
+    }
+    if (e != hipSuccess) return e;
+    sa = p.R;
+    s = 64 * jacobi_shape(p.N).NR;
+  }
   int dev = 0, cus = 0;
   if (hipError_t e = hipGetDevice(&dev)) return e;
   if (hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) return e;
   const int nb = (p.N + kBigW - 1) / kBigW;
   const int groups = std::max(1, std::min(cus, (nb + (nb & 1)) / 2));
-  double* sa = p.sa;
-  int s = p.s, N = p.N, sweeps = p.max_sweeps;
   double* V = p.V;
   unsigned long long* counters = reinterpret_cast<unsigned long long*>(p.log);
   void* args[] = {&sa, &s, &N, &V, &sweeps, &counters};
   prof_mark(3, st);
-  const void* fn = p.s <= 1024   ? reinterpret_cast<const void*>(svd_big_jacobi_kernel<16>)
-                   : p.s <= 2048 ? reinterpret_cast<const void*>(svd_big_jacobi_kernel<32>)
-                                 : reinterpret_cast<const void*>(svd_big_jacobi_kernel<0>);
+  const void* fn = s <= 1024   ? reinterpret_cast<const void*>(svd_big_jacobi_kernel<16>)
+                   : s <= 2048 ? reinterpret_cast<const void*>(svd_big_jacobi_kernel<32>)
+                               : reinterpret_cast<const void*>(svd_big_jacobi_kernel<0>);
   if (hipError_t e = hipLaunchCooperativeKernel(fn, dim3(groups), dim3(kBigThreads), args, 0, st)) return e;
   prof_mark(4, st);
-  svd_big_finish_kernel<<<1, 1024, (size_t)p.N * 8, st>>>(p.sa, p.s, p.N, p.k, p.V, p.max_sweeps, counters, p.sigma,
+  svd_big_finish_kernel<<<1, 1024, (size_t)p.N * 8, st>>>(sa, s, p.N, p.k, p.V, p.max_sweeps, counters, p.sigma,
                                                           p.order, p.Vk, p.sigma_k, p.info);
   prof_mark(5, st);
   return hipGetLastError();
