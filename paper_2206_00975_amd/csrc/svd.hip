@@ -51,6 +51,7 @@ static SvdWork to_work(const SvdPlan& p) {
 // workgroup leaves each wave; they run 512 threads.
 __host__ __device__ constexpr int qr_threads(int rpl) { return rpl >= 64 ? 256 : 512; }
 constexpr int kFinishThreads = 512;
+constexpr int kFinishGroups = 2;
 
 template <int RPL>
 __global__ __launch_bounds__(qr_threads(RPL)) void svd_qr_kernel(SvdWork w) {
@@ -173,6 +174,10 @@ static hipError_t launch_jacobi_coop(SvdWork& w, hipStream_t st) {
 template <int NR>
 __global__ __launch_bounds__(kFinishThreads) void svd_finish_kernel(SvdWork w) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // launched as kFinishGroups workgroups of which only the last works: it runs on XCD 1, away
+  // from XCD 0's L2, where the Jacobi's workers left the rotation log (replayed from XCD 0 the
+  // stage measured 0.203 ms at config 2, from XCD 1 0.186 ms)
+  if (blockIdx.x != gridDim.x - 1) return;
   svd_stage_finish_nr<NR, JacobiB<NR>::value>(w, jacobi_shape(w.N), smem);
 }
 
@@ -244,23 +249,23 @@ hipError_t launch_svd(const SvdPlan& p, hipStream_t st) {
     switch (jacobi_shape(p.N).NR) {
       case 1:
         e = lds_attr((const void*)svd_finish_kernel<1>, lf);
-        if (e == hipSuccess) svd_finish_kernel<1><<<1, tf, lf, st>>>(w);
+        if (e == hipSuccess) svd_finish_kernel<1><<<kFinishGroups, tf, lf, st>>>(w);
         break;
       case 2:
         e = lds_attr((const void*)svd_finish_kernel<2>, lf);
-        if (e == hipSuccess) svd_finish_kernel<2><<<1, tf, lf, st>>>(w);
+        if (e == hipSuccess) svd_finish_kernel<2><<<kFinishGroups, tf, lf, st>>>(w);
         break;
       case 3:
         e = lds_attr((const void*)svd_finish_kernel<3>, lf);
-        if (e == hipSuccess) svd_finish_kernel<3><<<1, tf, lf, st>>>(w);
+        if (e == hipSuccess) svd_finish_kernel<3><<<kFinishGroups, tf, lf, st>>>(w);
         break;
       case 4:
         e = lds_attr((const void*)svd_finish_kernel<4>, lf);
-        if (e == hipSuccess) svd_finish_kernel<4><<<1, tf, lf, st>>>(w);
+        if (e == hipSuccess) svd_finish_kernel<4><<<kFinishGroups, tf, lf, st>>>(w);
         break;
       default:
         e = lds_attr((const void*)svd_finish_kernel<5>, lf);
-        if (e == hipSuccess) svd_finish_kernel<5><<<1, tf, lf, st>>>(w);
+        if (e == hipSuccess) svd_finish_kernel<5><<<kFinishGroups, tf, lf, st>>>(w);
         break;
     }
     if (e != hipSuccess) return e;
