@@ -20,6 +20,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+
+#include <algorithm>
 #include <type_traits>
 
 #include "nsk_internal.hpp"
@@ -256,8 +259,16 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
 //    k range) need the same 8 Philox blocks (block (j, q) holds rows 4q .. 4q + 3 of column j);
 //    each lane draws 2 of them, and a 4 x 4 exchange of 2-entry items over the quad (DPP quad
 //    permutations) leaves every lane the 8 entries of its own row;
-//  * entries whose FP32 rounding is not certified are redrawn in FP64, one per lane at a time;
 //  * MW x (column tiles) MFMAs.
+// Entries whose FP32 rounding is not certified (about one in 10^4) enter the MFMAs with their
+// FP32 rounding and are recorded (K step, lane, entry mask) in LDS; after the K loop the
+// workgroup recomputes each in FP64, and where the FP64 rounding differs it adds the difference
+// times the entry's row of A to its partial sketch, the corrections taken in (row, column of
+// G_hat) order so that the result does not depend on the recording order.  Redrawing them in
+// place inside the K loop held every wave at the K step's barrier while one lane ran the FP64
+// Box-Muller, and the loop's mere presence cost the main path about 19 us at 99,900 x 100,
+// s = 200.  A workgroup whose records or corrections overflow (kGFix, kGCor: several times
+// what the draw rate gives) redoes its sums with the entries redrawn in place.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
@@ -268,6 +279,18 @@ constexpr int kGWaves = 8;
 constexpr int kGThreads = 64 * kGWaves;
 constexpr int kGNT = 8;                 // column tiles of a column group
 constexpr int kGCols = 16 * kGNT;       // 128 columns
+
+constexpr int kGFix = 256;              // recorded uncertified (lane, K step) entries per workgroup
+constexpr int kGCor = 1024;             // corrections (entries whose two roundings differ)
+
+// FP32 value of an element of A as the MFMA reads it (E4M3: without the column's exponent,
+// which the reduction applies).
+__device__ inline float gauss_elem(uint16_t x) { return __uint_as_float((unsigned)x << 16); }
+__device__ inline float gauss_elem(uint8_t x) {
+  const unsigned e = (x >> 3) & 15u, mt = x & 7u;
+  const float a = e == 0 ? (float)mt * 0x1p-9f : ldexpf(1.0f + (float)mt * 0.125f, (int)e - 7);
+  return (x & 0x80u) ? -a : a;
+}
 
 // LDS bytes between consecutive columns of the staged A tile: the 32 k values plus 16 bytes
 // (keeps 16-byte alignment and spreads the columns over the banks).
@@ -282,14 +305,21 @@ __device__ inline unsigned sel4(int k, unsigned a, unsigned b, unsigned c, unsig
   return k == 0 ? a : k == 1 ? b : k == 2 ? c : d;
 }
 
+// fix_cap (<= kGFix): records kept per workgroup before the in-place pass takes over.
 template <bool FP8, int MW>
 __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m, int N, int s, uint64_t seed,
-                                                          int ksteps_per_group, float* __restrict__ partial) {
+                                                          int ksteps_per_group, int fix_cap,
+                                                          float* __restrict__ partial) {
   using E = typename std::conditional<FP8, uint8_t, uint16_t>::type;
   constexpr int FMT = FP8 ? NSK_F8E4M3 : NSK_BF16;
   constexpr int IB = FP8 ? 8 : 16;        // bits of one entry
   constexpr int CS = gauss_col_stride<FP8>();
   __shared__ __align__(16) unsigned char btile[2][kGCols * CS];
+  __shared__ unsigned fix_n, cor_n;
+  __shared__ uint2 fix[kGFix];           // ((K step - kb) << 10 | thread, entry mask)
+  __shared__ uint4 cor[kGCor];           // (row i of G_hat, column j, difference bits, -)
+  __shared__ unsigned short cor_at[kGCor];  // corrections in (i, j) order
+  __shared__ unsigned short cor_wave[kGWaves][kGCor];  // each wave's own, in that order
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int kq = lane >> 4, li = lane & 15, quad = li >> 2, hq = li & 3;
@@ -338,6 +368,15 @@ __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m,
     else *reinterpret_cast<u32x4*>(p) = u32x4{r[0], r[1], r[2], r[3]};
   };
 
+  if (t == 0) {
+    fix_n = 0;
+    cor_n = 0;
+  }
+  // the K loop; RECORD: uncertified entries recorded for the correction pass (the common path,
+  // with no FP64 work inside the loop), else redrawn in FP64 in place (taken only when the
+  // records overflow kGFix, after the first pass's sums are discarded)
+  auto kloop = [&](auto record_tag) {
+  constexpr bool RECORD = decltype(record_tag)::value;
   unsigned ra[FP8 ? 2 : 4];
   if (kb < ke) {
     load_a(kb, ra);
@@ -373,8 +412,17 @@ __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m,
         doubt |= d << (8 * u + 4 * v);
       }
     }
-    // entries whose FP32 rounding is not certified: FP64 Box-Muller, one entry per lane at a time
-    while (__any(doubt != 0)) {
+    // entries whose FP32 rounding is not certified: recorded for the correction after the K
+    // loop (a full list is noticed after the loop), or FP64 Box-Muller in place, one entry per
+    // lane at a time
+    if constexpr (RECORD) {
+      if (doubt != 0) {
+        const unsigned slot = atomicAdd(&fix_n, 1u);
+        if (slot < (unsigned)fix_cap) fix[slot] = make_uint2(((unsigned)(ks - kb) << 10) | (unsigned)t, doubt);
+        doubt = 0;
+      }
+    }
+    while (!RECORD && __any(doubt != 0)) {
       if (doubt != 0) {
         const int bit = __builtin_ctz(doubt);
         doubt &= doubt - 1;
@@ -431,6 +479,112 @@ __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m,
     }
     if (ks + 1 < ke) store_a(buf ^ 1, ra);
     __syncthreads();
+  }
+  };
+  kloop(std::true_type{});
+  __syncthreads();
+  // each record's entries: the FP32 rounding the MFMAs used and the FP64 one the draw rule
+  // gives; the differences go to the correction list
+  bool redo = fix_n > (unsigned)fix_cap;  // uniform: some records were lost
+  if (!redo && fix_n > 0) {
+    for (unsigned e = t; e < fix_n; e += blockDim.x) {
+      const uint2 rec = fix[e];
+      const int64_t ks = kb + (rec.x >> 10);
+      const int tt = (int)(rec.x & 1023u), ln = tt & 63;
+      const int fkq = ln >> 4, fli = ln & 15, fquad = fli >> 2, fhq = fli & 3;
+      const int fmt0 = blockIdx.z * kGWaves * MW + (tt >> 6);
+      const int64_t jq = ks * kGK + 8 * fkq + 2 * fhq;
+      for (unsigned mask = rec.y; mask != 0; mask &= mask - 1) {
+        const int bit = __builtin_ctz(mask);
+        const int u = bit >> 3, v = (bit >> 2) & 1, h = bit & 3;
+        const int q = (fmt0 + kGWaves * u) * 4 + fquad;
+        const int64_t j = jq + v;
+        const Words w = philox(seed, (uint64_t)j, (uint32_t)q, kGauss);
+        float g32[4];
+        gauss_hat4_fast<FMT>(w, g32);
+        const float g64 = gauss_hat64<FMT>(w, h);
+        if (g64 != g32[h]) {
+          const unsigned slot = atomicAdd(&cor_n, 1u);
+          if (slot < (unsigned)kGCor)
+            cor[slot] = make_uint4((unsigned)(4 * q + h), (unsigned)j, __float_as_uint(g64 - g32[h]), 0u);
+        }
+      }
+    }
+    __syncthreads();
+    redo = cor_n > (unsigned)kGCor;
+  }
+  if (redo) {  // redo the sums with the uncertified entries redrawn in place
+#pragma unroll
+    for (int u = 0; u < MW; ++u)
+#pragma unroll
+      for (int c = 0; c < kGNT; ++c) acc[u][c] = floatx4{0, 0, 0, 0};
+    kloop(std::false_type{});
+  } else if (cor_n > 0) {
+    // corrections in (row, column of G_hat) order, so that an accumulator receives its
+    // corrections in an order that does not depend on the recording order
+    const unsigned ncor = cor_n;
+    for (unsigned e = t; e < ncor; e += blockDim.x) {
+      const uint4 me = cor[e];
+      unsigned rank = 0;
+      for (unsigned f = 0; f < ncor; ++f) {
+        const uint4 o = cor[f];
+        rank += o.x < me.x || (o.x == me.x && o.y < me.y);
+      }
+      cor_at[rank] = (unsigned short)e;
+    }
+    __syncthreads();
+    // each wave adds (g64 - g32) A[j, :] to the accumulators of its own rows: lanes 16 kq ..
+    // 16 kq + 15 hold rows 4 kq .. 4 kq + 3 of a tile, one column of each column tile
+    const E* cbase[kGNT];
+    int64_t cld[kGNT];
+    bool cval[kGNT];
+#pragma unroll
+    for (int c = 0; c < kGNT; ++c) {
+      const int col = (nt0 + c) * 16 + li;
+      cval[c] = nt0 + c < ntiles && col < N;
+      column_ref<E>(op, cval[c] ? col : 0, cbase[c], cld[c]);
+    }
+    // this wave's corrections, compacted in order (a ballot per 64 of the sorted list)
+    unsigned short* mine = cor_wave[wave];
+    unsigned nmine = 0;
+    for (unsigned base = 0; base < ncor; base += 64) {
+      const unsigned r = base + lane;
+      bool owned = false;
+      if (r < ncor) {
+        const int du = ((int)cor[cor_at[r]].x >> 4) - mt0;
+        owned = du >= 0 && du % kGWaves == 0 && du / kGWaves < MW;
+      }
+      const unsigned long long bal = __ballot(owned);
+      if (owned) mine[nmine + __popcll(bal & ((1ull << lane) - 1))] = cor_at[r];
+      nmine += (unsigned)__popcll(bal);
+    }
+    wave_lds_sync();
+    // four at a time, every load of the four issued before the first addition
+    for (unsigned r0 = 0; r0 < nmine; r0 += 4) {
+      uint4 c4[4];
+      float av[4][kGNT];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        c4[b] = r0 + b < nmine ? cor[mine[r0 + b]] : make_uint4(0xFFFFFFFFu, 0u, 0u, 0u);
+        const bool here = c4[b].x != 0xFFFFFFFFu && (((int)c4[b].x & 15) >> 2) == kq;
+#pragma unroll
+        for (int c = 0; c < kGNT; ++c) av[b][c] = here && cval[c] ? gauss_elem(cbase[c][(int64_t)c4[b].y * cld[c]]) : 0.0f;
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (c4[b].x == 0xFFFFFFFFu) continue;
+        const int i = (int)c4[b].x;
+        const int u = ((i >> 4) - mt0) / kGWaves, h = i & 3;
+        const float dg = __uint_as_float(c4[b].z);
+#pragma unroll
+        for (int c = 0; c < kGNT; ++c)
+#pragma unroll
+          for (int uu = 0; uu < MW; ++uu)
+#pragma unroll
+            for (int hh = 0; hh < 4; ++hh)
+              if (uu == u && hh == h) acc[uu][c][hh] += dg * av[b][c];
+      }
+    }
   }
   float* out = partial + (size_t)blockIdx.x * s * N;
 #pragma unroll
@@ -576,13 +730,17 @@ static hipError_t gauss_dispatch(const Operand& op, const SketchPlan& p, hipStre
   float* part = static_cast<float*>(p.partial);
   const dim3 grid(p.groups, g.ngroups, g.mgroups);
   const bool f8 = op.dtype == NSK_F8E4M3;
-#define NSK_GAUSS_CASE(MWV)                                                                      \
-  if (g.mw == MWV) {                                                                             \
-    if (f8)                                                                                      \
-      gauss_kernel<true, MWV><<<grid, kGThreads, 0, st>>>(op, p.m, p.N, p.s, p.seed, per, part);  \
-    else                                                                                         \
-      gauss_kernel<false, MWV><<<grid, kGThreads, 0, st>>>(op, p.m, p.N, p.s, p.seed, per, part); \
-    return hipGetLastError();                                                                    \
+  // NSK_GAUSS_FIX_CAP (0..kGFix) lowers the records kept per workgroup, so that tests can take
+  // the in-place pass that a full record list falls back to
+  int cap = kGFix;
+  if (const char* env = std::getenv("NSK_GAUSS_FIX_CAP")) cap = std::max(0, std::min(kGFix, std::atoi(env)));
+#define NSK_GAUSS_CASE(MWV)                                                                           \
+  if (g.mw == MWV) {                                                                                  \
+    if (f8)                                                                                           \
+      gauss_kernel<true, MWV><<<grid, kGThreads, 0, st>>>(op, p.m, p.N, p.s, p.seed, per, cap, part);  \
+    else                                                                                              \
+      gauss_kernel<false, MWV><<<grid, kGThreads, 0, st>>>(op, p.m, p.N, p.s, p.seed, per, cap, part); \
+    return hipGetLastError();                                                                         \
   }
   NSK_GAUSS_CASE(1)
   NSK_GAUSS_CASE(2)

@@ -185,8 +185,16 @@ def test_sketch_column_blocks_equal_concatenation(lib):
     assert colrel(strided, ref) < 1e-12
 
 
+@pytest.mark.parametrize("fix_cap", [None, "0", "1"])
 @pytest.mark.parametrize("fmt", ["bf16", "e4m3"])
-def test_gaussian_sketch_parity(lib, fmt):
+def test_gaussian_sketch_parity(lib, fmt, fix_cap, monkeypatch):
+    """fix_cap None: uncertified entries corrected after the K loop (the common path); "0" and
+    "1" (NSK_GAUSS_FIX_CAP): the record list overflows, so every workgroup with an uncertified
+    entry redoes its sums with the entries redrawn in place."""
+    if fix_cap is None:
+        monkeypatch.delenv("NSK_GAUSS_FIX_CAP", raising=False)
+    else:
+        monkeypatch.setenv("NSK_GAUSS_FIX_CAP", fix_cap)
     m, n, s = 6000, 45, 96
     rng = np.random.default_rng(9)
     a = rng.standard_normal((m, n)) * np.exp(rng.uniform(-2, 2, n))[None, :]
