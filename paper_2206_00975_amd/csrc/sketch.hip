@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
 //    each lane draws 2 of them, and a 4 x 4 exchange of 2-entry items over the quad (DPP quad
 //    permutations) leaves every lane the 8 entries of its own row;
 //  * MW x (column tiles) MFMAs.
-// Entries whose FP32 rounding is not certified (about one in 10^4) enter the MFMAs with their
+// Entries whose FP32 rounding is not certified (about one in 10^3 at BF16) enter the MFMAs with their
 // FP32 rounding and are recorded (K step, lane, entry mask) in LDS; after the K loop the
 // workgroup recomputes each in FP64, and where the FP64 rounding differs it adds the difference
 // times the entry's row of A to its partial sketch, the corrections taken in (row, column of
@@ -301,8 +301,12 @@ template <int D> __device__ inline unsigned quad_xor(unsigned x) {
   constexpr int ctrl = D == 1 ? 0xB1 : D == 2 ? 0x4E : 0x1B;  // [1,0,3,2], [2,3,0,1], [3,2,1,0]
   return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, 0xF, 0xF, false);
 }
+// (selects on named values: a nested conditional with non-trivial arms becomes a divergent
+// branch)
 __device__ inline unsigned sel4(int k, unsigned a, unsigned b, unsigned c, unsigned d) {
-  return k == 0 ? a : k == 1 ? b : k == 2 ? c : d;
+  const unsigned lo = (k & 1) ? b : a;
+  const unsigned hi = (k & 1) ? d : c;
+  return (k & 2) ? hi : lo;
 }
 
 // fix_cap (<= kGFix): records kept per workgroup before the in-place pass takes over.
@@ -451,8 +455,10 @@ __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m,
       }
     }
 #pragma unroll
+    // every row and column tile of the group, also those past s or N: their operands are zero
+    // (entries past s masked, columns past N loaded as zero) and their sums are not written,
+    // while a skip test per MFMA keeps ten lane masks live and spills them
     for (int u = 0; u < MW; ++u) {
-      if (mt0 + kGWaves * u >= mtiles) continue;
       // lane hq needs row hq of every quad lane's columns: R[p] = P_p[hq]
       const unsigned r1 = quad_xor<1>(sel4(hq ^ 1, P[u][0], P[u][1], P[u][2], P[u][3]));
       const unsigned r2 = quad_xor<2>(sel4(hq ^ 2, P[u][0], P[u][1], P[u][2], P[u][3]));
@@ -461,12 +467,10 @@ __global__ __launch_bounds__(kGThreads) void gauss_kernel(Operand op, int64_t m,
       unsigned R[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const int d = p ^ hq;  // R[p] came from lane p = hq ^ d
-        R[p] = d == 0 ? own : d == 1 ? r1 : d == 2 ? r2 : r3;
+        R[p] = sel4(p ^ hq, own, r1, r2, r3);  // R[p] came from lane p = hq ^ (p ^ hq)
       }
 #pragma unroll
       for (int c = 0; c < kGNT; ++c) {
-        if (nt0 + c >= ntiles) continue;
         if constexpr (FP8) {
           const long av = (long)((unsigned long)(R[0] | (R[1] << 16)) | ((unsigned long)(R[2] | (R[3] << 16)) << 32));
           const long bb = (long)((unsigned long)bop[c][0] | ((unsigned long)bop[c][1] << 32));

@@ -27,23 +27,26 @@ __device__ inline float bf16_round(float x) {
 }
 
 // Round to FP8 E4M3 (OCP, no infinities, max 448) to nearest even, saturating.
+// Both forms are evaluated and selected, here and in e4m3_bits: an early return becomes a
+// divergent branch.
 __device__ inline float e4m3_round(float x) {
   const float ax = fabsf(x);
-  if (ax < 0.015625f) return rintf(x * 512.0f) * (1.0f / 512.0f);
+  const float sub = rintf(x * 512.0f) * (1.0f / 512.0f);
   uint32_t b = __float_as_uint(x);
   b = (b + 0x7FFFFu + ((b >> 20) & 1u)) & 0xFFF00000u;
-  const float r = __uint_as_float(b);
-  return fminf(fmaxf(r, -448.0f), 448.0f);
+  const float r = fminf(fmaxf(__uint_as_float(b), -448.0f), 448.0f);
+  return ax < 0.015625f ? sub : r;
 }
 
 __device__ inline uint32_t e4m3_bits(float r) {  // r already rounded
   const uint32_t sign = (__float_as_uint(r) >> 24) & 0x80u;
   const float a = fabsf(r);
-  if (a < 0.015625f) return sign | (uint32_t)(a * 512.0f);
+  const uint32_t sub = sign | (uint32_t)(a * 512.0f);
   const uint32_t b = __float_as_uint(a);
-  const uint32_t e = ((b >> 23) & 0xFFu) - 127u + 7u;
+  const uint32_t e = ((b >> 23) & 0xFFu) - 127u + 7u;  // wraps below 2^-6, where sub is taken
   const uint32_t mant = (b >> 20) & 7u;
-  return sign | (e << 3) | mant;
+  const uint32_t normal = sign | (e << 3) | mant;
+  return a < 0.015625f ? sub : normal;
 }
 
 // Round an FP64 value to bfloat16 (8 significant bits) and to E4M3 (4 significant bits, quantum
@@ -82,7 +85,10 @@ __device__ inline GaussPair box_muller32(uint32_t a, uint32_t b) {
   float rc = __builtin_amdgcn_rcpf(dw);
   rc = fmaf(rc, fmaf(-dw, rc, 1.0f), rc);
   const float lg = __builtin_amdgcn_logf(low ? u : w);
-  const float l2 = low ? lg : (w == 1.0f ? -x * 1.4426950408889634f : lg * (x * rc));
+  const float tiny = -x * 1.4426950408889634f;
+  const float ident = lg * (x * rc);
+  const float upper = w == 1.0f ? tiny : ident;
+  const float l2 = low ? lg : upper;
   const float r = __builtin_sqrtf(-1.3862943611198906f * l2);
   const float v = (float)(int32_t)b * 0x1p-32f;
   return GaussPair{r * __builtin_amdgcn_cosf(v), r * __builtin_amdgcn_sinf(v), r};
