@@ -68,14 +68,29 @@ __host__ __device__ inline void sparse_column(uint64_t seed, uint64_t j, int s, 
 
 // Columns per workgroup of the sparse-sign sketch: the widest of 16, 8, 4 whose (s + 1) x cols
 // accumulator plus the double-buffered draw table (1024 rows x zeta) fits in 160 KB of LDS.
-__host__ __device__ inline int sparse_cols(int s, int zeta, int acc) {
+// The sparse-sign kernel's column tile and draw staging: cols columns of (s + 1) accumulator
+// rows in LDS beside the staged draws of `bufs` 1024-row chunks (two: the next chunk is staged
+// while the current one is accumulated; one: a barrier more per chunk).  16 columns whenever
+// they fit, single-buffered if need be: with 8 FP64 columns two target rows share each 16-lane
+// group of a 64-bit LDS atomic, and random rows collide on the same half of the banks about half
+// the time (39 % of the LDS cycles were bank conflicts at s = 1024), while 16 columns give each
+// group one row.  Otherwise the widest tile that fits double-buffered.
+struct SparseTile {
+  int cols, bufs;
+};
+__host__ __device__ inline size_t sparse_lds_need(int s, int zeta, int acc, int cols, int bufs) {
   const size_t zmax = zeta <= 8 ? 8 : 32;
-  const size_t table = 2 * 1024 * zmax * 2 + 2 * 1024 * 4;
   const size_t el = acc == NSK_F64 ? 8 : 4;
-  for (int c = 16; c > 4; c >>= 1)
-    if ((size_t)(s + 1) * c * el + table <= 160 * 1024) return c;
-  return 4;
+  return (size_t)(s + 1) * cols * el + (size_t)bufs * 1024 * (zmax * 2 + 4);
 }
+__host__ __device__ inline SparseTile sparse_tile(int s, int zeta, int acc) {
+  constexpr size_t kLds = 160 * 1024;
+  if (sparse_lds_need(s, zeta, acc, 16, 2) <= kLds) return SparseTile{16, 2};
+  if (sparse_lds_need(s, zeta, acc, 16, 1) <= kLds) return SparseTile{16, 1};
+  if (sparse_lds_need(s, zeta, acc, 8, 2) <= kLds) return SparseTile{8, 2};
+  return SparseTile{4, 2};
+}
+__host__ __device__ inline int sparse_cols(int s, int zeta, int acc) { return sparse_tile(s, zeta, acc).cols; }
 
 // Columns per SRHT tile for an N-column operand sketched to s rows (host plans and kernels
 // share it): 16-column tiles (512 threads, 256 registers a thread) hold up to 32 sampled rows

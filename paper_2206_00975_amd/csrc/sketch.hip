@@ -99,7 +99,8 @@ size_t sparse_table_bytes(int64_t m, int zeta) {
   return (size_t)m * (zmax / 8) * 16 + (size_t)m * 4;
 }
 
-template <typename TIn, typename TAcc, int ZMAX, int COLS>
+// SB: chunks of staged draws in LDS (sparse_tile: 2, or 1 where only that fits).
+template <typename TIn, typename TAcc, int ZMAX, int COLS, int SB>
 __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t m, int N, int s,
                                                             int groups, const uint4* __restrict__ rows_tab,
                                                             const uint32_t* __restrict__ neg_tab,
@@ -110,8 +111,8 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
   constexpr int ZW = ZMAX / 8;            // 16-byte table words per row
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TAcc* acc = reinterpret_cast<TAcc*>(smem_raw);                                  // (s + 1) x COLS
-  uint4* hrow = reinterpret_cast<uint4*>(acc + (size_t)(s + 1) * COLS);          // 2 x kSpThreads x ZW
-  uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + 2 * kSpThreads * ZW);       // 2 x kSpThreads
+  uint4* hrow = reinterpret_cast<uint4*>(acc + (size_t)(s + 1) * COLS);          // SB x kSpThreads x ZW
+  uint32_t* hneg = reinterpret_cast<uint32_t*>(hrow + SB * kSpThreads * ZW);      // SB x kSpThreads
 
   const int tiles = (N + COLS - 1) / COLS;
   const int64_t item = xcd_work_item(blockIdx.x, (int64_t)tiles * groups);
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
       hneg[buf * kSpThreads + t] = tn;
     };
     // chunk k + 1's values load into the register set chunk k does not use (two sets taken in
-    // turn); after the last full chunk the prefetch re-reads it and is discarded
+    // turn); after the last full chunk the prefetch re-reads it and is discarded.  With one
+    // staging buffer chunk k + 1's draws wait in registers until every thread has read chunk k's.
     auto step = [&](int64_t k, int buf, const TIn (&cur)[VPT], TIn (&nxt)[VPT]) {
       const int64_t kn = k + 1 < nfull ? k + 1 : k;
       uint4 tr[ZW];
@@ -189,8 +191,9 @@ __global__ __launch_bounds__(kSpThreads) void sparse_kernel(Operand op, int64_t 
       table(kn, tr, tn);
       __builtin_amdgcn_sched_barrier(0);  // table loads issue before the value loads
       fetch(kn, nxt);
-      accumulate(buf, cur);
-      stage(buf ^ 1, tr, tn);
+      accumulate(SB == 2 ? buf : 0, cur);
+      if constexpr (SB == 1) lds_barrier();
+      stage(SB == 2 ? buf ^ 1 : 0, tr, tn);
       lds_barrier();
     };
     TIn va[VPT], vb[VPT];
@@ -655,40 +658,43 @@ static hipError_t srht_dispatch(const Operand& op, const SketchPlan& p, hipStrea
   return srht_cols(p.N, p.s) == 8 ? srht_dispatch_cols<TIn, TAcc, 8>(op, p, st) : srht_dispatch_cols<TIn, TAcc, 16>(op, p, st);
 }
 
-static size_t sparse_lds_bytes_cols(int s, int zeta, int acc, int cols) {
-  const int zmax = zeta <= 8 ? 8 : 32;
-  return (size_t)(s + 1) * cols * (acc == NSK_F64 ? 8 : 4) + (size_t)2 * kSpThreads * zmax * 2 +
-         (size_t)2 * kSpThreads * 4;
-}
+static_assert(kSpThreads == 1024, "sparse_lds_need counts 1024 staged rows per chunk");
 
-size_t sparse_lds_bytes(int s, int zeta, int acc) { return sparse_lds_bytes_cols(s, zeta, acc, sparse_cols(s, zeta, acc)); }
+size_t sparse_lds_bytes(int s, int zeta, int acc) {
+  const SparseTile tl = sparse_tile(s, zeta, acc);
+  return sparse_lds_need(s, zeta, acc, tl.cols, tl.bufs);
+}
 
 template <typename TIn, typename TAcc>
 static hipError_t sparse_dispatch(const Operand& op, const SketchPlan& p, hipStream_t st) {
   const int acc = sizeof(TAcc) == 8 ? NSK_F64 : NSK_F32;
   // FP64 values take twice the registers: 16-column tiles (16 values a thread, two sets)
-  // would spill, so FP64 input uses at most 8 columns
-  int cols = sparse_cols(p.s, p.zeta, acc);
-  if (sizeof(TIn) == 8 && cols > 8) cols = 8;
+  // would spill, so FP64 input uses at most 8 columns (double-buffered: they fit wherever 16
+  // single-buffered columns do)
+  SparseTile tl = sparse_tile(p.s, p.zeta, acc);
+  if (sizeof(TIn) == 8 && tl.cols > 8) tl = SparseTile{8, 2};
+  const int cols = tl.cols;
   dim3 grid((unsigned)xcd_grid((int64_t)((p.N + cols - 1) / cols) * p.groups));
   const int zmax = p.zeta <= 8 ? 8 : 32;
-  const size_t lds = sparse_lds_bytes_cols(p.s, p.zeta, acc, cols);
+  const size_t lds = sparse_lds_need(p.s, p.zeta, acc, cols, tl.bufs);
   TAcc* part = static_cast<TAcc*>(p.partial);
   const uint4* rt = static_cast<const uint4*>(p.draws);
   const uint32_t* nt = reinterpret_cast<const uint32_t*>(rt + (size_t)p.m * (zmax / 8));
-#define NSK_SPARSE(Z, C)                                                                               \
+#define NSK_SPARSE(Z, C, SB)                                                                           \
   {                                                                                                    \
-    if (hipError_t e = set_lds_limit((const void*)sparse_kernel<TIn, TAcc, Z, C>, lds)) return e;      \
-    sparse_kernel<TIn, TAcc, Z, C><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.groups, rt, nt, part); \
+    if (hipError_t e = set_lds_limit((const void*)sparse_kernel<TIn, TAcc, Z, C, SB>, lds)) return e;  \
+    sparse_kernel<TIn, TAcc, Z, C, SB><<<grid, kSpThreads, lds, st>>>(op, p.m, p.N, p.s, p.groups, rt, nt, part); \
   }
   if (zmax == 8) {
-    if (cols == 16) NSK_SPARSE(8, 16)
-    else if (cols == 8) NSK_SPARSE(8, 8)
-    else NSK_SPARSE(8, 4)
+    if (cols == 16 && tl.bufs == 1) NSK_SPARSE(8, 16, 1)
+    else if (cols == 16) NSK_SPARSE(8, 16, 2)
+    else if (cols == 8) NSK_SPARSE(8, 8, 2)
+    else NSK_SPARSE(8, 4, 2)
   } else {
-    if (cols == 16) NSK_SPARSE(32, 16)
-    else if (cols == 8) NSK_SPARSE(32, 8)
-    else NSK_SPARSE(32, 4)
+    if (cols == 16 && tl.bufs == 1) NSK_SPARSE(32, 16, 1)
+    else if (cols == 16) NSK_SPARSE(32, 16, 2)
+    else if (cols == 8) NSK_SPARSE(32, 8, 2)
+    else NSK_SPARSE(32, 4, 2)
   }
 #undef NSK_SPARSE
   return hipGetLastError();

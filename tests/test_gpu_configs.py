@@ -122,7 +122,8 @@ def tls32():
 
 
 def test_sparse_sketch_fp32_s1024(lib):
-    """s = 1024 with FP32 input selects 8-column tiles of the sparse-sign kernel."""
+    """s = 1024 with FP32 input: 16-column tiles of the sparse-sign kernel with one chunk of
+    staged draws (with two they do not fit the LDS)."""
     a = np.random.default_rng(17).standard_normal((20_000, 257)).astype(np.float32)
     ref = operators.sketch(a.astype(np.float64), "sparse", S5, 77)
     SA = lib.sketch(t(a), "sparse", S5, 77).cpu().numpy()

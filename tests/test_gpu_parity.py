@@ -164,8 +164,11 @@ def test_srdct_one_workgroup_per_column_tile(lib):
 
 
 @pytest.mark.parametrize("m,n,s,zeta,dt", [(5003, 37, 150, 8, np.float32), (20_000, 201, 804, 8, np.float32),
-                                           (3000, 30, 90, 3, np.float64), (4100, 17, 64, 16, np.float32)])
+                                           (3000, 30, 90, 3, np.float64), (4100, 17, 64, 16, np.float32),
+                                           (12_001, 40, 1206, 8, np.float32), (9000, 33, 200, 24, np.float32)])
 def test_sparse_sketch_parity(lib, m, n, s, zeta, dt):
+    # tiles (sparse_tile): 16 columns with two chunks of staged draws, except s = 1206 (8 columns:
+    # 16 do not fit at FP64 accumulation) and zeta = 24 at s = 200 (16 columns, one chunk staged)
     a = np.random.default_rng(m + n).standard_normal((m, n)).astype(dt)
     SA = lib.sketch(t(a), "sparse", s, 77, zeta=zeta).cpu().numpy()
     ref = operators.sketch(a.astype(np.float64), "sparse", s, 77, zeta=zeta)
