@@ -112,6 +112,60 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Operand op, int64
   }
 }
 
+// FP32 rows stored contiguously (one row-major block, or adjacent blocks of one buffer), k = 1,
+// 4 <= N <= 256: lane l reads columns 4l .. 4l + 3 of a row with one 16-byte load (4-byte
+// alignment suffices for it), so a row is one wave load instead of one per 64 columns.  The
+// lane holding column N - 1 reads the window N - 4 .. N - 1 with zero weight on the columns
+// below its own (no load passes the row's end); lanes past N read that window with zero
+// weights.  Row sums as in residual_kernel.
+template <int RT>
+__global__ __launch_bounds__(kResThreads) void residual_rows_kernel(const float* __restrict__ A, int64_t ld,
+                                                                    int64_t m, int N, const double* __restrict__ v,
+                                                                    double* __restrict__ partial) {
+  __shared__ double wsum[kResThreads / 64];
+  constexpr int SH = 6 - ceil_log2(RT);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
+  const int my_row = lane >> SH;
+  const bool lead = (lane & ((1 << SH) - 1)) == 0;
+  const int c0 = 4 * lane;
+  const int cs = c0 + 4 <= N ? c0 : N - 4;  // window start
+  double w[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) w[j] = (cs + j >= c0 && cs + j < N) ? v[cs + j] : 0.0;
+  double local = 0;
+  for (int64_t r0 = ((int64_t)blockIdx.x * wpb + wave) * RT; r0 < m; r0 += (int64_t)gridDim.x * wpb * RT) {
+    const int nrow = m - r0 < RT ? (int)(m - r0) : RT;
+    float4 a[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) __builtin_memcpy(&a[r], A + (r0 + (r < nrow ? r : 0)) * ld + cs, sizeof(float4));
+    double d[16];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      d[r] = (double)a[r].x * w[0] + (double)a[r].y * w[1] + (double)a[r].z * w[2] + (double)a[r].w * w[3];
+    const double t = reduce_t<RT>(d, lane);
+    if (lead && my_row < nrow) local += t * t;
+  }
+  local = wave_sum64(local);
+  if (lane == 0) wsum[wave] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int q = 0; q < wpb; ++q) t += wsum[q];
+    partial[blockIdx.x] = t;
+  }
+}
+
+// The blocks of op are one row-major FP32 buffer: each starts where the previous one's columns
+// end, with the same row stride.
+static bool contiguous_rows(const Operand& op) {
+  if (op.dtype != NSK_F32) return false;
+  const float* p0 = static_cast<const float*>(op.ptr[0]);
+  for (int b = 1; b < op.nb; ++b)
+    if (op.ld[b] != op.ld[0] || static_cast<const float*>(op.ptr[b]) != p0 + op.col0[b]) return false;
+  return true;
+}
+
 // Fixed-order sum of the partials: lane l adds parts l, l + 64, ...; then a fixed butterfly.
 __global__ void residual_finish(const double* __restrict__ partial, int parts, double* out, nsk_info* info) {
   double t = 0;
@@ -130,7 +184,10 @@ hipError_t launch_residual(const Operand& op, int64_t m, const double* Vk, int k
 #define NSK_RES(T, KQ, RT, CI) \
   residual_kernel<T, KQ, RT, CI><<<parts, kResThreads, lds, st>>>(op, m, N, Vk, k, partial)
   const bool wide = N > 128;
-  if (op.dtype == NSK_F64) {
+  if (k == 1 && N >= 4 && N <= 256 && contiguous_rows(op)) {
+    residual_rows_kernel<16><<<parts, kResThreads, 0, st>>>(static_cast<const float*>(op.ptr[0]), op.ld[0], m, N, Vk,
+                                                            partial);
+  } else if (op.dtype == NSK_F64) {
     if (k == 1) { if (wide) NSK_RES(double, 1, 8, 4); else NSK_RES(double, 1, 16, 2); }
     else if (k == 2) { if (wide) NSK_RES(double, 2, 8, 4); else NSK_RES(double, 2, 16, 2); }
     else { if (wide) NSK_RES(double, 4, 4, 4); else NSK_RES(double, 4, 8, 2); }

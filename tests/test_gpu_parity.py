@@ -409,6 +409,22 @@ def test_coop_hand_over_forms_agree_bitwise(lib, m, N, k, monkeypatch):
     assert_vectors(vk_ref, v1.cpu().numpy(), vec_tol(sig, k))
 
 
+@pytest.mark.parametrize("m,N", [(40_003, 201), (5_001, 37), (777, 4), (9_999, 256), (3, 10)])
+def test_residual_contiguous_rows(lib, m, N):
+    # FP32 rows in one buffer, k = 1 (one 16-byte load per lane and row): as one block, as the
+    # TLS split [A | b] of the same buffer, and as blocks of separate buffers (the general path)
+    M = np.random.default_rng(m + N).standard_normal((m, N)).astype(np.float32)
+    v = np.random.default_rng(N).standard_normal((N, 1))
+    ref = np.linalg.norm(M.astype(np.float64) @ v)
+    Mt = t(M)
+    whole = float(lib.residual(Mt, t(v)))
+    split = float(lib.residual([Mt[:, :N - 1], Mt[:, N - 1:]], t(v)))
+    apart = float(lib.residual([Mt[:, :N - 1].contiguous(), Mt[:, N - 1:].contiguous()], t(v)))
+    for r in (whole, split, apart):
+        assert abs(r - ref) <= 1e-13 * ref, (r, ref)
+    assert whole == split
+
+
 def test_residual_entry_point(lib):
     a = np.random.default_rng(3).standard_normal((50_001, 33)).astype(np.float32)
     v = np.linalg.qr(np.random.default_rng(4).standard_normal((33, 3)))[0]
