@@ -76,6 +76,9 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst*
       srht_tile<TIn, TAcc, 16, kBatchCols, true>(I.op, I.m, I.N, I.s, I.seed, I.rows, tile.ctile, tile.g, I.groups, part, smem);
     else
       srht_tile<TIn, TAcc, 32, kBatchCols, false>(I.op, I.m, I.N, I.s, I.seed, I.rows, tile.ctile, tile.g, I.groups, part, smem);
+    // every wave's partial stores complete before the barrier: thread 0's release below waits
+    // only for its own wave's stores, and the workgroup barrier does not wait for stores
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) {
       const int prev = __hip_atomic_fetch_add(&counters[1 + tile.inst], 1, __ATOMIC_ACQ_REL,
