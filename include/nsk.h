@@ -132,7 +132,9 @@ size_t nsk_workspace_bytes(int64_t m, int64_t N, int64_t k, const nsk_desc* d);
  * Errors: NSK_EINVAL if m < N, s <= N, s > m, a block has cols < 1 or ld < cols, nblocks
  *   outside 1..4, zeta outside 1..min(s,32); NSK_EUNSUPPORTED for other dtype/kind pairs
  *   and for s > 2048 or m > 2^31 with NSK_SRHT or NSK_SRDCT, NSK_HRHT with acc = NSK_F32, m > 2^21 or
- *   s + m_p/1024 > 10240;
+ *   s + m_p/1024 > 10240, and NSK_SPARSE_SIGN when its (s + 1)-row accumulator of 4 columns and
+ *   two chunks of staged draws exceed 160 KB of LDS (zeta <= 8: s > 3839 with FP64 arithmetic,
+ *   s > 7679 with NSK_F32; zeta > 8: s > 767 and s > 1535);
  *   NSK_EWORKSPACE if
  *   ws_bytes < nsk_workspace_bytes(m, N, 1, d).
  */
